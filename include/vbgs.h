@@ -1,0 +1,170 @@
+/*
+ * vbgs.h -- C ABI of the MI355X (gfx950) library for the variational-Bayes
+ * Gaussian-splatting fit step: per-frame E-step, sufficient statistics,
+ * conjugate update and evidence lower bound.
+ *
+ * Model (Sec. 2.1.2, Fig. 2): each of K components has a Normal-Wishart
+ * posterior q(mu_k, Lambda_k) = NW(m_k, kappa_k, W_k, nu_k) and the mixture
+ * weights a Dirichlet(alpha). The paper's NIW(m, kappa, V, n) on (mu, Sigma)
+ * is the same distribution with W = V^{-1}, nu = n. The fit step of Alg. 1
+ * (responsibilities R, statistics Delta S = R^T S_u of Eq. (fused_contr),
+ * S <- S + Delta S, closed-form update) becomes:
+ *
+ *   vbgs_estep_stats : score every point against every component,
+ *                      rho_nk = E[ln pi_k] + 1/2 E[ln|Lambda_k|] - D/2 ln(2 pi)
+ *                               - 1/2 (D/kappa_k + nu_k (x-m_k)^T W_k (x-m_k)),
+ *                      normalise over k (LSE_n), and accumulate
+ *                      N_k = sum_n r_nk, S1_k = sum_n r_nk x_n,
+ *                      S2_k = sum_n r_nk x_n x_n^T; the N x K responsibility
+ *                      matrix is never stored.
+ *   vbgs_update      : posterior <- frame prior (+) statistics (conjugate,
+ *                      natural parameters); optionally commit it as the
+ *                      next frame's prior (replay-free continual update).
+ *   vbgs_elbo        : F(q) = sum_n LSE_n - KL(Dir(alpha)||Dir(alpha_p))
+ *                      - sum_k KL(NW_k || NW_p,k).
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are caller-owned (e.g. PyTorch tensors), contiguous, on
+ *    the device of `stream`. `stream` is a hipStream_t passed as void*
+ *    (NULL = the legacy default stream).
+ *  - Calls only enqueue work on `stream`: they never synchronise (except
+ *    vbgs_sync_status) and never allocate device memory. State and workspace
+ *    are caller-provided buffers sized by vbgs_query_sizes.
+ *  - Every call returns a vbgs_status; no C++ exception crosses the ABI.
+ *    Argument and shape errors are returned synchronously and leave the
+ *    context unchanged. Numeric faults found on the device (a W^{-1} that is
+ *    not positive definite, non-finite input points) set sticky device flags
+ *    that vbgs_sync_status reports.
+ *  - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef VBGS_H
+#define VBGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VBGS_ABI_VERSION 1
+#define VBGS_MAX_D 8
+
+typedef struct vbgs_ctx vbgs_ctx;
+
+typedef enum {
+  VBGS_OK = 0,
+  VBGS_ERR_ARG = -1,         /* null pointer, bad enum, out-of-range scalar */
+  VBGS_ERR_SHAPE = -2,       /* D, K or N outside the supported/declared range */
+  VBGS_ERR_HIP = -3,         /* a HIP runtime call failed (message in vbgs_last_error) */
+  VBGS_ERR_NOT_PD = -4,      /* sticky: some W^{-1} was not positive definite */
+  VBGS_ERR_NONFINITE = -5,   /* sticky: non-finite input coordinates */
+  VBGS_ERR_STATE = -6,       /* call order: e.g. vbgs_elbo(X=NULL) after an update */
+  VBGS_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+} vbgs_status;
+
+/* Precision of the score GEMM (the dot product of quadratic point features
+ * [1, x, upper(x x^T)] with per-component coefficient rows on MFMA).
+ * VBGS_FP64 selects the plain direct-form FP64 path (no GEMM). */
+typedef enum {
+  VBGS_FP64 = 0,    /* direct form (x-m)^T W (x-m) in FP64 on the vector ALUs */
+  VBGS_FP32 = 1,    /* v_mfma_f32_16x16x4_f32, FP32 accumulation */
+  VBGS_BF16 = 2,    /* v_mfma_f32_16x16x32_bf16, FP32 accumulation */
+  VBGS_BF16X3 = 3   /* split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+} vbgs_prec;
+
+typedef struct {
+  int32_t abi_version;     /* must be VBGS_ABI_VERSION */
+  int32_t D;               /* feature dimension, 1..8 (MFMA precisions: 1..6) */
+  int64_t K;               /* number of components, >= 1 */
+  int64_t n_max;           /* largest N any call will pass (workspace sizing) */
+  double kappa0, nu0, alpha0;  /* shared prior scalars: kappa0 > 0, nu0 > D-1, alpha0 > 0 */
+  int32_t score_prec;      /* vbgs_prec */
+  int32_t exact;           /* MFMA precisions only. 1: the GEMM is a bounded screen and every
+                              pair that can carry mass is rescored exactly in FP64 (results
+                              match the FP64 path to rounding); 0: the GEMM scores are used
+                              as they are (the error is that of the precision) */
+  double screen_margin;    /* nats; pairs whose upper bound is more than this below the
+                              point's running maximum (pass 1) or its LSE (pass 2) are
+                              skipped. <= 0 selects ln(K) + ln(1e12). */
+  int32_t n_split;         /* pass-2 point splits; 0 = automatic */
+  int32_t reserved0;
+  int64_t reserved[6];     /* must be zero */
+} vbgs_params;
+
+/* Fill *p with defaults for (D, K, n_max): kappa0 = 1, nu0 = D + 2, alpha0 = 1,
+ * score_prec = VBGS_BF16X3, exact = 1, screen_margin = 0 (automatic). */
+vbgs_status vbgs_default_params(vbgs_params* p, int32_t D, int64_t K, int64_t n_max);
+
+/* Bytes of caller-owned device memory: `state` persists across calls and frames
+ * (frame prior + posterior: a checkpoint of it is a checkpoint of the model);
+ * `workspace` is scratch reused by every call (its contents do not need to
+ * survive between frames). Both must be 256-byte aligned. */
+vbgs_status vbgs_query_sizes(const vbgs_params* p, size_t* state_bytes, size_t* workspace_bytes);
+
+/* Create a context and initialise the state: for every component k the frame
+ * prior and the posterior are set to (alpha0, kappa0, m0[k], W0, nu0).
+ *   m0      : device, K x D row-major FP64, the prior means.
+ *   W0      : HOST, D x D row-major FP64, symmetric positive definite Wishart
+ *             scale (the same for every component). Not PD -> VBGS_ERR_NOT_PD.
+ *   state, workspace : device buffers of the sizes from vbgs_query_sizes.
+ * The state is written by kernels on `stream`; *out is set only on success. */
+vbgs_status vbgs_init(vbgs_ctx** out, const vbgs_params* p, const double* m0, const double* W0,
+                      void* state, void* workspace, void* stream);
+
+/* Attach a context to an existing state buffer (resume from a checkpoint):
+ * no kernel runs; the state must come from a context with the same params. */
+vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void* workspace);
+
+/* E-step + sufficient statistics of one frame at the current posterior.
+ *   X         : device, N x D row-major FP32 points (N <= n_max; N = 0 allowed).
+ *   lse_out   : device, N FP64 or NULL. LSE_n in nats (the per-point ELBO term).
+ *   stats_out : device, K x F FP64 or NULL, F = 1 + D + D(D+1)/2, per component
+ *               [N_k, S1_k (D), S2_k upper triangle row-major (i <= j)], raw
+ *               coordinates. The statistics are also kept in the workspace for
+ *               vbgs_update. Reductions are deterministic (fixed order). */
+vbgs_status vbgs_estep_stats(vbgs_ctx* ctx, const float* X, int64_t N, double* lse_out,
+                             double* stats_out, void* stream);
+
+/* Conjugate update: posterior <- frame prior (+) the last statistics
+ * (alpha += N_k, kappa += N_k, nu += N_k, kappa m += S1_k,
+ * W^{-1} + kappa m m^T += S2_k). commit = 1 then copies the posterior into the
+ * frame prior (end of frame). Needs a preceding vbgs_estep_stats. */
+vbgs_status vbgs_update(vbgs_ctx* ctx, int32_t commit, void* stream);
+
+/* Evidence lower bound F(q) at the current posterior against the frame prior,
+ * written to elbo_dev (device, 1 FP64). X = NULL reuses sum_n LSE_n of the last
+ * vbgs_estep_stats (VBGS_ERR_STATE if the posterior changed since); otherwise
+ * the LSE pass runs on X (N points). */
+vbgs_status vbgs_elbo(vbgs_ctx* ctx, const float* X, int64_t N, double* elbo_dev, void* stream);
+
+/* Copy the posterior (which = 0) or the frame prior (which = 1) out of / into
+ * the state. Device buffers: alpha, kappa, nu: K; m: K x D; Winv: K x D x D
+ * (full, symmetric). Setting does not check positive definiteness (the next
+ * E-step flags it). */
+vbgs_status vbgs_get_params(vbgs_ctx* ctx, int32_t which, double* alpha, double* kappa, double* m,
+                            double* Winv, double* nu, void* stream);
+vbgs_status vbgs_set_params(vbgs_ctx* ctx, int32_t which, const double* alpha, const double* kappa,
+                            const double* m, const double* Winv, const double* nu, void* stream);
+
+/* Synchronise `stream` and return the sticky device flags (VBGS_ERR_NOT_PD,
+ * VBGS_ERR_NONFINITE) or VBGS_OK. Clears nothing; vbgs_clear_flags does. */
+vbgs_status vbgs_sync_status(vbgs_ctx* ctx, void* stream);
+vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
+
+/* Synchronise `stream` and read host-side counters of the last E-step:
+ * out[0] = pairs rescored exactly in pass 1, out[1] = in pass 2,
+ * out[2] = number of points, out[3] = number of components. */
+vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[4], void* stream);
+
+/* Last error message of this context ("" if none). Never NULL. */
+const char* vbgs_last_error(const vbgs_ctx* ctx);
+
+/* Release the host-side context (no device memory is owned). NULL is a no-op. */
+void vbgs_destroy(vbgs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VBGS_H */

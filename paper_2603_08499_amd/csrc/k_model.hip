@@ -1,0 +1,503 @@
+// Per-frame preparation and per-component FP64 kernels:
+//   frame moments and quadratic point features (the per-point statistics S_u of Alg. 1),
+//   posterior -> expectations -> score coefficients (+ KL terms for the ELBO),
+//   conjugate update (Alg. 1: S <- S + Delta S, update_from_statistics), ELBO reduction.
+#include "vbgs_internal.h"
+
+namespace vbgs {
+
+// ---------------------------------------------------------------------------
+// state records: [alpha, kappa, nu, m (D), W^{-1} upper-packed row-major (i <= j)]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tri_up(int i, int j, int D) {  // index of (i, j), i <= j
+  return i * D - i * (i - 1) / 2 + (j - i);
+}
+
+__global__ void k_init_state(StateHeader* hdr, double* prior, double* post, const double* __restrict__ m0, Init0 in,
+                             int D, int64_t K) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) {
+    hdr->magic = STATE_MAGIC;
+    hdr->abi = VBGS_ABI_VERSION;
+    hdr->D = D;
+    hdr->K = K;
+  }
+  if (k >= K) return;
+  double r[REC];
+  for (int i = 0; i < REC; ++i) r[i] = 0.0;
+  r[0] = in.alpha0;
+  r[1] = in.kappa0;
+  r[2] = in.nu0;
+  for (int i = 0; i < D; ++i) r[3 + i] = m0[k * D + i];
+  for (int i = 0; i < D; ++i)
+    for (int j = i; j < D; ++j) r[3 + D + tri_up(i, j, D)] = in.W0inv[i * D + j];
+  for (int i = 0; i < REC; ++i) {
+    prior[k * REC + i] = r[i];
+    post[k * REC + i] = r[i];
+  }
+}
+
+hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& init, hipStream_t s) {
+  const int64_t K = d.K;
+  hipLaunchKernelGGL(k_init_state, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<StateHeader*>(d.state), d.prior(), d.post(), m0, init, d.D, K);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// frame moments (deterministic two-level reduction) and features
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_moments_partial(const float* __restrict__ X, int64_t N, int D,
+                                                         double* __restrict__ part) {
+  __shared__ double sh[256][2 * MAXD];
+  const int t = threadIdx.x;
+  const int64_t per = (N + MOM_BLOCKS - 1) / MOM_BLOCKS;
+  const int64_t a = (int64_t)blockIdx.x * per, b = min(N, a + per);
+  double s1[MAXD], s2[MAXD];
+  for (int i = 0; i < MAXD; ++i) s1[i] = s2[i] = 0.0;
+  for (int64_t n = a + t; n < b; n += 256)
+    for (int i = 0; i < D; ++i) {
+      const double v = (double)X[n * D + i];
+      if (isfinite(v)) {
+        s1[i] += v;
+        s2[i] += v * v;
+      }
+    }
+  for (int i = 0; i < MAXD; ++i) {
+    sh[t][i] = s1[i];
+    sh[t][MAXD + i] = s2[i];
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int i = 0; i < 2 * MAXD; ++i) sh[t][i] += sh[t + w][i];
+    __syncthreads();
+  }
+  if (t < 2 * MAXD) part[blockIdx.x * 2 * MAXD + t] = sh[0][t];
+}
+
+__global__ void k_moments_final(const double* __restrict__ part, int64_t N, int D, FrameInfo* fr) {
+  const int i = threadIdx.x;
+  if (i >= MAXD) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = 0; b < MOM_BLOCKS; ++b) {
+    s1 += part[b * 2 * MAXD + i];
+    s2 += part[b * 2 * MAXD + MAXD + i];
+  }
+  float mu = 0.0f;
+  double sc = 1.0;
+  if (i < D && N > 0) {
+    const double mean = s1 / (double)N;
+    const double var = fmax(s2 / (double)N - mean * mean, 0.0);
+    mu = (float)mean;
+    const double sd = sqrt(var);
+    if (sd > 0.0 && isfinite(sd)) sc = exp2(rint(log2(sd)));  // power of two: scaling is exact
+  }
+  fr->mu[i] = mu;
+  fr->s[i] = sc;
+  fr->inv_s[i] = (float)(1.0 / sc);
+  if (i == 0) {
+    fr->refined1 = 0;
+    fr->refined2 = 0;
+  }
+}
+
+// phi(x') = [1, x'_0..x'_{D-1}, x'_i x'_j (i <= j, row-major)], zero padded to 32 slots,
+// with x' = (x - mu) / s computed in FP32. Stored as FP32 and as a bfloat16 hi/lo split,
+// plus the Euclidean norm (rounded up) used by the screening bound.
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ X, int64_t N, int D,
+                                                  const FrameInfo* __restrict__ fr, float* __restrict__ phi32,
+                                                  uint16_t* __restrict__ phih, uint16_t* __restrict__ phil,
+                                                  float* __restrict__ nphi, int* flags) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float xs[MAXD];
+  bool fin = true;
+  for (int i = 0; i < MAXD; ++i) {
+    if (i < D) {
+      const float v = X[n * D + i];
+      fin = fin && isfinite(v);
+      xs[i] = (v - fr->mu[i]) * fr->inv_s[i];
+    }
+  }
+  if (!fin) {
+    atomicOr(flags, FLAG_NONFINITE);
+    for (int i = 0; i < D; ++i) xs[i] = 0.0f;
+  }
+  float f[FP];
+  for (int i = 0; i < FP; ++i) f[i] = 0.0f;
+  f[0] = 1.0f;
+  int o = 1 + D;
+  for (int i = 0; i < D; ++i) {
+    f[1 + i] = xs[i];
+    for (int j = i; j < D; ++j) f[o++] = xs[i] * xs[j];
+  }
+  double nn = 0.0;
+  for (int i = 0; i < FP; ++i) nn += (double)f[i] * (double)f[i];
+  f32x4* p32 = reinterpret_cast<f32x4*>(phi32 + n * FP);
+  for (int q = 0; q < FP / 4; ++q) p32[q] = f32x4{f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]};
+  uint32_t* ph = reinterpret_cast<uint32_t*>(phih + n * FP);
+  uint32_t* pl = reinterpret_cast<uint32_t*>(phil + n * FP);
+  for (int q = 0; q < FP / 2; ++q) {
+    const uint16_t h0 = f2bf(f[2 * q]), h1 = f2bf(f[2 * q + 1]);
+    const uint16_t l0 = f2bf(f[2 * q] - bf2f(h0)), l1 = f2bf(f[2 * q + 1] - bf2f(h1));
+    ph[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    pl[q] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+  }
+  nphi[n] = (float)(sqrt(nn) * (1.0 + 1e-6));
+}
+
+// sum of alpha over the posterior and the frame prior (fixed-order tree)
+__global__ __launch_bounds__(1024) void k_alpha_sums(const double* __restrict__ prior,
+                                                     const double* __restrict__ post, int64_t K,
+                                                     FrameInfo* fr) {
+  __shared__ double sq[1024], sp[1024];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t k = t; k < K; k += 1024) {
+    a += post[k * REC];
+    b += prior[k * REC];
+  }
+  sq[t] = a;
+  sp[t] = b;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      sq[t] += sq[t + w];
+      sp[t] += sp[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    fr->sum_alpha_q = sq[0];
+    fr->sum_alpha_p = sp[0];
+  }
+}
+
+hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s) {
+  const Layout& L = *d.L;
+  double* part = d.at<double>(L.mom_part);
+  hipLaunchKernelGGL(k_moments_partial, dim3(MOM_BLOCKS), dim3(256), 0, s, X, N, d.D, part);
+  hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64), 0, s, part, N, d.D, d.frame());
+  if (N > 0 && d.D <= 6)  // quadratic features fill 1 + D + D(D+1)/2 <= 32 slots only for D <= 6
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, N, d.D, d.frame(),
+                       d.at<float>(L.phi32), d.at<uint16_t>(L.phih), d.at<uint16_t>(L.phil), d.at<float>(L.nphi),
+                       &d.frame()->flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// posterior -> expectations -> coefficient rows (FP64, one thread per component)
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ bool cholesky(double A[D][D]) {  // in place, lower factor; false if not PD
+  for (int j = 0; j < D; ++j) {
+    double s = A[j][j];
+    for (int t = 0; t < j; ++t) s -= A[j][t] * A[j][t];
+    if (!(s > 0.0) || !isfinite(s)) return false;
+    const double l = sqrt(s);
+    A[j][j] = l;
+    for (int i = j + 1; i < D; ++i) {
+      double v = A[i][j];
+      for (int t = 0; t < j; ++t) v -= A[i][t] * A[j][t];
+      A[i][j] = v / l;
+    }
+  }
+  return true;
+}
+
+template <int D>
+__device__ void load_winv(const double* r, double A[D][D]) {
+  for (int i = 0; i < D; ++i)
+    for (int j = i; j < D; ++j) A[i][j] = A[j][i] = r[3 + D + tri_up(i, j, D)];
+}
+
+struct CoefOut {
+  double* direct;
+  float* c32;
+  uint16_t* ch;
+  uint16_t* cl;
+  float* nc;
+  double* kl;
+};
+
+__device__ void write_dead_row(const CoefOut& o, int64_t k, int dts, bool expanded) {
+  for (int i = 0; i < (expanded ? FP : 0); ++i) {
+    const float v = i == 0 ? DEAD_C0 : 0.0f;
+    o.c32[k * FP + i] = v;
+    const uint16_t h = f2bf(v);
+    o.ch[k * FP + i] = h;
+    o.cl[k * FP + i] = f2bf(v - bf2f(h));
+  }
+  if (expanded) o.nc[k] = 0.0f;
+  for (int i = 0; i < dts; ++i) o.direct[k * dts + i] = i == 0 ? -1.0e300 : 0.0;
+}
+
+template <int D>
+__global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior, const double* __restrict__ post,
+                                                int64_t K, int64_t Kpad, const FrameInfo* __restrict__ fr,
+                                                CoefOut o, int* flags) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Kpad) return;
+  constexpr int dts = D <= 6 ? 32 : 48;
+  if (k >= K) {
+    write_dead_row(o, k, dts, D <= 6);
+    return;
+  }
+  const double* q = post + k * REC;
+  const double* p = prior + k * REC;
+  const double alpha = q[0], kappa = q[1], nu = q[2];
+  double m[D];
+  for (int i = 0; i < D; ++i) m[i] = q[3 + i];
+  double L[D][D];
+  load_winv<D>(q, L);
+  if (!cholesky<D>(L)) {
+    atomicOr(flags, FLAG_NOT_PD);
+    write_dead_row(o, k, dts, D <= 6);
+    o.kl[k] = 0.0;
+    return;
+  }
+  double lndetW = 0.0;
+  for (int i = 0; i < D; ++i) lndetW -= 2.0 * log(L[i][i]);
+  // Linv = L^{-1} (lower triangular)
+  double Li[D][D];
+  for (int j = 0; j < D; ++j) {
+    for (int i = 0; i < D; ++i) Li[i][j] = 0.0;
+    Li[j][j] = 1.0 / L[j][j];
+    for (int i = j + 1; i < D; ++i) {
+      double v = 0.0;
+      for (int t = j; t < i; ++t) v += L[i][t] * Li[t][j];
+      Li[i][j] = -v / L[i][i];
+    }
+  }
+  // W = Linv^T Linv
+  double W[D][D];
+  for (int a = 0; a < D; ++a)
+    for (int b = a; b < D; ++b) {
+      double v = 0.0;
+      for (int t = b; t < D; ++t) v += Li[t][a] * Li[t][b];
+      W[a][b] = W[b][a] = v;
+    }
+  double ElnLam = D * LN2 + lndetW;
+  for (int i = 1; i <= D; ++i) ElnLam += vb_digamma(0.5 * (nu + 1.0 - i));
+  const double psi_sum = vb_digamma(fr->sum_alpha_q);
+  const double psi_a = vb_digamma(alpha);
+  const double Elnpi = psi_a - psi_sum;
+  const double g = Elnpi + 0.5 * ElnLam - 0.5 * D * LN2PI - 0.5 * D / kappa;
+
+  // direct-form row (raw coordinates, log2 units)
+  double* T = o.direct + k * dts;
+  T[0] = LOG2E * g;
+  for (int i = 0; i < D; ++i) T[1 + i] = m[i];
+  const double us = sqrt(0.5 * nu * LOG2E);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j <= i; ++j) T[1 + D + i * (i + 1) / 2 + j] = us * Li[i][j];
+  for (int i = 1 + D + D * (D + 1) / 2; i < dts; ++i) T[i] = 0.0;
+
+  // expanded coefficients in centred/scaled coordinates x' = (x - mu) / s (MFMA paths: D <= 6)
+  if constexpr (D <= 6) {
+  double ms[D], Wm[D];
+  for (int i = 0; i < D; ++i) ms[i] = (m[i] - (double)fr->mu[i]) / fr->s[i];
+  double mWm = 0.0;
+  for (int a = 0; a < D; ++a) {
+    double v = 0.0;
+    for (int b = 0; b < D; ++b) v += W[a][b] * fr->s[a] * fr->s[b] * ms[b];
+    Wm[a] = v;
+    mWm += ms[a] * v;
+  }
+  double c[FP];
+  for (int i = 0; i < FP; ++i) c[i] = 0.0;
+  c[0] = LOG2E * (g - 0.5 * nu * mWm);
+  for (int a = 0; a < D; ++a) c[1 + a] = LOG2E * nu * Wm[a];
+  int oo = 1 + D;
+  for (int a = 0; a < D; ++a)
+    for (int b = a; b < D; ++b) {
+      const double wab = W[a][b] * fr->s[a] * fr->s[b];
+      c[oo++] = (a == b ? -0.5 : -1.0) * LOG2E * nu * wab;
+    }
+  double nn = 0.0;
+  for (int i = 0; i < FP; ++i) {
+    const float v = (float)c[i];
+    o.c32[k * FP + i] = v;
+    const uint16_t h = f2bf(v);
+    o.ch[k * FP + i] = h;
+    o.cl[k * FP + i] = f2bf(v - bf2f(h));
+    nn += c[i] * c[i];
+  }
+  o.nc[k] = (float)(sqrt(nn) * (1.0 + 1e-6));
+  }
+
+  // KL(NW(q_k) || NW(p_k)) + the per-component part of KL(Dir(alpha) || Dir(alpha_p))
+  const double ap = p[0], kp = p[1], np = p[2];
+  double Lp[D][D];
+  load_winv<D>(p, Lp);
+  double Ap[D][D];
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) Ap[a][b] = Lp[a][b];
+  if (!cholesky<D>(Lp)) {
+    atomicOr(flags, FLAG_NOT_PD);
+    o.kl[k] = 0.0;
+    return;
+  }
+  double lndetWp = 0.0;
+  for (int i = 0; i < D; ++i) lndetWp -= 2.0 * log(Lp[i][i]);
+  double quad = 0.0, tr = 0.0;
+  double dm[D];
+  for (int i = 0; i < D; ++i) dm[i] = m[i] - p[3 + i];
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      quad += dm[a] * W[a][b] * dm[b];
+      tr += Ap[a][b] * W[b][a];
+    }
+  const double lnB_q = -0.5 * nu * lndetW - 0.5 * nu * D * LN2 - vb_mvlgamma(0.5 * nu, D);
+  const double lnB_p = -0.5 * np * lndetWp - 0.5 * np * D * LN2 - vb_mvlgamma(0.5 * np, D);
+  const double klnw = 0.5 * (kp * nu * quad + D * kp / kappa - D + D * log(kappa / kp)) + lnB_q - lnB_p +
+                      0.5 * (nu - np) * ElnLam - 0.5 * nu * D + 0.5 * nu * tr;
+  const double kd = -lgamma(alpha) + lgamma(ap) + (alpha - ap) * (psi_a - psi_sum);
+  o.kl[k] = klnw + kd;
+}
+
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s) {
+  const Layout& L = *d.L;
+  hipLaunchKernelGGL(k_alpha_sums, dim3(1), dim3(1024), 0, s, d.prior(), d.post(), d.K, d.frame());
+  CoefOut o{d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch), d.at<uint16_t>(L.cl),
+            d.at<float>(L.nc), d.at<double>(L.kl)};
+  const dim3 grid((unsigned)((L.Kpad + 127) / 128)), blk(128);
+  int* fl = &d.frame()->flags;
+  switch (d.D) {
+#define VB_CASE(DD) \
+  case DD:          \
+    hipLaunchKernelGGL(k_coeffs<DD>, grid, blk, 0, s, d.prior(), d.post(), d.K, L.Kpad, d.frame(), o, fl); break;
+    VB_CASE(1) VB_CASE(2) VB_CASE(3) VB_CASE(4) VB_CASE(5) VB_CASE(6) VB_CASE(7) VB_CASE(8)
+#undef VB_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// conjugate update through natural parameters (FP64, one thread per component)
+// ---------------------------------------------------------------------------
+__global__ void k_update(double* prior, double* post, const double* __restrict__ st, int D, int64_t K,
+                         int commit) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int F = nfeat(D);
+  const double* p = prior + k * REC;
+  const double* S = st + k * F;
+  const double Nk = S[0];
+  double r[REC];
+  for (int i = 0; i < REC; ++i) r[i] = 0.0;
+  const double kp = p[1];
+  const double kappa = kp + Nk;
+  r[0] = p[0] + Nk;
+  r[1] = kappa;
+  r[2] = p[2] + Nk;
+  double m[MAXD], mp[MAXD];
+  for (int i = 0; i < D; ++i) {
+    mp[i] = p[3 + i];
+    m[i] = (kp * mp[i] + S[1 + i]) / kappa;
+    r[3 + i] = m[i];
+  }
+  // W^{-1} + kappa m m^T is additive: T3 = T3_prior + S2
+  int o = 1 + D;
+  for (int i = 0; i < D; ++i)
+    for (int j = i; j < D; ++j) {
+      const int t = tri_up(i, j, D);
+      r[3 + D + t] = p[3 + D + t] + S[o + t] + kp * mp[i] * mp[j] - kappa * m[i] * m[j];
+    }
+  for (int i = 0; i < REC; ++i) post[k * REC + i] = r[i];
+  if (commit)
+    for (int i = 0; i < REC; ++i) prior[k * REC + i] = r[i];
+}
+
+hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.prior(), d.post(),
+                     d.at<double>(d.L->stats), d.D, d.K, commit);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ELBO: F = ln2 * sum LSE2 - [lnGamma(sum alpha) - lnGamma(sum alpha_p)] - sum_k kl_k
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_elbo(const double* __restrict__ lse_part, int64_t np,
+                                               const double* __restrict__ kl, int64_t K,
+                                               const FrameInfo* __restrict__ fr, double* out) {
+  __shared__ double a[1024], b[1024];
+  const int t = threadIdx.x;
+  double s = 0.0, u = 0.0;
+  for (int64_t i = t; i < np; i += 1024) s += lse_part[i];
+  for (int64_t i = t; i < K; i += 1024) u += kl[i];
+  a[t] = s;
+  b[t] = u;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      a[t] += a[t + w];
+      b[t] += b[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double kdir0 = lgamma(fr->sum_alpha_q) - lgamma(fr->sum_alpha_p);
+    out[0] = LN2 * a[0] - kdir0 - b[0];
+  }
+}
+
+hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_elbo, dim3(1), dim3(1024), 0, s, d.at<double>(d.L->lse_part), n_lse_part,
+                     d.at<double>(d.L->kl), d.K, d.frame(), out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// parameter get / set (full symmetric W^{-1} outside, upper-packed inside)
+// ---------------------------------------------------------------------------
+__global__ void k_get_set(double* rec, int set, int D, int64_t K, double* alpha, double* kappa, double* m,
+                          double* Winv, double* nu) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double* r = rec + k * REC;
+  if (set) {
+    r[0] = alpha[k];
+    r[1] = kappa[k];
+    r[2] = nu[k];
+    for (int i = 0; i < D; ++i) r[3 + i] = m[k * D + i];
+    for (int i = 0; i < D; ++i)
+      for (int j = i; j < D; ++j)
+        r[3 + D + tri_up(i, j, D)] = 0.5 * (Winv[(k * D + i) * D + j] + Winv[(k * D + j) * D + i]);
+  } else {
+    alpha[k] = r[0];
+    kappa[k] = r[1];
+    nu[k] = r[2];
+    for (int i = 0; i < D; ++i) m[k * D + i] = r[3 + i];
+    for (int i = 0; i < D; ++i)
+      for (int j = i; j < D; ++j) {
+        const double v = r[3 + D + tri_up(i, j, D)];
+        Winv[(k * D + i) * D + j] = v;
+        Winv[(k * D + j) * D + i] = v;
+      }
+  }
+}
+
+hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, double* kappa, double* m,
+                          double* Winv, double* nu, hipStream_t s) {
+  double* rec = which == 0 ? d.post() : d.prior();
+  hipLaunchKernelGGL(k_get_set, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, rec, set, d.D, d.K, alpha,
+                     kappa, m, Winv, nu);
+  return hipGetLastError();
+}
+
+__global__ void k_clear_flags(FrameInfo* fr) {
+  fr->flags = 0;
+  fr->refined1 = 0;
+  fr->refined2 = 0;
+}
+
+hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(1), 0, s, d.frame());
+  return hipGetLastError();
+}
+
+}  // namespace vbgs

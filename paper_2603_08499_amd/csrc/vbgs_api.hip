@@ -1,0 +1,372 @@
+// C ABI of libvbgs: parameter validation, workspace layout, launch sequencing.
+// Every entry point enqueues on the caller's stream; nothing here allocates device memory.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "vbgs_internal.h"
+
+using namespace vbgs;
+
+struct vbgs_ctx {
+  vbgs_params p;
+  Layout L;
+  void* state;
+  void* ws;
+  int64_t last_N;
+  uint64_t post_version;
+  uint64_t lse_version;
+  bool have_stats;
+  int nsplit;
+  float T2;
+  std::string err;
+  DevPtrs dev() const { return DevPtrs{(char*)ws, (double*)state, &L, p.D, p.K}; }
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int auto_split_mfma(int64_t Kpad) {
+  const int64_t tiles = Kpad / CT;
+  int64_t s = (1024 + tiles - 1) / tiles;
+  return (int)(s < 1 ? 1 : (s > 32 ? 32 : s));
+}
+int auto_split_direct(int64_t K) {
+  const int64_t tiles = (K + 255) / 256;
+  int64_t s = (2048 + tiles - 1) / tiles;
+  return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
+}
+
+vbgs_status check_params(const vbgs_params* p, std::string* why) {
+  if (!p) {
+    if (why) *why = "params is NULL";
+    return VBGS_ERR_ARG;
+  }
+  if (p->abi_version != VBGS_ABI_VERSION) {
+    if (why) *why = "abi_version mismatch";
+    return VBGS_ERR_ARG;
+  }
+  if (p->D < 1 || p->D > VBGS_MAX_D) {
+    if (why) *why = "D must be in 1..8";
+    return VBGS_ERR_SHAPE;
+  }
+  if (p->K < 1 || p->K > (int64_t)1 << 30) {
+    if (why) *why = "K must be in 1..2^30";
+    return VBGS_ERR_SHAPE;
+  }
+  if (p->n_max < 0 || p->n_max > (int64_t)1 << 31) {
+    if (why) *why = "n_max must be in 0..2^31";
+    return VBGS_ERR_SHAPE;
+  }
+  if (!(p->kappa0 > 0) || !(p->alpha0 > 0) || !(p->nu0 > p->D - 1) || !isfinite(p->kappa0) ||
+      !isfinite(p->alpha0) || !isfinite(p->nu0)) {
+    if (why) *why = "prior scalars need kappa0 > 0, alpha0 > 0, nu0 > D - 1";
+    return VBGS_ERR_ARG;
+  }
+  if (p->score_prec < VBGS_FP64 || p->score_prec > VBGS_BF16X3) {
+    if (why) *why = "unknown score_prec";
+    return VBGS_ERR_ARG;
+  }
+  if (p->score_prec != VBGS_FP64 && p->D > 6) {
+    if (why) *why = "MFMA precisions support D <= 6 (32 feature slots); use VBGS_FP64";
+    return VBGS_ERR_UNSUPPORTED;
+  }
+  if (p->exact != 0 && p->exact != 1) {
+    if (why) *why = "exact must be 0 or 1";
+    return VBGS_ERR_ARG;
+  }
+  if (!isfinite(p->screen_margin)) {
+    if (why) *why = "screen_margin must be finite";
+    return VBGS_ERR_ARG;
+  }
+  if (p->n_split < 0 || p->n_split > 64) {
+    if (why) *why = "n_split must be in 0..64";
+    return VBGS_ERR_ARG;
+  }
+  for (int i = 0; i < 6; ++i)
+    if (p->reserved[i] != 0 || p->reserved0 != 0) {
+      if (why) *why = "reserved fields must be zero";
+      return VBGS_ERR_ARG;
+    }
+  return VBGS_OK;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+vbgs_status fail(vbgs_ctx* c, vbgs_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+vbgs_status hipfail(vbgs_ctx* c, hipError_t e, const char* where) {
+  if (e == hipSuccess) return VBGS_OK;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+  return fail(c, VBGS_ERR_HIP, buf);
+}
+
+bool aligned(const void* p) { return ((uintptr_t)p % ALIGN) == 0; }
+
+}  // namespace
+
+namespace vbgs {
+Layout make_layout(const vbgs_params& p) {
+  Layout L{};
+  const int64_t K = p.K, n = p.n_max;
+  L.Kpad = (K + CT - 1) / CT * CT;
+  L.n_lse_part = (n + 255) / 256;
+  int ns = auto_split_mfma(L.Kpad);
+  const int nd = auto_split_direct(K);
+  if (nd > ns) ns = nd;
+  if (p.n_split > ns) ns = p.n_split;
+  L.nsplit_max = ns;
+  const int dts = direct_stride(p.D);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = up(o + (bytes ? bytes : 1));
+    return at;
+  };
+  L.frame = take(sizeof(FrameInfo));
+  L.mom_part = take((size_t)MOM_BLOCKS * 2 * MAXD * 8);
+  L.phi32 = take((size_t)n * FP * 4);
+  L.phih = take((size_t)n * FP * 2);
+  L.phil = take((size_t)n * FP * 2);
+  L.nphi = take((size_t)n * 4);
+  L.lse2 = take((size_t)n * 8);
+  L.lse_part = take((size_t)(L.n_lse_part + 1) * 8);
+  L.direct = take((size_t)L.Kpad * dts * 8);
+  L.c32 = take((size_t)L.Kpad * FP * 4);
+  L.ch = take((size_t)L.Kpad * FP * 2);
+  L.cl = take((size_t)L.Kpad * FP * 2);
+  L.nc = take((size_t)L.Kpad * 4);
+  L.kl = take((size_t)K * 8);
+  L.spart = take((size_t)ns * L.Kpad * stat_stride(p.D) * 8);
+  L.stats = take((size_t)K * nfeat(p.D) * 8);
+  L.total = o;
+  return L;
+}
+}  // namespace vbgs
+
+extern "C" {
+
+vbgs_status vbgs_default_params(vbgs_params* p, int32_t D, int64_t K, int64_t n_max) {
+  if (!p) return VBGS_ERR_ARG;
+  memset(p, 0, sizeof *p);
+  p->abi_version = VBGS_ABI_VERSION;
+  p->D = D;
+  p->K = K;
+  p->n_max = n_max;
+  p->kappa0 = 1.0;
+  p->nu0 = D + 2.0;
+  p->alpha0 = 1.0;
+  p->score_prec = D <= 6 ? VBGS_BF16X3 : VBGS_FP64;
+  p->exact = 1;
+  p->screen_margin = 0.0;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_query_sizes(const vbgs_params* p, size_t* state_bytes, size_t* workspace_bytes) {
+  const vbgs_status st = check_params(p, nullptr);
+  if (st != VBGS_OK) return st;
+  if (!state_bytes || !workspace_bytes) return VBGS_ERR_ARG;
+  *state_bytes = sizeof(StateHeader) + (size_t)2 * p->K * REC * 8;
+  *workspace_bytes = make_layout(*p).total;
+  return VBGS_OK;
+}
+
+static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
+  vbgs_ctx* c = new (std::nothrow) vbgs_ctx();
+  if (!c) return nullptr;
+  c->p = *p;
+  c->L = make_layout(*p);
+  c->state = state;
+  c->ws = ws;
+  c->last_N = -1;
+  c->post_version = 0;
+  c->lse_version = ~(uint64_t)0;
+  c->have_stats = false;
+  const int auto_ns = p->score_prec == VBGS_FP64 ? auto_split_direct(p->K) : auto_split_mfma(c->L.Kpad);
+  c->nsplit = p->n_split > 0 ? p->n_split : auto_ns;
+  const double T = p->screen_margin > 0 ? p->screen_margin : log((double)p->K) + log(1e12);
+  c->T2 = (float)(T * LOG2E);
+  return c;
+}
+
+vbgs_status vbgs_init(vbgs_ctx** out, const vbgs_params* p, const double* m0, const double* W0, void* state,
+                      void* workspace, void* stream) {
+  std::string why;
+  vbgs_status st = check_params(p, &why);
+  if (st != VBGS_OK) return st;
+  if (!out || !m0 || !W0 || !state || !workspace) return VBGS_ERR_ARG;
+  if (!aligned(state) || !aligned(workspace)) return VBGS_ERR_ARG;
+  const int D = p->D;
+  // W0^{-1} on the host: Cholesky of W0 (rejects non-PD), then invert
+  double L[MAXD][MAXD] = {{0}};
+  for (int j = 0; j < D; ++j) {
+    for (int i = 0; i < D; ++i)
+      if (fabs(W0[i * D + j] - W0[j * D + i]) > 1e-12 * (fabs(W0[i * D + j]) + fabs(W0[j * D + i])) + 1e-300)
+        return VBGS_ERR_NOT_PD;
+    double s = W0[j * D + j];
+    for (int t = 0; t < j; ++t) s -= L[j][t] * L[j][t];
+    if (!(s > 0) || !isfinite(s)) return VBGS_ERR_NOT_PD;
+    L[j][j] = sqrt(s);
+    for (int i = j + 1; i < D; ++i) {
+      double v = W0[i * D + j];
+      for (int t = 0; t < j; ++t) v -= L[i][t] * L[j][t];
+      L[i][j] = v / L[j][j];
+    }
+  }
+  double Li[MAXD][MAXD] = {{0}};
+  for (int j = 0; j < D; ++j) {
+    Li[j][j] = 1.0 / L[j][j];
+    for (int i = j + 1; i < D; ++i) {
+      double v = 0.0;
+      for (int t = j; t < i; ++t) v += L[i][t] * Li[t][j];
+      Li[i][j] = -v / L[i][i];
+    }
+  }
+  Init0 in{};
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) {
+      double v = 0.0;
+      for (int t = 0; t < D; ++t) v += Li[t][a] * Li[t][b];  // W0^{-1} = L^{-T} L^{-1}
+      in.W0inv[a * D + b] = v;
+    }
+  in.alpha0 = p->alpha0;
+  in.kappa0 = p->kappa0;
+  in.nu0 = p->nu0;
+  vbgs_ctx* c = new_ctx(p, state, workspace);
+  if (!c) return VBGS_ERR_ARG;
+  hipError_t e = launch_init_state(c->dev(), m0, in, S(stream));
+  if (e == hipSuccess) e = launch_clear_flags(c->dev(), S(stream));
+  if (e != hipSuccess) {
+    delete c;
+    return VBGS_ERR_HIP;
+  }
+  *out = c;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void* workspace) {
+  std::string why;
+  vbgs_status st = check_params(p, &why);
+  if (st != VBGS_OK) return st;
+  if (!out || !state || !workspace || !aligned(state) || !aligned(workspace)) return VBGS_ERR_ARG;
+  vbgs_ctx* c = new_ctx(p, state, workspace);
+  if (!c) return VBGS_ERR_ARG;
+  *out = c;
+  return VBGS_OK;
+}
+
+static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, void* stream) {
+  const DevPtrs d = c->dev();
+  EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
+  hipError_t e = launch_frame_prep(d, X, N, S(stream));
+  if (e == hipSuccess) e = launch_coeffs(d, S(stream));
+  if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, S(stream));
+  return hipfail(c, e, "pass 1");
+}
+
+vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, double* stats_out,
+                             void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+  if (N > 0 && !X) return fail(c, VBGS_ERR_ARG, "X is NULL");
+  vbgs_status st = run_pass1(c, X, N, lse_out, stream);
+  if (st != VBGS_OK) return st;
+  const DevPtrs d = c->dev();
+  EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
+  hipError_t e = launch_pass2(d, cfg, X, N, S(stream));
+  if (e == hipSuccess) e = launch_fold(d, cfg, stats_out, S(stream));
+  if (e != hipSuccess) return hipfail(c, e, "pass 2");
+  c->last_N = N;
+  c->lse_version = c->post_version;
+  c->have_stats = true;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_update(vbgs_ctx* c, int32_t commit, void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  if (commit != 0 && commit != 1) return fail(c, VBGS_ERR_ARG, "commit must be 0 or 1");
+  if (!c->have_stats) return fail(c, VBGS_ERR_STATE, "vbgs_update needs a preceding vbgs_estep_stats");
+  hipError_t e = launch_update(c->dev(), commit, S(stream));
+  if (e != hipSuccess) return hipfail(c, e, "update");
+  c->post_version++;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_elbo(vbgs_ctx* c, const float* X, int64_t N, double* elbo_dev, void* stream) {
+  if (!c || !elbo_dev) return VBGS_ERR_ARG;
+  if (!X) {
+    if (c->last_N < 0 || c->lse_version != c->post_version)
+      return fail(c, VBGS_ERR_STATE, "no LSE at the current posterior: pass X");
+  } else {
+    if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+    vbgs_status st = run_pass1(c, X, N, nullptr, stream);
+    if (st != VBGS_OK) return st;
+    c->last_N = N;
+    c->lse_version = c->post_version;
+  }
+  const int64_t np = (c->last_N + 255) / 256;
+  return hipfail(c, launch_elbo(c->dev(), np, elbo_dev, S(stream)), "elbo");
+}
+
+vbgs_status vbgs_get_params(vbgs_ctx* c, int32_t which, double* alpha, double* kappa, double* m, double* Winv,
+                            double* nu, void* stream) {
+  if (!c || (which != 0 && which != 1) || !alpha || !kappa || !m || !Winv || !nu) return VBGS_ERR_ARG;
+  return hipfail(c, launch_get_set(c->dev(), which, 0, alpha, kappa, m, Winv, nu, S(stream)), "get_params");
+}
+
+vbgs_status vbgs_set_params(vbgs_ctx* c, int32_t which, const double* alpha, const double* kappa,
+                            const double* m, const double* Winv, const double* nu, void* stream) {
+  if (!c || (which != 0 && which != 1) || !alpha || !kappa || !m || !Winv || !nu) return VBGS_ERR_ARG;
+  hipError_t e = launch_get_set(c->dev(), which, 1, (double*)alpha, (double*)kappa, (double*)m, (double*)Winv,
+                                (double*)nu, S(stream));
+  if (e != hipSuccess) return hipfail(c, e, "set_params");
+  c->post_version++;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_sync_status(vbgs_ctx* c, void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  int32_t flags = 0;
+  hipError_t e = hipStreamSynchronize(S(stream));
+  if (e == hipSuccess)
+    e = hipMemcpy(&flags, (char*)c->ws + c->L.frame + offsetof(FrameInfo, flags), sizeof flags,
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hipfail(c, e, "sync_status");
+  if (flags & FLAG_NOT_PD) return fail(c, VBGS_ERR_NOT_PD, "a W^{-1} was not positive definite");
+  if (flags & FLAG_NONFINITE) return fail(c, VBGS_ERR_NONFINITE, "non-finite input coordinates");
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_clear_flags(vbgs_ctx* c, void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  return hipfail(c, launch_clear_flags(c->dev(), S(stream)), "clear_flags");
+}
+
+vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[4], void* stream) {
+  if (!c || !out) return VBGS_ERR_ARG;
+  unsigned long long v[2] = {0, 0};
+  hipError_t e = hipStreamSynchronize(S(stream));
+  if (e == hipSuccess)
+    e = hipMemcpy(v, (char*)c->ws + c->L.frame + offsetof(FrameInfo, refined1), sizeof v, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hipfail(c, e, "counters");
+  out[0] = (int64_t)v[0];
+  out[1] = (int64_t)v[1];
+  out[2] = c->last_N;
+  out[3] = c->p.K;
+  return VBGS_OK;
+}
+
+const char* vbgs_last_error(const vbgs_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void vbgs_destroy(vbgs_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+// Internal definitions shared by the HIP translation units of libvbgs.
+// gfx950 (CDNA4) only: 64-lane wavefronts, MFMA matrix cores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vbgs.h"
+
+namespace vbgs {
+
+constexpr double LOG2E = 1.4426950408889634074;
+constexpr double LN2 = 0.69314718055994530942;
+constexpr double LN2PI = 1.8378770664093454836;
+constexpr double LNPI = 1.1447298858494001741;
+
+constexpr int MAXD = VBGS_MAX_D;
+constexpr int FP = 32;        // padded feature / coefficient slots per row
+constexpr int REC = 48;       // doubles per component record in the state
+constexpr int CT = 64;        // components per LDS tile (pass 1) and per pass-2 workgroup
+constexpr int PT = 64;        // points per LDS tile (pass 2)
+constexpr int P1_PB = 4;      // 16-point blocks per wave in pass 1
+constexpr int P1_PTS = 4 * P1_PB * 16;  // points per pass-1 workgroup (4 waves)
+constexpr int MOM_BLOCKS = 256;
+constexpr float DEAD_C0 = -1.0e30f;     // constant slot of padding components
+
+// device flag bits
+constexpr int FLAG_NOT_PD = 1;
+constexpr int FLAG_NONFINITE = 2;
+
+inline __host__ __device__ int nfeat(int D) { return 1 + D + D * (D + 1) / 2; }
+inline __host__ __device__ int ntri(int D) { return D * (D + 1) / 2; }
+inline __host__ __device__ int direct_stride(int D) { return D <= 6 ? 32 : 48; }
+// doubles per component row of the statistics partials (F = 45 at D = 8)
+inline __host__ __device__ int stat_stride(int D) { return D <= 6 ? 32 : 48; }
+
+// Per-frame data written by the moment kernels, read by every later kernel.
+struct FrameInfo {
+  float mu[MAXD];        // centring offsets (FP32 values, used exactly)
+  float inv_s[MAXD];     // 1 / s, s a power of two (exact)
+  double s[MAXD];
+  double sum_alpha_q, sum_alpha_p;
+  int32_t flags;
+  int32_t pad0;
+  unsigned long long refined1, refined2;
+  double pad1[4];
+};
+
+// Offsets (bytes) into the caller's workspace.
+struct Layout {
+  size_t frame, mom_part, phi32, phih, phil, nphi, lse2, lse_part, direct, c32, ch, cl, nc, kl,
+      spart, stats, total;
+  int64_t Kpad, n_lse_part;
+  int nsplit_max;
+};
+
+// State buffer: a header followed by the frame-prior and posterior records.
+struct StateHeader {
+  int64_t magic, abi, D, K;
+  int64_t pad[28];
+};
+constexpr int64_t STATE_MAGIC = 0x5342474256ll;  // "VBGBS"
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// float -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Digamma for x > 0: upward recurrence psi(x) = psi(x+1) - 1/x until x >= 10,
+// then the asymptotic series of Abramowitz & Stegun 6.3.18 (Bernoulli numbers
+// B_2..B_14); the first omitted term is below 1e-16 at x = 10.
+__device__ inline double vb_digamma(double x) {
+  double acc = 0.0;
+  while (x < 10.0) {
+    acc -= 1.0 / x;
+    x += 1.0;
+  }
+  const double r = 1.0 / x, r2 = r * r;
+  const double t =
+      r2 * (1.0 / 12 -
+            r2 * (1.0 / 120 -
+                  r2 * (1.0 / 252 - r2 * (1.0 / 240 - r2 * (1.0 / 132 - r2 * (691.0 / 32760 - r2 / 12))))));
+  return acc + log(x) - 0.5 * r - t;
+}
+
+// ln Gamma_D(a) = D(D-1)/4 ln pi + sum_{i=1..D} ln Gamma(a + (1-i)/2)
+__device__ inline double vb_mvlgamma(double a, int D) {
+  double s = 0.25 * D * (D - 1) * LNPI;
+  for (int i = 1; i <= D; ++i) s += lgamma(a + 0.5 * (1 - i));
+  return s;
+}
+
+// Exact score of one (point, component) pair in log2 units, FP64, direct
+// (non-expanded) form: s2 = g2 - || U (x - m) ||^2 with U = sqrt(nu log2(e) / 2) L^{-1},
+// L L^T = W^{-1}. Row layout: [g2, m_0..m_{D-1}, U lower-packed row-major].
+__device__ __forceinline__ double direct_score2(const double* __restrict__ T, const float* __restrict__ x,
+                                                int D) {
+  double d[MAXD];
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i)
+    if (i < D) d[i] = (double)x[i] - T[1 + i];
+  double q = 0.0;
+  const double* U = T + 1 + D;
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) {
+    if (i < D) {
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) y = fma(U[i * (i + 1) / 2 + j], d[j], y);
+      q = fma(y, y, q);
+    }
+  }
+  return T[0] - q;
+}
+
+// Same score, also returning the difference vector d = x - m (raw coordinates, FP64).
+__device__ __forceinline__ double direct_score2_d(const double* __restrict__ T, const float* __restrict__ x, int D,
+                                                  double* d) {
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) d[i] = (i < D) ? (double)x[i] - T[1 + i] : 0.0;
+  double q = 0.0;
+  const double* U = T + 1 + D;
+#pragma unroll
+  for (int i = 0; i < MAXD; ++i) {
+    if (i < D) {
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) y = fma(U[i * (i + 1) / 2 + j], d[j], y);
+      q = fma(y, y, q);
+    }
+  }
+  return T[0] - q;
+}
+
+template <int D>
+__device__ __forceinline__ double direct_score2_dt(const double* __restrict__ T, const float* __restrict__ x,
+                                                   double* d) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) d[i] = (double)x[i] - T[1 + i];
+  double q = 0.0;
+  const double* U = T + 1 + D;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double y = 0.0;
+#pragma unroll
+    for (int j = 0; j <= i; ++j) y = fma(U[i * (i + 1) / 2 + j], d[j], y);
+    q = fma(y, y, q);
+  }
+  return T[0] - q;
+}
+
+template <int D>
+__device__ __forceinline__ double direct_score2_t(const double* __restrict__ T, const double* __restrict__ x) {
+  double d[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) d[i] = x[i] - T[1 + i];
+  double q = 0.0;
+  const double* U = T + 1 + D;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double y = 0.0;
+#pragma unroll
+    for (int j = 0; j <= i; ++j) y = fma(U[i * (i + 1) / 2 + j], d[j], y);
+    q = fma(y, y, q);
+  }
+  return T[0] - q;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+Layout make_layout(const vbgs_params& p);
+
+struct DevPtrs {
+  char* ws;
+  double* state;
+  const Layout* L;
+  int D;
+  int64_t K;
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+  FrameInfo* frame() const { return at<FrameInfo>(L->frame); }
+  double* prior() const { return state + sizeof(StateHeader) / 8; }
+  double* post() const { return prior() + (size_t)K * REC; }
+};
+
+struct Init0 {
+  double W0inv[MAXD * MAXD];
+  double alpha0, kappa0, nu0;
+};
+
+hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& init, hipStream_t s);
+hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s);
+hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s);
+hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStream_t s);
+hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, double* kappa, double* m,
+                          double* Winv, double* nu, hipStream_t s);
+hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s);
+
+struct EstepCfg {
+  int prec;      // vbgs_prec
+  int exact;     // 1: screen + exact rescoring
+  float T2;      // screen margin in log2 units
+  int nsplit;    // pass-2 point splits
+};
+hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
+                        hipStream_t s);
+hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s);
+hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, hipStream_t s);
+
+}  // namespace vbgs

@@ -1,0 +1,166 @@
+"""Python binding of libvbgs: the same calls as the C ABI, over torch device tensors.
+
+This module only marshals arguments (device pointers, sizes, the current HIP
+stream); every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+class VBGSError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__("%s (%d)%s" % (_lib.STATUS.get(status, "?"), status, (": " + msg) if msg else ""))
+        self.status = status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(s=None):
+    s = torch.cuda.current_stream() if s is None else s
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x3", exact=True,
+                screen_margin=0.0, n_split=0):
+    p = _lib.Params()
+    L = _lib.load()
+    st = L.vbgs_default_params(ctypes.byref(p), int(D), int(K), int(n_max))
+    if st:
+        raise VBGSError(st)
+    p.kappa0 = float(kappa0)
+    p.nu0 = float(D + 2 if nu0 is None else nu0)
+    p.alpha0 = float(alpha0)
+    p.score_prec = _lib.PREC[score_prec] if isinstance(score_prec, str) else int(score_prec)
+    p.exact = 1 if exact else 0
+    p.screen_margin = float(screen_margin)
+    p.n_split = int(n_split)
+    return p
+
+
+def query_sizes(p):
+    L = _lib.load()
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    st = L.vbgs_query_sizes(ctypes.byref(p), ctypes.byref(sb), ctypes.byref(wb))
+    if st:
+        raise VBGSError(st)
+    return sb.value, wb.value
+
+
+class VBGS:
+    """One mixture of K Normal-Wishart components over D-dimensional points.
+
+    State (frame prior + posterior) and workspace are torch uint8 tensors owned
+    by this object; the library never allocates device memory.
+    """
+
+    def __init__(self, D, K, n_max, m0, W0, device="cuda", state=None, **kw):
+        self.lib = _lib.load()
+        self.D, self.K, self.n_max = int(D), int(K), int(n_max)
+        self.F = 1 + self.D + self.D * (self.D + 1) // 2
+        self.device = torch.device(device)
+        self.params = make_params(D, K, n_max, **kw)
+        sb, wb = query_sizes(self.params)
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.ctx = ctypes.c_void_p()
+        if state is not None:
+            if state.numel() != sb or state.dtype != torch.uint8 or state.device != self.device:
+                raise ValueError("state tensor does not match these params")
+            self.state = state
+            st = self.lib.vbgs_attach(ctypes.byref(self.ctx), ctypes.byref(self.params), _ptr(self.state),
+                                      _ptr(self.workspace))
+        else:
+            self.state = torch.empty(sb, dtype=torch.uint8, device=self.device)
+            m0 = torch.as_tensor(np.asarray(m0, np.float64) if not torch.is_tensor(m0) else m0,
+                                 dtype=torch.float64).to(self.device).contiguous()
+            if tuple(m0.shape) != (self.K, self.D):
+                raise ValueError("m0 must be K x D")
+            W0 = np.ascontiguousarray(np.asarray(W0, np.float64).reshape(self.D, self.D))
+            self._m0 = m0
+            st = self.lib.vbgs_init(ctypes.byref(self.ctx), ctypes.byref(self.params), _ptr(m0),
+                                    W0.ctypes.data_as(ctypes.c_void_p), _ptr(self.state), _ptr(self.workspace),
+                                    _stream())
+        if st:
+            raise VBGSError(st)
+
+    def _check(self, st):
+        if st:
+            raise VBGSError(st, self.lib.vbgs_last_error(self.ctx).decode())
+
+    def _points(self, X):
+        if X.dtype != torch.float32 or X.device != self.device or not X.is_contiguous() or X.dim() != 2 \
+                or X.shape[1] != self.D:
+            raise ValueError("X must be a contiguous N x D float32 tensor on %s" % self.device)
+        return X
+
+    def estep_stats(self, X, lse=True, stats=True, lse_out=None, stats_out=None):
+        X = self._points(X)
+        N = X.shape[0]
+        if lse and lse_out is None:
+            lse_out = torch.empty(N, dtype=torch.float64, device=self.device)
+        if stats and stats_out is None:
+            stats_out = torch.empty((self.K, self.F), dtype=torch.float64, device=self.device)
+        self._check(self.lib.vbgs_estep_stats(self.ctx, _ptr(X), N, _ptr(lse_out if lse else None),
+                                              _ptr(stats_out if stats else None), _stream()))
+        return (lse_out if lse else None), (stats_out if stats else None)
+
+    def update(self, commit=False):
+        self._check(self.lib.vbgs_update(self.ctx, 1 if commit else 0, _stream()))
+
+    def elbo(self, X=None, out=None):
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        if X is None:
+            st = self.lib.vbgs_elbo(self.ctx, None, 0, _ptr(out), _stream())
+        else:
+            X = self._points(X)
+            st = self.lib.vbgs_elbo(self.ctx, _ptr(X), X.shape[0], _ptr(out), _stream())
+        self._check(st)
+        return out
+
+    def get_params(self, which="posterior"):
+        w = 0 if which == "posterior" else 1
+        K, D, dev = self.K, self.D, self.device
+        o = dict(alpha=torch.empty(K, dtype=torch.float64, device=dev),
+                 kappa=torch.empty(K, dtype=torch.float64, device=dev),
+                 m=torch.empty((K, D), dtype=torch.float64, device=dev),
+                 Winv=torch.empty((K, D, D), dtype=torch.float64, device=dev),
+                 nu=torch.empty(K, dtype=torch.float64, device=dev))
+        self._check(self.lib.vbgs_get_params(self.ctx, w, _ptr(o["alpha"]), _ptr(o["kappa"]), _ptr(o["m"]),
+                                             _ptr(o["Winv"]), _ptr(o["nu"]), _stream()))
+        return o
+
+    def set_params(self, which, alpha, kappa, m, Winv, nu):
+        w = 0 if which == "posterior" else 1
+        t = [torch.as_tensor(np.asarray(a, np.float64) if not torch.is_tensor(a) else a, dtype=torch.float64)
+             .to(self.device).contiguous() for a in (alpha, kappa, m, Winv, nu)]
+        self._keep = t  # alive until the stream has consumed them
+        self._check(self.lib.vbgs_set_params(self.ctx, w, *[_ptr(a) for a in t], _stream()))
+
+    def sync_status(self):
+        return self.lib.vbgs_sync_status(self.ctx, _stream())
+
+    def clear_flags(self):
+        self._check(self.lib.vbgs_clear_flags(self.ctx, _stream()))
+
+    def counters(self):
+        out = (ctypes.c_int64 * 4)()
+        self._check(self.lib.vbgs_counters(self.ctx, out, _stream()))
+        return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3])
+
+    def close(self):
+        if self.ctx:
+            self.lib.vbgs_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+declared entry point, and its pure-host calls validate parameters."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(vbgs_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def _lib():
+    from paper_2603_08499_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libvbgs.so not built")
+    return L.load(), L
+
+
+def test_every_declared_symbol_is_exported():
+    lib, _ = _lib()
+    declared = _declared()
+    assert {"vbgs_init", "vbgs_estep_stats", "vbgs_update", "vbgs_elbo"} <= declared
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_query_sizes_and_validation():
+    import paper_2603_08499_amd as P
+    _lib()
+    p = P.make_params(6, 100000, 307200)
+    sb, wb = P.query_sizes(p)
+    assert sb == 256 + 2 * 100000 * 48 * 8
+    assert wb > 307200 * 32 * 8 and wb % 256 == 0
+    bad = [dict(D=0), dict(D=9), dict(K=0), dict(n_max=-1)]
+    for b in bad:
+        args = dict(D=6, K=10, n_max=10)
+        args.update(b)
+        with pytest.raises(P.VBGSError):
+            P.query_sizes(P.make_params(**args))
+    with pytest.raises(P.VBGSError) as e:
+        P.query_sizes(P.make_params(7, 10, 10, score_prec="bf16"))
+    assert e.value.status == -7
+    p = P.make_params(7, 10, 10, score_prec="fp64")
+    P.query_sizes(p)
+    p = P.make_params(6, 10, 10, nu0=4.0)
+    with pytest.raises(P.VBGSError):
+        P.query_sizes(p)
+
+
+def test_params_struct_layout_matches_header():
+    from paper_2603_08499_amd import _lib as L
+    P = L.Params
+    assert ctypes.sizeof(P) == 120
+    assert P.screen_margin.offset == 56 and P.n_split.offset == 64 and P.reserved.offset == 72
+
+
+def test_null_context_calls_fail_cleanly():
+    lib, L = _lib()
+    assert lib.vbgs_estep_stats(None, None, 0, None, None, None) == -1
+    assert lib.vbgs_update(None, 0, None) == -1
+    assert lib.vbgs_elbo(None, None, 0, None, None) == -1
+    assert lib.vbgs_last_error(None) == b"null context"
+    lib.vbgs_destroy(None)
