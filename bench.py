@@ -1,0 +1,185 @@
+#!/usr/bin/env python
+"""Throughput of one VB update (E-step + sufficient statistics + ELBO + conjugate update)
+on one MI355X, in point-component pairs per second.
+
+Workload (default "c3"): 640x480 back-projected RGB-D frames of a seeded scene of 10000
+anisotropic Gaussians with per-Gaussian colours and depth noise sigma 0.005, D = 6,
+N = 307200 points per frame, K = 100000 components, the posterior committed as the next
+frame's prior after every update. Frames are generated on the host, copied to HBM before
+the timed region and cycled. A step is one whole fit step over one frame.
+
+Prints one JSON line. Options: --gpus N (only 1: the path runs on one GPU),
+--steps K, --warmup W, --prec, --exact, --workload {c3,c2}, --no-cpu, --no-fp64.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "point-component pairs/s per VB update, mixed vs FP64; stats rel err"
+PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
+HBM_PEAK = 8.0e12
+
+
+def workload(name, n_frames):
+    from synth import scenes
+    if name == "c3":
+        scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
+        frames = [scenes.c3_frame(t, scene=scene) for t in range(n_frames)]
+        prior = scenes.c3_prior(frames[0])
+        desc = ("c3: 640x480 back-projected RGB-D frames of a seeded 10k-Gaussian scene (depth noise 0.005), "
+                "D=6, N=307200, K=100000, posterior committed as the next prior each step")
+    elif name == "c2":
+        scene = scenes.gauss_scene(2, 2000, 0.005, 0.05)
+        frames = [scenes.c2_frame(t, scene=scene) for t in range(n_frames)]
+        prior = scenes.c2_prior(frames[0])
+        desc = "c2: 3-D stream of 2k seeded anisotropic Gaussians, D=6, N=200000, K=10000, sliding window"
+    else:
+        raise SystemExit("unknown workload " + name)
+    return frames, prior, desc
+
+
+def run_steps(model, Xs, steps, torch):
+    for i in range(steps):
+        model.estep_stats(Xs[i % len(Xs)], lse=False, stats=False)
+        model.elbo()
+        model.update(commit=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--prec", default="bf16x3")
+    ap.add_argument("--exact", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=4)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-points", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this path runs on one GPU; --gpus %d is not supported (see the design notes on "
+              "sharding)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2603_08499_amd as P
+
+    dev = torch.device("cuda:0")
+    frames, pr, desc = workload(args.workload, args.frames)
+    N, D, K = frames[0].shape[0], pr.D, pr.K
+    Xs = [torch.from_numpy(f).to(dev) for f in frames]
+    print("bench: workload %s N=%d K=%d D=%d prec=%s exact=%d" % (args.workload, N, K, D, args.prec, args.exact),
+          file=sys.stderr, flush=True)
+
+    def new_model(prec, exact):
+        return P.VBGS(D, K, N, pr.m0, pr.W0, device=dev, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
+                      score_prec=prec, exact=bool(exact))
+
+    # ---- accuracy on frame 0 at the prior: mixed vs plain FP64 GPU path ------------------------
+    acc = {}
+    mm = new_model(args.prec, args.exact)
+    lse_m, st_m = mm.estep_stats(Xs[0])
+    cnt = mm.counters()
+    if not args.no_fp64:
+        mf = new_model("fp64", 0)
+        lse_f, st_f = mf.estep_stats(Xs[0])
+        torch.cuda.synchronize()
+        a, b = st_f.cpu().numpy(), st_m.cpu().numpy()
+        blocks = [(0, 1), (1, 1 + D), (1 + D, a.shape[1])]
+        rel = [float(np.linalg.norm(a[:, i:j] - b[:, i:j]) / max(np.linalg.norm(a[:, i:j]), 1e-30))
+               for i, j in blocks]
+        acc = {"stats_relerr_vs_fp64_gpu": max(rel), "stats_relerr_blocks": rel,
+               "lse_maxabs_vs_fp64_gpu": float((lse_f - lse_m).abs().max())}
+        del mf
+    lse_m_host = lse_m.cpu().numpy()
+    del mm
+    torch.cuda.synchronize()
+    print("bench: accuracy done", acc, file=sys.stderr, flush=True)
+
+    # ---- timed mixed-precision updates --------------------------------------------------------
+    model = new_model(args.prec, args.exact)
+    run_steps(model, Xs, args.warmup, torch)
+    torch.cuda.synchronize()
+    model.timing(True)
+    model.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(model, Xs, args.steps, torch)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = model.timing_read()
+    model.timing(False)
+    ms = (t1 - t0) / args.steps * 1e3
+    value = N * K / (ms * 1e-3)
+    status = model.sync_status()
+    print("bench: mixed %.3f ms/step, phases %s" % (ms, {k: round(v[0] / max(v[1], 1), 4) for k, v in
+                                                        phases.items() if v[1]}), file=sys.stderr, flush=True)
+
+    # ---- plain FP64 GPU comparator --------------------------------------------------------------
+    fp64 = None
+    if not args.no_fp64 and args.fp64_steps > 0:
+        m64 = new_model("fp64", 0)
+        run_steps(m64, Xs, 1, torch)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        run_steps(m64, Xs, args.fp64_steps, torch)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - s0) / args.fp64_steps * 1e3
+        fp64 = {"value": N * K / (ms64 * 1e-3), "ms_per_step": ms64, "steps": args.fp64_steps}
+        del m64
+        print("bench: fp64 %.3f ms/step" % ms64, file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel (live HIP-event durations) -----------------------------
+    F = 1 + D + D * (D + 1) // 2
+    avg = {k: v[0] / v[1] for k, v in phases.items() if v[1]}
+    dom = max(("pass1", "pass2"), key=lambda k: avg.get(k, 0.0))
+    t_dom = avg[dom] * 1e-3
+    algo_flops = 2.0 * F * N * K  # the score contraction c_k . phi(x_n) over all pairs, one launch
+    peak = PEAK.get(args.prec, PEAK["bf16"])
+    roof = {"bound": "mfma", "kernel": dom, "achieved": algo_flops / t_dom / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": algo_flops / t_dom / peak, "traffic": None,
+            "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": avg[dom],
+            "pairs_rescored_pass1": cnt["refined_pass1"], "pairs_rescored_pass2": cnt["refined_pass2"]}
+
+    # ---- CPU baseline: the oracle on a bounded sample --------------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        from oracle import vbgs_ref as R
+        ns = min(args.cpu_points, N)
+        idx = np.linspace(0, N - 1, ns).astype(np.int64)
+        Xc = frames[0][idx]
+        p = R.NW.from_prior(pr)
+        c0 = time.perf_counter()
+        res = R.cavi_step(Xc, p, p)
+        tc = time.perf_counter() - c0
+        cpu = {"value": ns * K / tc, "unit": "pairs/s", "cores": int(R.lib().oracle_threads()), "kind": "oracle",
+               "sample": "%d evenly strided points of frame 0 x all K=%d components, one full FP64 step "
+                         "(expectations, LSE, statistics with centred scatter, update, ELBO) in %.1f s"
+                         % (ns, K, tc),
+               "lse_maxabs_vs_gpu_mixed": float(np.abs(res.lse - lse_m_host[idx]).max())}
+        print("bench: cpu oracle %.1f s" % tc, file=sys.stderr, flush=True)
+
+    out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.prec + ("+f64" if args.exact else ""), "data": "synthetic",
+           "config": {"workload": desc, "N": N, "K": K, "D": D, "score_prec": args.prec,
+                      "exact": bool(args.exact), "frames_cycled": args.frames},
+           "phase_ms": {k: round(v, 5) for k, v in avg.items()},
+           "fp64_gpu": fp64, "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
+           "device_status": status, "roofline": roof, "cpu_baseline": cpu}
+    out.update(acc)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

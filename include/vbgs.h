@@ -157,6 +157,16 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
  * out[2] = number of points, out[3] = number of components. */
 vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[4], void* stream);
 
+/* Per-phase timing with HIP events recorded on the stream of each call.
+ * Phases: 0 frame moments + features, 1 expectations + coefficient rows, 2 pass 1 (LSE),
+ * 3 pass 2 (statistics), 4 fold, 5 update, 6 ELBO reduction, 7 reserved.
+ * vbgs_timing(ctx, 1) creates the events (host-side objects, no device memory) and records
+ * every later phase; 0 stops recording. vbgs_timing_read synchronises `stream`, writes the
+ * summed duration in ms and the number of recorded launches of each phase, and clears them. */
+#define VBGS_NPHASE 8
+vbgs_status vbgs_timing(vbgs_ctx* ctx, int32_t enable);
+vbgs_status vbgs_timing_read(vbgs_ctx* ctx, double ms[VBGS_NPHASE], int64_t counts[VBGS_NPHASE], void* stream);
+
 /* Last error message of this context ("" if none). Never NULL. */
 const char* vbgs_last_error(const vbgs_ctx* ctx);
 

@@ -10,6 +10,8 @@ LIB_PATH = os.path.join(HERE, "libvbgs.so")
 VBGS_ABI_VERSION = 1
 STATUS = {0: "VBGS_OK", -1: "VBGS_ERR_ARG", -2: "VBGS_ERR_SHAPE", -3: "VBGS_ERR_HIP", -4: "VBGS_ERR_NOT_PD",
           -5: "VBGS_ERR_NONFINITE", -6: "VBGS_ERR_STATE", -7: "VBGS_ERR_UNSUPPORTED"}
+NPHASE = 8
+PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "reserved"]
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
 
@@ -50,6 +52,8 @@ def load():
         "vbgs_sync_status": (i32, [vp, vp]),
         "vbgs_clear_flags": (i32, [vp, vp]),
         "vbgs_counters": (i32, [vp, ctypes.POINTER(i64), vp]),
+        "vbgs_timing": (i32, [vp, i32]),
+        "vbgs_timing_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp]),
         "vbgs_last_error": (ctypes.c_char_p, [vp]),
         "vbgs_destroy": (None, [vp]),
     }

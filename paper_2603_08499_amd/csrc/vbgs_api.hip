@@ -11,8 +11,22 @@
 
 using namespace vbgs;
 
+// Ring of event pairs per phase; a slot is harvested (its elapsed time added) when it is
+// reused, long after its events completed, so recording never waits inside a timed loop.
+struct PhaseTimer {
+  static constexpr int RING = 64;
+  hipEvent_t a[RING], b[RING];
+  bool used[RING];
+  int head;
+  double ms;
+  int64_t count;
+};
+
 struct vbgs_ctx {
   vbgs_params p;
+  bool timing;
+  bool timers_made;
+  PhaseTimer tm[VBGS_NPHASE];
   Layout L;
   void* state;
   void* ws;
@@ -98,6 +112,26 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+void harvest(PhaseTimer& t, int slot) {
+  if (!t.used[slot]) return;
+  float ms = 0.0f;
+  if (hipEventSynchronize(t.b[slot]) == hipSuccess && hipEventElapsedTime(&ms, t.a[slot], t.b[slot]) == hipSuccess) {
+    t.ms += ms;
+    t.count++;
+  }
+  t.used[slot] = false;
+}
+
+// RAII recorder of one phase on one stream
+struct Phase {
+  vbgs_ctx* c;
+  int ph;
+  hipStream_t s;
+  int slot;
+  Phase(vbgs_ctx* c_, int ph_, hipStream_t s_);
+  ~Phase();
+};
+
 vbgs_status fail(vbgs_ctx* c, vbgs_status st, const std::string& msg) {
   if (c) c->err = msg;
   return st;
@@ -113,6 +147,21 @@ vbgs_status hipfail(vbgs_ctx* c, hipError_t e, const char* where) {
 bool aligned(const void* p) { return ((uintptr_t)p % ALIGN) == 0; }
 
 }  // namespace
+
+Phase::Phase(vbgs_ctx* c_, int ph_, hipStream_t s_) : c(c_), ph(ph_), s(s_), slot(-1) {
+  if (!c->timing) return;
+  PhaseTimer& t = c->tm[ph];
+  slot = t.head;
+  harvest(t, slot);
+  hipEventRecord(t.a[slot], s);
+}
+Phase::~Phase() {
+  if (slot < 0) return;
+  PhaseTimer& t = c->tm[ph];
+  hipEventRecord(t.b[slot], s);
+  t.used[slot] = true;
+  t.head = (t.head + 1) % PhaseTimer::RING;
+}
 
 namespace vbgs {
 Layout make_layout(const vbgs_params& p) {
@@ -191,6 +240,8 @@ static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   c->post_version = 0;
   c->lse_version = ~(uint64_t)0;
   c->have_stats = false;
+  c->timing = false;
+  c->timers_made = false;
   const int auto_ns = p->score_prec == VBGS_FP64 ? auto_split_direct(p->K) : auto_split_mfma(c->L.Kpad);
   c->nsplit = p->n_split > 0 ? p->n_split : auto_ns;
   const double T = p->screen_margin > 0 ? p->screen_margin : log((double)p->K) + log(1e12);
@@ -267,9 +318,19 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
 static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, void* stream) {
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
-  hipError_t e = launch_frame_prep(d, X, N, S(stream));
-  if (e == hipSuccess) e = launch_coeffs(d, S(stream));
-  if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, S(stream));
+  hipError_t e;
+  {
+    Phase ph(c, 0, S(stream));
+    e = launch_frame_prep(d, X, N, S(stream));
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 1, S(stream));
+    e = launch_coeffs(d, S(stream));
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 2, S(stream));
+    e = launch_pass1(d, cfg, X, N, lse_out, S(stream));
+  }
   return hipfail(c, e, "pass 1");
 }
 
@@ -282,8 +343,15 @@ vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse
   if (st != VBGS_OK) return st;
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
-  hipError_t e = launch_pass2(d, cfg, X, N, S(stream));
-  if (e == hipSuccess) e = launch_fold(d, cfg, stats_out, S(stream));
+  hipError_t e;
+  {
+    Phase ph(c, 3, S(stream));
+    e = launch_pass2(d, cfg, X, N, S(stream));
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 4, S(stream));
+    e = launch_fold(d, cfg, stats_out, S(stream));
+  }
   if (e != hipSuccess) return hipfail(c, e, "pass 2");
   c->last_N = N;
   c->lse_version = c->post_version;
@@ -295,7 +363,11 @@ vbgs_status vbgs_update(vbgs_ctx* c, int32_t commit, void* stream) {
   if (!c) return VBGS_ERR_ARG;
   if (commit != 0 && commit != 1) return fail(c, VBGS_ERR_ARG, "commit must be 0 or 1");
   if (!c->have_stats) return fail(c, VBGS_ERR_STATE, "vbgs_update needs a preceding vbgs_estep_stats");
-  hipError_t e = launch_update(c->dev(), commit, S(stream));
+  hipError_t e;
+  {
+    Phase ph(c, 5, S(stream));
+    e = launch_update(c->dev(), commit, S(stream));
+  }
   if (e != hipSuccess) return hipfail(c, e, "update");
   c->post_version++;
   return VBGS_OK;
@@ -314,6 +386,7 @@ vbgs_status vbgs_elbo(vbgs_ctx* c, const float* X, int64_t N, double* elbo_dev, 
     c->lse_version = c->post_version;
   }
   const int64_t np = (c->last_N + 255) / 256;
+  Phase ph(c, 6, S(stream));
   return hipfail(c, launch_elbo(c->dev(), np, elbo_dev, S(stream)), "elbo");
 }
 
@@ -365,8 +438,56 @@ vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[4], void* stream) {
   return VBGS_OK;
 }
 
+vbgs_status vbgs_timing(vbgs_ctx* c, int32_t enable) {
+  if (!c || (enable != 0 && enable != 1)) return VBGS_ERR_ARG;
+  if (enable && !c->timers_made) {
+    for (int p = 0; p < VBGS_NPHASE; ++p) {
+      PhaseTimer& t = c->tm[p];
+      for (int i = 0; i < PhaseTimer::RING; ++i) {
+        hipError_t e = hipEventCreate(&t.a[i]);
+        if (e == hipSuccess) e = hipEventCreate(&t.b[i]);
+        if (e != hipSuccess) return hipfail(c, e, "hipEventCreate");
+        t.used[i] = false;
+      }
+      t.head = 0;
+      t.ms = 0.0;
+      t.count = 0;
+    }
+    c->timers_made = true;
+  }
+  c->timing = enable != 0;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_timing_read(vbgs_ctx* c, double ms[VBGS_NPHASE], int64_t counts[VBGS_NPHASE], void* stream) {
+  if (!c || !ms || !counts) return VBGS_ERR_ARG;
+  hipError_t e = hipStreamSynchronize(S(stream));
+  if (e != hipSuccess) return hipfail(c, e, "timing_read");
+  for (int p = 0; p < VBGS_NPHASE; ++p) {
+    ms[p] = 0.0;
+    counts[p] = 0;
+    if (!c->timers_made) continue;
+    PhaseTimer& t = c->tm[p];
+    for (int i = 0; i < PhaseTimer::RING; ++i) harvest(t, i);
+    ms[p] = t.ms;
+    counts[p] = t.count;
+    t.ms = 0.0;
+    t.count = 0;
+  }
+  return VBGS_OK;
+}
+
 const char* vbgs_last_error(const vbgs_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-void vbgs_destroy(vbgs_ctx* c) { delete c; }
+void vbgs_destroy(vbgs_ctx* c) {
+  if (!c) return;
+  if (c->timers_made)
+    for (int p = 0; p < VBGS_NPHASE; ++p)
+      for (int i = 0; i < PhaseTimer::RING; ++i) {
+        hipEventDestroy(c->tm[p].a[i]);
+        hipEventDestroy(c->tm[p].b[i]);
+      }
+  delete c;
+}
 
 }  // extern "C"

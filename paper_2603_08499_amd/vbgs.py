@@ -154,6 +154,15 @@ class VBGS:
         self._check(self.lib.vbgs_counters(self.ctx, out, _stream()))
         return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3])
 
+    def timing(self, enable=True):
+        self._check(self.lib.vbgs_timing(self.ctx, 1 if enable else 0))
+
+    def timing_read(self):
+        ms = (ctypes.c_double * _lib.NPHASE)()
+        cnt = (ctypes.c_int64 * _lib.NPHASE)()
+        self._check(self.lib.vbgs_timing_read(self.ctx, ms, cnt, _stream()))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.PHASES)}
+
     def close(self):
         if self.ctx:
             self.lib.vbgs_destroy(self.ctx)
