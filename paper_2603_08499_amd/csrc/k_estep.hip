@@ -6,18 +6,20 @@
 //
 // pass 1 (point-tile parallel): stream LDS-staged tiles of coefficient rows past a register-
 //   resident block of points; keep an online log-sum-exp per point -> LSE_n.
-// pass 2 (component-tile parallel): stream LDS-staged tiles of points past a register-
-//   resident block of components; recompute the scores, r = exp(s - LSE), and contract
-//   r^T phi on the matrix cores (the fused Delta S = R^T S_u of Eq. (fused_contr)); FP32
-//   accumulation per 64-point tile, folded into FP64 registers.
+// pass 2, plain precisions (exact = 0; component-tile parallel): stream LDS-staged tiles of
+//   points past a register-resident block of components; recompute the scores,
+//   r = exp(s - LSE), and contract r^T phi on the matrix cores (the fused Delta S = R^T S_u of
+//   Eq. (fused_contr)); FP32 accumulation per 64-point tile, folded into FP64 registers.
 // The N x K responsibility matrix is never stored.
 //
-// exact = 1: the low-precision GEMM is a *screen*. Its error is bounded by
+// exact = 1: the low-precision GEMM of pass 1 is a *screen*. Its error is bounded by
 //   |s~ - s| <= eps_prec * ||c_k|| * ||phi_n||  (rounding of features, coefficients,
 //   products and accumulation; Cauchy-Schwarz on sum_f |c_f phi_f|).
 // A pair is rescored exactly (FP64, direct form) unless its upper bound lies more than the
-// margin T below the point's running lower bound on max_k s (pass 1) or its LSE (pass 2);
-// every skipped pair carries < 2^-T of the point's mass.
+// margin T below a running lower bound on max_k s; every skipped pair carries < 2^-T of the
+// point's mass. The rescored pairs that may still carry mass are recorded per point, so the
+// statistics need no second sweep: r = 2^(s - LSE) of the recorded pairs is accumulated
+// exactly (128-bit fixed point, integer atomics: order-independent and deterministic).
 //
 // MFMA operand layouts used (64 lanes, lane = 16 g + c, g = lane / 16, c = lane % 16):
 //   v_mfma_f32_16x16x4_f32 : lane supplies A[c][g], B[g][c]; result lane holds D[4g + i][c].
@@ -118,6 +120,15 @@ struct EArgs {
   double* lse_part;           // pass-1 workgroups
   double* lse_out;            // N (nats) or null
   double* spart;              // nsplit x Kpad x 32
+  int32_t* cand_k;            // exact sweep: N x 4 x CS component indices
+  float* cand_s;              // N x 4 x CS exact scores (log2 units, rounded to FP32)
+  int32_t* cand_n;            // N x 4 list lengths, -1 = overflowed point
+  int32_t* over_list;         // overflowed points
+  unsigned long long* fx;     // Kpad x 32 x {lo, hi}: 128-bit fixed-point statistics (overflowed points)
+  int32_t* ccount;            // Kpad + 1: kept pairs per component
+  int32_t* coffset;           // Kpad + 1: exclusive scan of ccount
+  int32_t* ccursor;           // Kpad + 1: scatter cursors
+  int32_t* ent_n;             // kept pairs grouped by component: point index
   FrameInfo* frame;
   int64_t N, K, Kpad;
   int D, dts, nsplit;
@@ -149,8 +160,25 @@ __device__ __forceinline__ void count_refined(unsigned long long* ctr, unsigned 
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr, (unsigned long long)v);
 }
 
+// Drop candidates that can no longer carry mass (score below the exact running maximum minus
+// the margin); FP32 rounding is monotone, so fl(s) < fl(thr) implies s < thr.
+__device__ __noinline__ int evict_candidates(int32_t* __restrict__ ck, float* __restrict__ cs, float thr) {
+  int w = 0;
+  for (int j = 0; j < CS; ++j) {
+    const float v = cs[j];
+    const int32_t k = ck[j];
+    if (v >= thr) {
+      cs[w] = v;
+      ck[w] = k;
+      ++w;
+    }
+  }
+  return w;
+}
+
 // ---------------------------------------------------------------------------
-// pass 1: point-tile parallel online LSE
+// pass 1: point-tile parallel online LSE (exact mode: the only sweep over all pairs; every pair
+// that pass 2 would need has s >= LSE - T >= max - T, so it is rescored and recorded here)
 // ---------------------------------------------------------------------------
 template <int P>
 struct __attribute__((aligned(16))) CTile {
@@ -160,90 +188,125 @@ struct __attribute__((aligned(16))) CTile {
   float nc[CT];
 };
 
+// one thread's share of a coefficient tile (16 B pieces), staged in registers so the global
+// loads of tile t + 1 overlap the MFMA work on tile t
 template <int P>
-__device__ __forceinline__ void load_ctile(CTile<P>& T, const EArgs& a, int64_t k0) {
-  const int t = threadIdx.x;  // 256 threads, 16 B each per sweep
+struct TileRegs {
+  uint4 v[P == VBGS_FP32 ? 2 : (P == VBGS_BF16X3 ? 2 : 1)];
+  uint4 nc;
+};
+
+template <int P>
+__device__ __forceinline__ void tile_fetch(TileRegs<P>& R, const EArgs& a, int64_t k0) {
+  const int t = threadIdx.x;  // 256 threads
   if constexpr (P == VBGS_FP32) {
     const uint4* src = reinterpret_cast<const uint4*>(a.c32 + k0 * FP);
-    uint4* dst = reinterpret_cast<uint4*>(&T.c32[0][0]);
-    dst[t] = src[t];
-    dst[t + 256] = src[t + 256];
+    R.v[0] = src[t];
+    R.v[1] = src[t + 256];
   } else {
-    reinterpret_cast<uint4*>(&T.h[0][0])[t] = reinterpret_cast<const uint4*>(a.ch + k0 * FP)[t];
-    if constexpr (P == VBGS_BF16X3)
-      reinterpret_cast<uint4*>(&T.l[0][0])[t] = reinterpret_cast<const uint4*>(a.cl + k0 * FP)[t];
+    R.v[0] = reinterpret_cast<const uint4*>(a.ch + k0 * FP)[t];
+    if constexpr (P == VBGS_BF16X3) R.v[1] = reinterpret_cast<const uint4*>(a.cl + k0 * FP)[t];
   }
-  if (t < CT / 4) reinterpret_cast<uint4*>(T.nc)[t] = reinterpret_cast<const uint4*>(a.nc + k0)[t];
+  if (t < CT / 4) R.nc = reinterpret_cast<const uint4*>(a.nc + k0)[t];
+}
+
+template <int P>
+__device__ __forceinline__ void tile_store(CTile<P>& T, const TileRegs<P>& R) {
+  const int t = threadIdx.x;
+  if constexpr (P == VBGS_FP32) {
+    reinterpret_cast<uint4*>(&T.c32[0][0])[t] = R.v[0];
+    reinterpret_cast<uint4*>(&T.c32[0][0])[t + 256] = R.v[1];
+  } else {
+    reinterpret_cast<uint4*>(&T.h[0][0])[t] = R.v[0];
+    if constexpr (P == VBGS_BF16X3) reinterpret_cast<uint4*>(&T.l[0][0])[t] = R.v[1];
+  }
+  if (t < CT / 4) reinterpret_cast<uint4*>(T.nc)[t] = R.nc;
+}
+
+// Record a screened pair (its score upper bound hi) in the point's list for this lane group.
+// A full list first drops entries whose upper bound fell below the running lower bound on the
+// point's maximum minus the margin; if it is still full the point is marked overflowed.
+__device__ __forceinline__ void record_candidate(const EArgs& a, int64_t p, int g, int64_t k, float hi, float dead,
+                                                 int& cn, bool& ovf) {
+  int32_t* ck = a.cand_k + (p * 4 + g) * CS;
+  float* cs = a.cand_s + (p * 4 + g) * CS;
+  if (cn == CS) cn = evict_candidates(ck, cs, dead);
+  if (cn < CS) {
+    ck[cn] = (int32_t)k;
+    cs[cn] = hi;
+    ++cn;
+  } else {
+    ovf = true;
+  }
 }
 
 template <int P, bool EXACT>
 __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
-  __shared__ CTile<P> T;
+  __shared__ CTile<P> T[2];
   __shared__ double red[256];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
   const int64_t p0 = (int64_t)blockIdx.x * P1_PTS + w * (P1_PB * 16);
 
   Opnd<P> B[P1_PB];
-  float nph[P1_PB], M[P1_PB], ls[P1_PB];
-  double mref[P1_PB], lsd[P1_PB];
-  bool val[P1_PB];
+  float nphE[P1_PB], M[P1_PB], ls[P1_PB];
+  int cn[P1_PB];
+  bool val[P1_PB], ovf[P1_PB];
 #pragma unroll
   for (int b = 0; b < P1_PB; ++b) {
     const int64_t p = p0 + 16 * b + c;
     val[b] = p < a.N;
     if (val[b]) {
       B[b] = load_op<P>(a.phi32 + p * FP, a.phih + p * FP, a.phil + p * FP, g);
-      nph[b] = a.nphi[p];
+      nphE[b] = a.eps * a.nphi[p];
     } else {
       B[b] = zero_op<P>();
-      nph[b] = 0.0f;
+      nphE[b] = 0.0f;
     }
     M[b] = -INFINITY;
     ls[b] = 0.0f;
-    mref[b] = -INFINITY;
-    lsd[b] = 0.0;
+    cn[b] = 0;
+    ovf[b] = false;
   }
   unsigned nref = 0;
 
-  for (int64_t k0 = 0; k0 < a.Kpad; k0 += CT) {
-    __syncthreads();
-    load_ctile<P>(T, a, k0);
-    __syncthreads();
+  TileRegs<P> R;
+  tile_fetch<P>(R, a, 0);
+  tile_store<P>(T[0], R);
+  __syncthreads();
+  const int64_t ntiles = a.Kpad / CT;
+  for (int64_t it = 0; it < ntiles; ++it) {
+    const int cur = (int)(it & 1);
+    if (it + 1 < ntiles) tile_fetch<P>(R, a, (it + 1) * CT);
+    const CTile<P>& Tc = T[cur];
 #pragma unroll
     for (int cb = 0; cb < CT / 16; ++cb) {
       const int r = cb * 16 + c;
-      const Opnd<P> A = load_op<P>(&T.c32[P == VBGS_FP32 ? r : 0][0], &T.h[P == VBGS_FP32 ? 0 : r][0],
-                                   &T.l[P == VBGS_BF16X3 ? r : 0][0], g);
-      const f32x4 nc4 = *reinterpret_cast<const f32x4*>(&T.nc[cb * 16 + 4 * g]);
-      const int64_t kb = k0 + cb * 16 + 4 * g;
+      const Opnd<P> A = load_op<P>(&Tc.c32[P == VBGS_FP32 ? r : 0][0], &Tc.h[P == VBGS_FP32 ? 0 : r][0],
+                                   &Tc.l[P == VBGS_BF16X3 ? r : 0][0], g);
+      const f32x4 nc4 = *reinterpret_cast<const f32x4*>(&Tc.nc[cb * 16 + 4 * g]);
+      const float ncm = fmaxf(fmaxf(nc4[0], nc4[1]), fmaxf(nc4[2], nc4[3]));
 #pragma unroll
       for (int b = 0; b < P1_PB; ++b) {
         const f32x4 s = mfma_scores<P>(A, B[b]);
+        const float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
         if constexpr (EXACT) {
-          const float en = a.eps * nph[b];
-          const float e0 = en * nc4[0], e1 = en * nc4[1], e2 = en * nc4[2], e3 = en * nc4[3];
-          const float lo = fmaxf(fmaxf(s[0] - e0, s[1] - e1), fmaxf(s[2] - e2, s[3] - e3));
-          M[b] = fmaxf(M[b], lo);
-          const float thr = M[b] - a.T2;
-          int need = (s[0] + e0 >= thr ? 1 : 0) | (s[1] + e1 >= thr ? 2 : 0) | (s[2] + e2 >= thr ? 4 : 0) |
-                     (s[3] + e3 >= thr ? 8 : 0);
-          if (!val[b]) need = 0;
-          if (__builtin_amdgcn_ballot_w64(need != 0)) {
-            if (need) {
-              const int64_t p = p0 + 16 * b + c;
-              const float* x = a.X + p * a.D;
+          // one bound for the lane's four pairs: |s~ - s| <= e = eps ||phi|| max_i ||c_i||;
+          // M is a running lower bound on max_k s, so a pair whose upper bound s~ + e is below
+          // M - T carries < 2^-T of the point's mass and is skipped
+          const float e = nphE[b] * ncm;
+          M[b] = fmaxf(M[b], mx - e);
+          const float thr = M[b] - a.T2 - e;
+          if (val[b] && mx >= thr) {
+            const int64_t p = p0 + 16 * b + c;
+            const int64_t kb = it * CT + cb * 16 + 4 * g;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int64_t k = kb + i;
-                if (((need >> i) & 1) && k < a.K) {
-                  online_add(mref[b], lsd[b], direct_score2(a.direct + k * a.dts, x, a.D));
-                  ++nref;
-                }
+            for (int i = 0; i < 4; ++i)
+              if (s[i] >= thr && kb + i < a.K) {
+                record_candidate(a, p, g, kb + i, s[i] + e, M[b] - a.T2, cn[b], ovf[b]);
+                ++nref;
               }
-            }
           }
         } else {
-          const float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
           if (mx > M[b]) {
             ls[b] *= exp2f(M[b] - mx);
             M[b] = mx;
@@ -259,60 +322,74 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
         M[b] = fmaxf(M[b], __shfl_xor(M[b], 32));
       }
     }
+    if (it + 1 < ntiles) tile_store<P>(T[cur ^ 1], R);
+    __syncthreads();
   }
 
+  if constexpr (EXACT) {
+    // publish the lists: the four lane groups of a point agree on whether it overflowed
 #pragma unroll
-  for (int b = 0; b < P1_PB; ++b) {
-    double m = EXACT ? mref[b] : (double)M[b];
-    double l = EXACT ? lsd[b] : (double)ls[b];
-    for (int off = 16; off <= 32; off <<= 1) {
-      const double om = __shfl_xor(m, off);
-      const double ol = __shfl_xor(l, off);
-      lse_merge(m, l, om, ol);
-    }
-    const double L2 = m + log2(l);
-    const int64_t p = p0 + 16 * b + c;
-    if (g == 0) {
-      red[w * 64 + b * 16 + c] = val[b] ? L2 : 0.0;
+    for (int b = 0; b < P1_PB; ++b) {
+      const int64_t p = p0 + 16 * b + c;
+      int o = ovf[b] ? 1 : 0;
+      o |= __shfl_xor(o, 16);
+      o |= __shfl_xor(o, 32);
       if (val[b]) {
-        a.lse2[p] = L2;
-        if (a.lse_out) a.lse_out[p] = L2 * LN2;
+        a.cand_n[p * 4 + g] = o ? -1 : cn[b];
+        if (o && g == 0) a.over_list[atomicAdd(&a.frame->n_over, 1)] = (int32_t)p;
       }
     }
-  }
-  if constexpr (EXACT) count_refined(&a.frame->refined1, nref);
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int i = 0; i < 256; ++i) s += red[i];
-    a.lse_part[blockIdx.x] = s;
+    count_refined(&a.frame->refined1, nref);
+  } else {
+#pragma unroll
+    for (int b = 0; b < P1_PB; ++b) {
+      double m = (double)M[b];
+      double l = (double)ls[b];
+      for (int off = 16; off <= 32; off <<= 1) {
+        const double om = __shfl_xor(m, off);
+        const double ol = __shfl_xor(l, off);
+        lse_merge(m, l, om, ol);
+      }
+      const double L2 = m + log2(l);
+      const int64_t p = p0 + 16 * b + c;
+      if (g == 0) {
+        red[w * 64 + b * 16 + c] = val[b] ? L2 : 0.0;
+        if (val[b]) {
+          a.lse2[p] = L2;
+          if (a.lse_out) a.lse_out[p] = L2 * LN2;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sacc = 0.0;
+      for (int i = 0; i < 256; ++i) sacc += red[i];
+      a.lse_part[blockIdx.x] = sacc;
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// pass 2: component-tile parallel recompute + r^T phi on MFMA
+// pass 2 (plain GEMM precisions): component-tile parallel recompute + r^T phi on MFMA
 // ---------------------------------------------------------------------------
-template <int P, bool EXACT>
+template <int P>
 struct __attribute__((aligned(16))) PTile {
-  float f32[(P == VBGS_FP32 || !EXACT) ? PT : 1][FP];
+  float f32[PT][FP];
   uint16_t h[P == VBGS_FP32 ? 1 : PT][FP];
   uint16_t l[P == VBGS_BF16X3 ? PT : 1][FP];
   float nph[PT];
   double lse[PT];
 };
 
-template <int P, bool EXACT>
-__device__ __forceinline__ void load_ptile(PTile<P, EXACT>& T, const EArgs& a, int64_t n0) {
+template <int P>
+__device__ __forceinline__ void load_ptile(PTile<P>& T, const EArgs& a, int64_t n0) {
   const int t = threadIdx.x;
   const int64_t nvalid = a.N - n0;  // > 0
-  if constexpr (P == VBGS_FP32 || !EXACT) {
-    // 64 rows x 128 B = 512 x 16 B
-    for (int q = t; q < PT * FP / 4; q += 256) {
-      const int row = q / (FP / 4);
-      uint4 v = {0, 0, 0, 0};
-      if (row < nvalid) v = reinterpret_cast<const uint4*>(a.phi32 + n0 * FP)[q];
-      reinterpret_cast<uint4*>(&T.f32[0][0])[q] = v;
-    }
+  for (int q = t; q < PT * FP / 4; q += 256) {  // 64 rows x 128 B = 512 x 16 B
+    const int row = q / (FP / 4);
+    uint4 v = {0, 0, 0, 0};
+    if (row < nvalid) v = reinterpret_cast<const uint4*>(a.phi32 + n0 * FP)[q];
+    reinterpret_cast<uint4*>(&T.f32[0][0])[q] = v;
   }
   if constexpr (P != VBGS_FP32) {
     const int row = t / (FP / 8);  // 64 rows x 64 B = 256 x 16 B
@@ -332,116 +409,302 @@ __device__ __forceinline__ void load_ptile(PTile<P, EXACT>& T, const EArgs& a, i
   }
 }
 
-template <int P, bool EXACT, int DT>  // DT: compile-time D for the exact variant (0 for the plain tiers)
+template <int P>
 __global__ __launch_bounds__(256) void k_pass2(const EArgs a) {
-  __shared__ PTile<P, EXACT> T;
+  __shared__ PTile<P> T;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
   const int64_t kb = (int64_t)blockIdx.x * CT + w * 16;
   const int64_t kc = kb + c;
   const bool kval = kc < a.K;
   const Opnd<P> Bc = load_op<P>(a.c32 + kc * FP, a.ch + kc * FP, a.cl + kc * FP, g);
-  const float ncv = a.nc[kc];
-  const double* drow = a.direct + kc * a.dts;
   const int64_t ntile = (a.N + PT - 1) / PT;
   const int64_t t0 = ntile * blockIdx.y / a.nsplit, t1 = ntile * (blockIdx.y + 1) / a.nsplit;
-  // plain tiers: FP64 fold of the MFMA r^T phi tiles (lane: comps kb + 4g + j, slots c, 16 + c);
-  // exact tier: FP64 sums of the rescored pairs of component kc, centred at its mean m_kc
-  constexpr int NACC = EXACT ? 1 + DT + DT * (DT + 1) / 2 : 8;
-  double acc[NACC];
+  // FP64 fold of the FP32 MFMA r^T phi tiles; lane holds comps kb + 4g + j at slots c and 16 + c
+  double acc[8];
 #pragma unroll
-  for (int j = 0; j < NACC; ++j) acc[j] = 0.0;
-  unsigned nref = 0;
+  for (int j = 0; j < 8; ++j) acc[j] = 0.0;
 
   for (int64_t t = t0; t < t1; ++t) {
     const int64_t n0 = t * PT;
     __syncthreads();
-    load_ptile<P, EXACT>(T, a, n0);
+    load_ptile<P>(T, a, n0);
     __syncthreads();
     f32x4 sa = {0.f, 0.f, 0.f, 0.f}, sb = sa;
-    bool used = false;
 #pragma unroll
     for (int pb = 0; pb < PT / 16; ++pb) {
       const int r = pb * 16 + c;
-      const Opnd<P> A = load_op<P>(&T.f32[(P == VBGS_FP32 || !EXACT) ? r : 0][0], &T.h[P == VBGS_FP32 ? 0 : r][0],
-                                   &T.l[P == VBGS_BF16X3 ? r : 0][0], g);
+      const Opnd<P> A = load_op<P>(&T.f32[r][0], &T.h[P == VBGS_FP32 ? 0 : r][0], &T.l[P == VBGS_BF16X3 ? r : 0][0], g);
       const f32x4 s = mfma_scores<P>(A, Bc);  // lane: points pb*16 + 4g + i, component kc
       const int rb = pb * 16 + 4 * g;
-      float rr[4];
-      if constexpr (EXACT) {
-        const float en = a.eps * ncv;
-        int need = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float thr = (float)(T.lse[rb + i] - (double)a.T2);
-          if (kval && s[i] + en * T.nph[rb + i] >= thr) need |= 1 << i;
-        }
-        if (__builtin_amdgcn_ballot_w64(need != 0) != 0 && need) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if ((need >> i) & 1) {
-              const int64_t p = n0 + rb + i;
-              double dv[DT > 0 ? DT : 1];
-              const double s2 = direct_score2_dt<DT>(drow, a.X + p * DT, dv);
-              const double rv = exp2(s2 - T.lse[rb + i]);
-              acc[0] += rv;
-              int o = 1 + DT;
-#pragma unroll
-              for (int u = 0; u < DT; ++u) {
-                const double rd = rv * dv[u];
-                acc[1 + u] += rd;
-#pragma unroll
-                for (int v = u; v < DT; ++v) acc[o++] += rd * dv[v];
-              }
-              ++nref;
-            }
-          }
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) rr[i] = kval ? exp2f(s[i] - (float)T.lse[rb + i]) : 0.0f;
-        used = true;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float fa = T.f32[rb + i][c];
-          const float fb = T.f32[rb + i][16 + c];
-          sa = __builtin_amdgcn_mfma_f32_16x16x4f32(rr[i], fa, sa, 0, 0, 0);
-          sb = __builtin_amdgcn_mfma_f32_16x16x4f32(rr[i], fb, sb, 0, 0, 0);
-        }
+      for (int i = 0; i < 4; ++i) {
+        const float rr = kval ? exp2f(s[i] - (float)T.lse[rb + i]) : 0.0f;
+        sa = __builtin_amdgcn_mfma_f32_16x16x4f32(rr, T.f32[rb + i][c], sa, 0, 0, 0);
+        sb = __builtin_amdgcn_mfma_f32_16x16x4f32(rr, T.f32[rb + i][16 + c], sb, 0, 0, 0);
       }
     }
-    if constexpr (!EXACT) {
-      if (used) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[j] += (double)sa[j];
-          acc[4 + j] += (double)sb[j];
-        }
-      }
-    }
-  }
-  if constexpr (EXACT) {
-    // the four lane groups hold partial sums of the same component: combine (commutative pairs,
-    // so every lane ends with bitwise the same total)
-#pragma unroll
-    for (int j = 0; j < NACC; ++j) {
-      acc[j] += __shfl_xor(acc[j], 16);
-      acc[j] += __shfl_xor(acc[j], 32);
-    }
-    if (g == 0) {
-      double* out = a.spart + ((int64_t)blockIdx.y * a.Kpad + kc) * FP;
-#pragma unroll
-      for (int j = 0; j < 1 + DT + DT * (DT + 1) / 2; ++j) out[j] = acc[j];
-    }
-    count_refined(&a.frame->refined2, nref);
-  } else {
-    // lane holds components kb + 4g + j at slots c and 16 + c
-    double* out = a.spart + ((int64_t)blockIdx.y * a.Kpad + kb) * FP;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      out[(4 * g + j) * FP + c] = acc[j];
-      out[(4 * g + j) * FP + 16 + c] = acc[4 + j];
+      acc[j] += (double)sa[j];
+      acc[4 + j] += (double)sb[j];
     }
   }
+  double* out = a.spart + ((int64_t)blockIdx.y * a.Kpad + kb) * FP;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    out[(4 * g + j) * FP + c] = acc[j];
+    out[(4 * g + j) * FP + 16 + c] = acc[4 + j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exact mode, statistics from the recorded candidates
+// ---------------------------------------------------------------------------
+// v * 2^64 as a two's-complement 128-bit integer {lo, hi} added with integer atomics: the sum is
+// exact (to 2^-64 per term) and independent of the order of the additions, so the statistics
+// are bitwise reproducible without sorting the contributions by component.
+__device__ __forceinline__ void fx_add(unsigned long long* cell, double v) {
+  double hi_d = floor(v);
+  double frac = v - hi_d;  // exact, in [0, 1]
+  if (frac >= 1.0) {
+    frac = 0.0;
+    hi_d += 1.0;
+  }
+  const unsigned long long lo = (unsigned long long)(frac * 18446744073709551616.0);
+  const unsigned long long old = atomicAdd(&cell[0], lo);
+  const long long h = (long long)hi_d + ((old + lo < old) ? 1 : 0);
+  if (h != 0) atomicAdd(&cell[1], (unsigned long long)h);
+}
+
+// contributions of one pair to the statistics of component k, in coordinates centred at m_k
+// and scaled by the frame's power-of-two scales (so the fixed point keeps its resolution)
+template <int DT>
+__device__ __forceinline__ void fx_pair(unsigned long long* __restrict__ fx, int64_t k, double r,
+                                        const double* d, const double* is) {
+  unsigned long long* row = fx + k * FP * 2;
+  fx_add(row, r);
+  double u[DT];
+#pragma unroll
+  for (int i = 0; i < DT; ++i) {
+    u[i] = d[i] * is[i];
+    fx_add(row + 2 * (1 + i), r * u[i]);
+  }
+  int o = 1 + DT;
+#pragma unroll
+  for (int i = 0; i < DT; ++i)
+#pragma unroll
+    for (int j = i; j < DT; ++j, ++o) fx_add(row + 2 * o, r * u[i] * u[j]);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+// ---- exact LSE of the recorded candidates, one thread per point ---------------------------------
+template <int DT>
+__global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+  double L2 = 0.0;
+  if (p < a.N) {
+    if (a.cand_n[p * 4] < 0) {
+      L2 = a.lse2[p];  // overflowed point: full rescan by k_over_lse
+    } else {
+      const float* x = a.X + p * DT;
+      double m = -INFINITY, l = 0.0;
+      for (int g = 0; g < 4; ++g) {
+        const int cnt = a.cand_n[p * 4 + g];
+        for (int j = 0; j < cnt; ++j) {
+          const int64_t e = (p * 4 + g) * CS + j;
+          double d[DT];
+          const double s2 = direct_score2_dt<DT>(a.direct + (int64_t)a.cand_k[e] * a.dts, x, d);
+          online_add(m, l, s2);
+          a.cand_s[e] = (float)s2;
+        }
+      }
+      L2 = m + log2(l);
+      a.lse2[p] = L2;
+      // keep the pairs that can carry mass (FP32 rounding is monotone, see evict_candidates)
+      const float thr = (float)(L2 - (double)a.T2);
+      for (int g = 0; g < 4; ++g) {
+        const int cnt = a.cand_n[p * 4 + g];
+        for (int j = 0; j < cnt; ++j) {
+          const int64_t e = (p * 4 + g) * CS + j;
+          if (a.cand_s[e] >= thr) atomicAdd(&a.ccount[a.cand_k[e]], 1);
+          else a.cand_k[e] = -1;
+        }
+      }
+    }
+    if (a.lse_out) a.lse_out[p] = L2 * LN2;
+  }
+  red[tid] = L2;
+  __syncthreads();
+  if (tid == 0) {
+    double sacc = 0.0;
+    for (int i = 0; i < 256; ++i) sacc += red[i];
+    a.lse_part[blockIdx.x] = sacc;
+  }
+}
+
+// ---- overflowed points: exact LSE over all K (one workgroup per point) --------------------------
+template <int DT>
+__global__ __launch_bounds__(256) void k_over_lse(const EArgs a) {
+  __shared__ double sm[256], sl[256];
+  const int n_over = a.frame->n_over;
+  for (int i = blockIdx.x; i < n_over; i += gridDim.x) {
+    const int64_t p = a.over_list[i];
+    const float* x = a.X + p * DT;
+    double m = -INFINITY, l = 0.0;
+    for (int64_t k = threadIdx.x; k < a.K; k += 256) {
+      double d[DT];
+      online_add(m, l, direct_score2_dt<DT>(a.direct + k * a.dts, x, d));
+    }
+    sm[threadIdx.x] = m;
+    sl[threadIdx.x] = l;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        double mm = sm[threadIdx.x], ll = sl[threadIdx.x];
+        lse_merge(mm, ll, sm[threadIdx.x + w], sl[threadIdx.x + w]);
+        sm[threadIdx.x] = mm;
+        sl[threadIdx.x] = ll;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.lse2[p] = sm[0] + log2(sl[0]);
+    __syncthreads();
+  }
+}
+
+// ---- overflowed points: statistics of every pair within the margin (fixed-point atomics) --------
+template <int DT>
+__global__ __launch_bounds__(256) void k_over_stats(const EArgs a) {
+  const int n_over = a.frame->n_over;
+  double is[DT];
+#pragma unroll
+  for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
+  for (int i = blockIdx.x; i < n_over; i += gridDim.x) {
+    const int64_t p = a.over_list[i];
+    const double L2 = a.lse2[p];
+    const float* x = a.X + p * DT;
+    for (int64_t k = threadIdx.x; k < a.K; k += 256) {
+      double d[DT];
+      const double s2 = direct_score2_dt<DT>(a.direct + k * a.dts, x, d);
+      if (s2 >= L2 - (double)a.T2) fx_pair<DT>(a.fx, k, exp2(s2 - L2), d, is);
+    }
+  }
+}
+
+// ---- transpose of the kept pairs: exclusive scan of the per-component counts (one workgroup) ----
+__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* __restrict__ cnt, int32_t* __restrict__ off,
+                                                      int64_t K) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (K + 1023) / 1024;
+  const int64_t a0 = t * per, a1 = min(K, a0 + per);
+  int32_t sum = 0;
+  for (int64_t k = a0; k < a1; ++k) sum += cnt[k];
+  part[t] = sum;
+  __syncthreads();
+  for (int w = 1; w < 1024; w <<= 1) {  // inclusive Hillis-Steele scan
+    const int32_t v = t >= w ? part[t - w] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - sum;
+  for (int64_t k = a0; k < a1; ++k) {
+    off[k] = run;
+    run += cnt[k];
+  }
+  if (t == 1023) off[K] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.N || a.cand_n[p * 4] < 0) return;
+  for (int g = 0; g < 4; ++g) {
+    const int cnt = a.cand_n[p * 4 + g];
+    for (int j = 0; j < cnt; ++j) {
+      const int32_t k = a.cand_k[(p * 4 + g) * CS + j];
+      if (k >= 0) a.ent_n[a.coffset[k] + atomicAdd(&a.ccursor[k], 1)] = (int32_t)p;
+    }
+  }
+}
+
+// ---- per-component exact statistics: 128-bit fixed-point sums in registers ----------------------
+// The sum of integers does not depend on the order of the pairs, so the scatter order above does
+// not affect the result (bitwise reproducible).
+struct Fx128 {
+  unsigned long long lo;
+  long long hi;
+};
+
+__device__ __forceinline__ void fx_acc(Fx128& a, double v) {
+  double hi_d = floor(v);
+  double frac = v - hi_d;
+  if (frac >= 1.0) {
+    frac = 0.0;
+    hi_d += 1.0;
+  }
+  const unsigned long long lo = (unsigned long long)(frac * 18446744073709551616.0);
+  a.lo += lo;
+  a.hi += (long long)hi_d + (a.lo < lo ? 1 : 0);
+}
+
+template <int DT>
+__global__ __launch_bounds__(128) void k_comp_stats(const EArgs a) {
+  constexpr int F = 1 + DT + DT * (DT + 1) / 2;
+  const int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (k >= a.K) return;
+  double is[DT];
+#pragma unroll
+  for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
+  Fx128 acc[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {  // contributions of overflowed points (global fixed-point atomics)
+    acc[f].lo = a.fx[(k * FP + f) * 2];
+    acc[f].hi = (long long)a.fx[(k * FP + f) * 2 + 1];
+  }
+  const double* row = a.direct + k * a.dts;
+  const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
+  for (int32_t e = e0; e < e1; ++e) {
+    const int64_t n = a.ent_n[e];
+    double d[DT];
+    const double s2 = direct_score2_dt<DT>(row, a.X + n * DT, d);
+    const double r = exp2(s2 - a.lse2[n]);
+    fx_acc(acc[0], r);
+    double u[DT];
+#pragma unroll
+    for (int i = 0; i < DT; ++i) {
+      u[i] = d[i] * is[i];
+      fx_acc(acc[1 + i], r * u[i]);
+    }
+    int o = 1 + DT;
+#pragma unroll
+    for (int i = 0; i < DT; ++i)
+#pragma unroll
+      for (int j = i; j < DT; ++j, ++o) fx_acc(acc[o], r * u[i] * u[j]);
+  }
+  // fixed point -> FP64, undo the power-of-two scaling; raw coordinates centred at m_k
+  double* out = a.spart + k * FP;
+  out[0] = (double)acc[0].hi + (double)acc[0].lo * 5.42101086242752217e-20;
+#pragma unroll
+  for (int i = 0; i < DT; ++i)
+    out[1 + i] = ((double)acc[1 + i].hi + (double)acc[1 + i].lo * 5.42101086242752217e-20) * a.frame->s[i];
+  int o = 1 + DT;
+#pragma unroll
+  for (int i = 0; i < DT; ++i)
+#pragma unroll
+    for (int j = i; j < DT; ++j, ++o)
+      out[o] = ((double)acc[o].hi + (double)acc[o].lo * 5.42101086242752217e-20) * a.frame->s[i] * a.frame->s[j];
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -598,6 +861,15 @@ static EArgs make_args(const DevPtrs& d, const EstepCfg& c, const float* X, int6
   a.lse_part = d.at<double>(L.lse_part);
   a.lse_out = lse_out;
   a.spart = d.at<double>(L.spart);
+  a.cand_k = d.at<int32_t>(L.cand_k);
+  a.cand_s = d.at<float>(L.cand_s);
+  a.cand_n = d.at<int32_t>(L.cand_n);
+  a.over_list = d.at<int32_t>(L.over_list);
+  a.fx = d.at<unsigned long long>(L.fx);
+  a.ccount = d.at<int32_t>(L.ccount);
+  a.coffset = d.at<int32_t>(L.coffset);
+  a.ccursor = d.at<int32_t>(L.ccursor);
+  a.ent_n = d.at<int32_t>(L.ent_n);
   a.frame = d.frame();
   a.N = N;
   a.K = d.K;
@@ -629,12 +901,31 @@ hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int
   }
   const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
 #define VB_P1(PP, EE) hipLaunchKernelGGL((k_pass1<PP, EE>), grid, dim3(256), 0, s, a)
-  if (c.prec == VBGS_FP32) {
-    if (c.exact) VB_P1(VBGS_FP32, true); else VB_P1(VBGS_FP32, false);
-  } else if (c.prec == VBGS_BF16) {
-    if (c.exact) VB_P1(VBGS_BF16, true); else VB_P1(VBGS_BF16, false);
-  } else {
-    if (c.exact) VB_P1(VBGS_BF16X3, true); else VB_P1(VBGS_BF16X3, false);
+  if (!c.exact) {
+    if (c.prec == VBGS_FP32) VB_P1(VBGS_FP32, false);
+    else if (c.prec == VBGS_BF16) VB_P1(VBGS_BF16, false);
+    else VB_P1(VBGS_BF16X3, false);
+    return hipGetLastError();
+  }
+  // exact: screen sweep recording candidates, then exact LSE (overflowed points first)
+  const int64_t Kp1 = d.L->Kpad + 1;
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1);
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, d.L->Kpad * FP * 2);
+  if (c.prec == VBGS_FP32) VB_P1(VBGS_FP32, true);
+  else if (c.prec == VBGS_BF16) VB_P1(VBGS_BF16, true);
+  else VB_P1(VBGS_BF16X3, true);
+  const dim3 gp((unsigned)((N + 255) / 256));
+  switch (d.D) {
+#define VB_LSE(DD)                                                           \
+  case DD:                                                                   \
+    hipLaunchKernelGGL(k_over_lse<DD>, dim3(64), dim3(256), 0, s, a);        \
+    hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, a);             \
+    break;
+    VB_LSE(1) VB_LSE(2) VB_LSE(3) VB_LSE(4) VB_LSE(5) VB_LSE(6)
+#undef VB_LSE
+    default:
+      return hipErrorInvalidValue;
   }
 #undef VB_P1
   return hipGetLastError();
@@ -655,34 +946,48 @@ hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int
     }
     return hipGetLastError();
   }
+  if (c.exact) {
+    // statistics of the kept candidates: overflowed points (atomics), transpose, per-component sums
+    if (N > 0) {
+      const dim3 gp((unsigned)((N + 255) / 256));
+      const dim3 gk((unsigned)((d.K + 127) / 128));
+      switch (d.D) {
+#define VB_ST(DD)                                                                     \
+  case DD:                                                                            \
+    hipLaunchKernelGGL(k_over_stats<DD>, dim3(64), dim3(256), 0, s, a);               \
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, a.ccount, a.coffset, d.K); \
+    hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                      \
+    hipLaunchKernelGGL(k_comp_stats<DD>, gk, dim3(128), 0, s, a);                     \
+    break;
+        VB_ST(1) VB_ST(2) VB_ST(3) VB_ST(4) VB_ST(5) VB_ST(6)
+#undef VB_ST
+        default:
+          return hipErrorInvalidValue;
+      }
+    } else {
+      hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(a.spart),
+                         d.L->Kpad * FP);
+    }
+    return hipGetLastError();
+  }
   const dim3 grid((unsigned)(d.L->Kpad / CT), (unsigned)c.nsplit);
-#define VB_P2(PP, EE, DD) hipLaunchKernelGGL((k_pass2<PP, EE, DD>), grid, dim3(256), 0, s, a)
-#define VB_P2X(PP)                  \
-  switch (d.D) {                    \
-    case 1: VB_P2(PP, true, 1); break; \
-    case 2: VB_P2(PP, true, 2); break; \
-    case 3: VB_P2(PP, true, 3); break; \
-    case 4: VB_P2(PP, true, 4); break; \
-    case 5: VB_P2(PP, true, 5); break; \
-    case 6: VB_P2(PP, true, 6); break; \
-    default: return hipErrorInvalidValue; \
-  }
+#define VB_P2(PP) hipLaunchKernelGGL((k_pass2<PP>), grid, dim3(256), 0, s, a)
   if (c.prec == VBGS_FP32) {
-    if (c.exact) { VB_P2X(VBGS_FP32) } else VB_P2(VBGS_FP32, false, 0);
+    VB_P2(VBGS_FP32);
   } else if (c.prec == VBGS_BF16) {
-    if (c.exact) { VB_P2X(VBGS_BF16) } else VB_P2(VBGS_BF16, false, 0);
+    VB_P2(VBGS_BF16);
   } else {
-    if (c.exact) { VB_P2X(VBGS_BF16X3) } else VB_P2(VBGS_BF16X3, false, 0);
+    VB_P2(VBGS_BF16X3);
   }
-#undef VB_P2X
 #undef VB_P2
   return hipGetLastError();
 }
 
 hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, hipStream_t s) {
   const int mode = c.prec == VBGS_FP64 ? 0 : (c.exact ? 2 : 1);
+  const int nsplit = mode == 2 ? 1 : c.nsplit;
   hipLaunchKernelGGL(k_fold, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.at<double>(d.L->spart),
-                     c.nsplit, d.L->Kpad, d.K, d.D, d.frame(), d.at<double>(d.L->direct), direct_stride(d.D), mode,
+                     nsplit, d.L->Kpad, d.K, d.D, d.frame(), d.at<double>(d.L->direct), direct_stride(d.D), mode,
                      d.at<double>(d.L->stats), stats_out);
   return hipGetLastError();
 }

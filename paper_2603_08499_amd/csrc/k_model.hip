@@ -99,6 +99,7 @@ __global__ void k_moments_final(const double* __restrict__ part, int64_t N, int 
   if (i == 0) {
     fr->refined1 = 0;
     fr->refined2 = 0;
+    fr->n_over = 0;
   }
 }
 

@@ -90,6 +90,10 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "MFMA precisions support D <= 6 (32 feature slots); use VBGS_FP64";
     return VBGS_ERR_UNSUPPORTED;
   }
+  if (p->score_prec != VBGS_FP64 && p->exact == 1 && p->n_max > ((int64_t)1 << 25)) {
+    if (why) *why = "exact MFMA mode supports n_max <= 2^25 (candidate lists are indexed in int32)";
+    return VBGS_ERR_SHAPE;
+  }
   if (p->exact != 0 && p->exact != 1) {
     if (why) *why = "exact must be 0 or 1";
     return VBGS_ERR_ARG;
@@ -197,6 +201,16 @@ Layout make_layout(const vbgs_params& p) {
   L.kl = take((size_t)K * 8);
   L.spart = take((size_t)ns * L.Kpad * stat_stride(p.D) * 8);
   L.stats = take((size_t)K * nfeat(p.D) * 8);
+  const bool sparse = p.score_prec != VBGS_FP64;  // exact MFMA mode: candidate lists + fixed-point sums
+  L.cand_k = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
+  L.cand_s = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
+  L.cand_n = take(sparse ? (size_t)n * 4 * 4 : 0);
+  L.over_list = take(sparse ? (size_t)n * 4 : 0);
+  L.fx = take(sparse ? (size_t)L.Kpad * FP * 16 : 0);
+  L.ccount = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
+  L.coffset = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
+  L.ccursor = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
+  L.ent_n = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
   L.total = o;
   return L;
 }

@@ -22,6 +22,7 @@ constexpr int PT = 64;        // points per LDS tile (pass 2)
 constexpr int P1_PB = 4;      // 16-point blocks per wave in pass 1
 constexpr int P1_PTS = 4 * P1_PB * 16;  // points per pass-1 workgroup (4 waves)
 constexpr int MOM_BLOCKS = 256;
+constexpr int CS = 16;        // candidate slots per (point, lane group) in the exact sweep
 constexpr float DEAD_C0 = -1.0e30f;     // constant slot of padding components
 
 // device flag bits
@@ -43,13 +44,15 @@ struct FrameInfo {
   int32_t flags;
   int32_t pad0;
   unsigned long long refined1, refined2;
-  double pad1[4];
+  int32_t n_over;        // points whose candidate lists overflowed in the sweep
+  int32_t pad2;
+  double pad1[3];
 };
 
 // Offsets (bytes) into the caller's workspace.
 struct Layout {
   size_t frame, mom_part, phi32, phih, phil, nphi, lse2, lse_part, direct, c32, ch, cl, nc, kl,
-      spart, stats, total;
+      spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ccursor, ent_n, total;
   int64_t Kpad, n_lse_part;
   int nsplit_max;
 };

@@ -251,3 +251,25 @@ def test_full_k_c3_slice(dev):
     print("c3 slice: max|dLSE| %.2e stats relerr %.2e ELBO relerr %.2e" % (dl, es, abs(F.item() - Fr) / abs(Fr)),
           m.counters())
     assert dl < 2e-6 and es < 1e-5 and abs(F.item() - Fr) / abs(Fr) < 1e-6
+
+
+@gpu
+def test_candidate_overflow_fallback(dev):
+    """Hundreds of near-identical components: every point has far more relevant pairs than the
+    sweep's per-point lists hold, so the statistics come from the exact rescan fallback."""
+    g = np.random.default_rng(31)
+    D, K, N = 6, 320, 700
+    X = (0.5 + g.normal(0, 0.05, (N, D))).astype(np.float32)
+    m0 = 0.5 + g.normal(0, 1e-4, (K, D))
+    pr = scenes.Prior(m0=m0, W0=np.eye(D) * 50.0, kappa0=1.0, nu0=D + 2.0, alpha0=1.0)
+    m = _model(dev, pr, N, "bf16x3", True)
+    lse, st = m.estep_stats(torch.from_numpy(X).to(dev))
+    torch.cuda.synchronize()
+    p = R.NW.from_prior(pr)
+    e = R.expectations(p)
+    ls = R.lse(X, p, e)
+    ref = R.stats(X, p, ls, e, scatter=False).packed()
+    dl = np.abs(lse.cpu().numpy() - ls).max()
+    es = _stat_err(ref, st.cpu().numpy(), D)
+    print("overflow case: max|dLSE| %.2e stats relerr %.2e" % (dl, es), m.counters())
+    assert dl < 2e-6 and es < 1e-9
