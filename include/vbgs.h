@@ -88,9 +88,13 @@ typedef struct {
                               point's running maximum (pass 1) or its LSE (pass 2) are
                               skipped. <= 0 selects ln(K) + ln(1e12). */
   int32_t n_split;         /* pass-2 point splits; 0 = automatic */
-  int32_t reserved0;
-  int64_t reserved[6];     /* must be zero */
+  int32_t proposal;        /* 1: allocate the learned candidate proposal (MFMA precisions, D <= 6) */
+  int32_t C;               /* candidates per point proposed by the network, 1..64 (default 32) */
+  int32_t train_batch;     /* largest training minibatch, 0..65536 (default 4096) */
+  int64_t reserved[5];     /* must be zero */
 } vbgs_params;
+
+#define VBGS_H 128         /* hidden width of the proposal network (= embedding width) */
 
 /* Fill *p with defaults for (D, K, n_max): kappa0 = 1, nu0 = D + 2, alpha0 = 1,
  * score_prec = VBGS_BF16X3, exact = 1, screen_margin = 0 (automatic). */
@@ -152,9 +156,9 @@ vbgs_status vbgs_set_params(vbgs_ctx* ctx, int32_t which, const double* alpha, c
 vbgs_status vbgs_sync_status(vbgs_ctx* ctx, void* stream);
 vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
 
-/* Synchronise `stream` and read host-side counters of the last E-step:
- * out[0] = pairs rescored exactly in pass 1, out[1] = in pass 2,
- * out[2] = number of points, out[3] = number of components. */
+/* Synchronise `stream` and read counters of the last E-step (exact MFMA mode):
+ * out[0] = pairs recorded by the screen sweep, out[1] = pairs kept for the statistics
+ * (within the margin of their point's LSE), out[2] = number of points, out[3] = K. */
 vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[4], void* stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each call.
@@ -163,9 +167,61 @@ vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[4], void* stream);
  * vbgs_timing(ctx, 1) creates the events (host-side objects, no device memory) and records
  * every later phase; 0 stops recording. vbgs_timing_read synchronises `stream`, writes the
  * summed duration in ms and the number of recorded launches of each phase, and clears them. */
-#define VBGS_NPHASE 8
+#define VBGS_NPHASE 8  /* phase 7: proposal network (forward, logits, top-C, audit) */
 vbgs_status vbgs_timing(vbgs_ctx* ctx, int32_t enable);
 vbgs_status vbgs_timing_read(vbgs_ctx* ctx, double ms[VBGS_NPHASE], int64_t counts[VBGS_NPHASE], void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned candidate proposal (needs params.proposal = 1). Not part of the paper's method:
+ * a network h2 = relu(W2 relu(W1 x' + b1) + b2), x' = (x - mu_in) * inv_s_in, with logits
+ * z_nk = h2_n . E_k + beta_k picks C candidate components per point; only those are scored
+ * exactly, and the responsibilities are renormalised over them. Trained on responsibilities
+ * of exact E-steps. Weights are FP32 row-major: W1 H x D, b1 H, W2 H x H, b2 H, E K x H,
+ * beta K, mu_in D, inv_s_in D (H = VBGS_H), all device pointers.
+ * ------------------------------------------------------------------------------------- */
+
+/* Copy weights into the state and reset the Adam moments and step count. */
+vbgs_status vbgs_proposal_set(vbgs_ctx* ctx, const float* W1, const float* b1, const float* W2, const float* b2,
+                              const float* E, const float* beta, const float* mu_in, const float* inv_s_in,
+                              void* stream);
+/* Copy the current weights out of the state. */
+vbgs_status vbgs_proposal_get(vbgs_ctx* ctx, float* W1, float* b1, float* W2, float* b2, float* E, float* beta,
+                              void* stream);
+
+/* E-step + statistics with candidates from the network (top-C of the logits, ties broken on the
+ * smaller component index), every candidate scored exactly in FP64, LSE and r over the candidates.
+ * Audit: the dense exact LSE of the n_audit points audit_idx (device int32, distinct, < N) gives
+ * each one's captured log-mass ln sum_{k in C_n} r_nk = LSE_C(n) - LSE(n) (nats). The frame falls
+ * back to the dense exact E-step when ln(mean exp(captured)) < logmass_bound or more than
+ * frac_bound of the audited points lie below logmass_bound; the decision is taken on the device
+ * and the dense kernels run only then (no host synchronisation). n_audit = 0 disables the audit.
+ * report (device, 4 FP64, or NULL): [fallback 0/1, ln mean captured mass, fraction below the
+ * bound, minimum captured log-mass]. Outputs as vbgs_estep_stats. */
+vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* ctx, const float* X, int64_t N, const int32_t* audit_idx,
+                                    int64_t n_audit, double logmass_bound, double frac_bound, double* lse_out,
+                                    double* stats_out, double* report, void* stream);
+
+/* Run the network on X (N points) and write each point's C candidates, ascending component
+ * index, to cand_out (device, N x C int32; -1 pads when K < C). Logits use BF16 operands with
+ * FP32 accumulation; ties at the C-th place are broken by the smaller component index. */
+vbgs_status vbgs_proposal_candidates(vbgs_ctx* ctx, const float* X, int64_t N, int32_t* cand_out, void* stream);
+
+/* After a vbgs_estep_stats (exact mode): training targets per point, the kept pairs of the
+ * exact E-step (at most 64), tk (device, N x 64 int32, -1 = empty) and their responsibilities
+ * tr (device, N x 64 FP32). N must equal the N of that E-step. */
+vbgs_status vbgs_export_targets(vbgs_ctx* ctx, int64_t N, int32_t* tk, float* tr, void* stream);
+
+/* One training step of the proposal on a minibatch: rows batch_idx (device int32, B of them) of
+ * the points X and of the targets (tk, tr as exported). Loss: mean over the batch of
+ * LSE_k(z_nk) - sum_j rbar_nj z_{n,k_j} with rbar the targets renormalised per point; the big
+ * products run on BF16 MFMA with FP32 accumulation, master weights FP32.
+ * apply = 1: Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8); apply = 0: only gradients.
+ * loss_out (device, 1 FP64) or NULL; grads_out (device FP32, the six trainable arrays W1, b1, W2,
+ * b2, E, beta concatenated) or NULL. Gradients of E and beta accumulate the sparse target term
+ * with FP32 atomics, so they are reproducible to rounding, not bitwise. */
+vbgs_status vbgs_proposal_train_step(vbgs_ctx* ctx, const float* X, const int32_t* tk, const float* tr,
+                                     const int32_t* batch_idx, int32_t B, float lr, int32_t apply,
+                                     double* loss_out, float* grads_out, void* stream);
 
 /* Last error message of this context ("" if none). Never NULL. */
 const char* vbgs_last_error(const vbgs_ctx* ctx);

@@ -11,7 +11,8 @@ VBGS_ABI_VERSION = 1
 STATUS = {0: "VBGS_OK", -1: "VBGS_ERR_ARG", -2: "VBGS_ERR_SHAPE", -3: "VBGS_ERR_HIP", -4: "VBGS_ERR_NOT_PD",
           -5: "VBGS_ERR_NONFINITE", -6: "VBGS_ERR_STATE", -7: "VBGS_ERR_UNSUPPORTED"}
 NPHASE = 8
-PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "reserved"]
+PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "proposal"]
+H = 128
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
 
@@ -19,8 +20,8 @@ class Params(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_int32), ("D", ctypes.c_int32), ("K", ctypes.c_int64),
                 ("n_max", ctypes.c_int64), ("kappa0", ctypes.c_double), ("nu0", ctypes.c_double),
                 ("alpha0", ctypes.c_double), ("score_prec", ctypes.c_int32), ("exact", ctypes.c_int32),
-                ("screen_margin", ctypes.c_double), ("n_split", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 6)]
+                ("screen_margin", ctypes.c_double), ("n_split", ctypes.c_int32), ("proposal", ctypes.c_int32),
+                ("C", ctypes.c_int32), ("train_batch", ctypes.c_int32), ("reserved", ctypes.c_int64 * 5)]
 
 
 _lib = None
@@ -52,6 +53,12 @@ def load():
         "vbgs_sync_status": (i32, [vp, vp]),
         "vbgs_clear_flags": (i32, [vp, vp]),
         "vbgs_counters": (i32, [vp, ctypes.POINTER(i64), vp]),
+        "vbgs_proposal_set": (i32, [vp] + [vp] * 8 + [vp]),
+        "vbgs_proposal_get": (i32, [vp] + [vp] * 6 + [vp]),
+        "vbgs_estep_stats_pruned": (i32, [vp, vp, i64, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]),
+        "vbgs_export_targets": (i32, [vp, i64, vp, vp, vp]),
+        "vbgs_proposal_candidates": (i32, [vp, vp, i64, vp, vp]),
+        "vbgs_proposal_train_step": (i32, [vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, vp, vp, vp]),
         "vbgs_timing": (i32, [vp, i32]),
         "vbgs_timing_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp]),
         "vbgs_last_error": (ctypes.c_char_p, [vp]),

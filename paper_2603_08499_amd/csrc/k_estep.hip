@@ -105,35 +105,7 @@ __device__ __forceinline__ f32x4 mfma_scores(const Opnd<P>& A, const Opnd<P>& B)
   return acc;
 }
 
-struct EArgs {
-  const float* X;             // raw points N x D (FP32)
-  const float* phi32;         // N x 32
-  const uint16_t* phih;       // N x 32
-  const uint16_t* phil;       // N x 32
-  const float* nphi;          // N
-  const double* direct;       // Kpad x dts
-  const float* c32;           // Kpad x 32
-  const uint16_t* ch;         // Kpad x 32
-  const uint16_t* cl;         // Kpad x 32
-  const float* nc;            // Kpad
-  double* lse2;               // N (log2 units)
-  double* lse_part;           // pass-1 workgroups
-  double* lse_out;            // N (nats) or null
-  double* spart;              // nsplit x Kpad x 32
-  int32_t* cand_k;            // exact sweep: N x 4 x CS component indices
-  float* cand_s;              // N x 4 x CS exact scores (log2 units, rounded to FP32)
-  int32_t* cand_n;            // N x 4 list lengths, -1 = overflowed point
-  int32_t* over_list;         // overflowed points
-  unsigned long long* fx;     // Kpad x 32 x {lo, hi}: 128-bit fixed-point statistics (overflowed points)
-  int32_t* ccount;            // Kpad + 1: kept pairs per component
-  int32_t* coffset;           // Kpad + 1: exclusive scan of ccount
-  int32_t* ccursor;           // Kpad + 1: scatter cursors
-  int32_t* ent_n;             // kept pairs grouped by component: point index
-  FrameInfo* frame;
-  int64_t N, K, Kpad;
-  int D, dts, nsplit;
-  float T2, eps;
-};
+
 
 // online log-sum-exp (log2 units) of exactly rescored pairs, FP64
 __device__ __forceinline__ void online_add(double& m, double& l, double s) {
@@ -244,6 +216,7 @@ template <int P, bool EXACT>
 __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
   __shared__ CTile<P> T[2];
   __shared__ double red[256];
+  if (EXACT && a.gate && a.gate[0] == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
   const int64_t p0 = (int64_t)blockIdx.x * P1_PTS + w * (P1_PB * 16);
 
@@ -496,7 +469,8 @@ __device__ __forceinline__ void fx_pair(unsigned long long* __restrict__ fx, int
     for (int j = i; j < DT; ++j, ++o) fx_add(row + 2 * o, r * u[i] * u[j]);
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+__global__ void k_zero_u64(unsigned long long* p, int64_t n, const int32_t* gate) {
+  if (gate && gate[0] == 0) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0ull;
 }
@@ -505,9 +479,11 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
 template <int DT>
 __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
   __shared__ double red[256];
+  if (a.gate && a.gate[0] == 0) return;
   const int tid = threadIdx.x;
   const int64_t p = (int64_t)blockIdx.x * 256 + tid;
   double L2 = 0.0;
+  unsigned kept = 0;
   if (p < a.N) {
     if (a.cand_n[p * 4] < 0) {
       L2 = a.lse2[p];  // overflowed point: full rescan by k_over_lse
@@ -532,14 +508,19 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
         const int cnt = a.cand_n[p * 4 + g];
         for (int j = 0; j < cnt; ++j) {
           const int64_t e = (p * 4 + g) * CS + j;
-          if (a.cand_s[e] >= thr) atomicAdd(&a.ccount[a.cand_k[e]], 1);
-          else a.cand_k[e] = -1;
+          if (a.cand_s[e] >= thr) {
+            atomicAdd(&a.ccount[a.cand_k[e]], 1);
+            ++kept;
+          } else {
+            a.cand_k[e] = -1;
+          }
         }
       }
     }
     if (a.lse_out) a.lse_out[p] = L2 * LN2;
   }
   red[tid] = L2;
+  count_refined(&a.frame->refined2, kept);
   __syncthreads();
   if (tid == 0) {
     double sacc = 0.0;
@@ -552,6 +533,7 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
 template <int DT>
 __global__ __launch_bounds__(256) void k_over_lse(const EArgs a) {
   __shared__ double sm[256], sl[256];
+  if (a.gate && a.gate[0] == 0) return;
   const int n_over = a.frame->n_over;
   for (int i = blockIdx.x; i < n_over; i += gridDim.x) {
     const int64_t p = a.over_list[i];
@@ -702,7 +684,8 @@ __global__ __launch_bounds__(128) void k_comp_stats(const EArgs a) {
       out[o] = ((double)acc[o].hi + (double)acc[o].lo * 5.42101086242752217e-20) * a.frame->s[i] * a.frame->s[j];
 }
 
-__global__ void k_zero_i32(int32_t* p, int64_t n) {
+__global__ void k_zero_i32(int32_t* p, int64_t n, const int32_t* gate) {
+  if (gate && gate[0] == 0) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
 }
@@ -844,7 +827,81 @@ __global__ void k_fold(const double* __restrict__ spart, int nsplit, int64_t Kpa
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static EArgs make_args(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out) {
+// exact mode: screen sweep recording candidates, then the exact LSE (overflowed points first);
+// every kernel honours a.gate
+hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  const int64_t Kp1 = a.Kpad + 1;
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, a.gate);
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1, a.gate);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, a.gate);
+  const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
+  if (prec == VBGS_FP32) hipLaunchKernelGGL((k_pass1<VBGS_FP32, true>), grid, dim3(256), 0, s, a);
+  else if (prec == VBGS_BF16) hipLaunchKernelGGL((k_pass1<VBGS_BF16, true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_pass1<VBGS_BF16X3, true>), grid, dim3(256), 0, s, a);
+  const dim3 gp((unsigned)((N + 255) / 256));
+  switch (D) {
+#define VB_LSE(DD)                                                    \
+  case DD:                                                            \
+    hipLaunchKernelGGL(k_over_lse<DD>, dim3(64), dim3(256), 0, s, a); \
+    hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, a);      \
+    break;
+    VB_LSE(1) VB_LSE(2) VB_LSE(3) VB_LSE(4) VB_LSE(5) VB_LSE(6)
+#undef VB_LSE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// exact LSE of externally provided candidate lists (counts are zeroed here, ungated)
+hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s) {
+  const int64_t Kp1 = a.Kpad + 1;
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, nullptr);
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1, nullptr);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, nullptr);
+  if (N <= 0) return hipGetLastError();
+  EArgs u = a;
+  u.gate = nullptr;
+  const dim3 gp((unsigned)((N + 255) / 256));
+  switch (D) {
+#define VB_PL(DD) \
+  case DD:        \
+    hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, u); break;
+    VB_PL(1) VB_PL(2) VB_PL(3) VB_PL(4) VB_PL(5) VB_PL(6)
+#undef VB_PL
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// statistics of the kept candidates: overflowed points (atomics), transpose, per-component sums
+hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) {
+  if (N > 0) {
+    const dim3 gp((unsigned)((N + 255) / 256));
+    const dim3 gk((unsigned)((a.K + 127) / 128));
+    switch (D) {
+#define VB_ST(DD)                                                                         \
+  case DD:                                                                                \
+    hipLaunchKernelGGL(k_over_stats<DD>, dim3(64), dim3(256), 0, s, a);                   \
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, a.ccount, a.coffset, a.K); \
+    hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                          \
+    hipLaunchKernelGGL(k_comp_stats<DD>, gk, dim3(128), 0, s, a);                         \
+    break;
+      VB_ST(1) VB_ST(2) VB_ST(3) VB_ST(4) VB_ST(5) VB_ST(6)
+#undef VB_ST
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(a.spart),
+                       a.Kpad * FP, nullptr);
+  }
+  return hipGetLastError();
+}
+
+EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out) {
   const Layout& L = *d.L;
   EArgs a;
   a.X = X;
@@ -871,6 +928,7 @@ static EArgs make_args(const DevPtrs& d, const EstepCfg& c, const float* X, int6
   a.ccursor = d.at<int32_t>(L.ccursor);
   a.ent_n = d.at<int32_t>(L.ent_n);
   a.frame = d.frame();
+  a.gate = c.gate;
   a.N = N;
   a.K = d.K;
   a.Kpad = L.Kpad;
@@ -885,7 +943,7 @@ static EArgs make_args(const DevPtrs& d, const EstepCfg& c, const float* X, int6
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
                         hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  const EArgs a = make_args(d, c, X, N, lse_out);
+  const EArgs a = make_eargs(d, c, X, N, lse_out);
   if (c.prec == VBGS_FP64) {
     const dim3 grid((unsigned)((N + 255) / 256));
     switch (d.D) {
@@ -907,32 +965,13 @@ hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int
     else VB_P1(VBGS_BF16X3, false);
     return hipGetLastError();
   }
-  // exact: screen sweep recording candidates, then exact LSE (overflowed points first)
-  const int64_t Kp1 = d.L->Kpad + 1;
-  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1);
-  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1);
-  hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, d.L->Kpad * FP * 2);
-  if (c.prec == VBGS_FP32) VB_P1(VBGS_FP32, true);
-  else if (c.prec == VBGS_BF16) VB_P1(VBGS_BF16, true);
-  else VB_P1(VBGS_BF16X3, true);
-  const dim3 gp((unsigned)((N + 255) / 256));
-  switch (d.D) {
-#define VB_LSE(DD)                                                           \
-  case DD:                                                                   \
-    hipLaunchKernelGGL(k_over_lse<DD>, dim3(64), dim3(256), 0, s, a);        \
-    hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, a);             \
-    break;
-    VB_LSE(1) VB_LSE(2) VB_LSE(3) VB_LSE(4) VB_LSE(5) VB_LSE(6)
-#undef VB_LSE
-    default:
-      return hipErrorInvalidValue;
-  }
+  return launch_exact_sweep(a, c.prec, d.D, N, s);
 #undef VB_P1
   return hipGetLastError();
 }
 
 hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s) {
-  const EArgs a = make_args(d, c, X, N, nullptr);
+  const EArgs a = make_eargs(d, c, X, N, nullptr);
   if (c.prec == VBGS_FP64) {
     const dim3 grid((unsigned)((d.K + 255) / 256), (unsigned)c.nsplit);
     switch (d.D) {
@@ -946,30 +985,7 @@ hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int
     }
     return hipGetLastError();
   }
-  if (c.exact) {
-    // statistics of the kept candidates: overflowed points (atomics), transpose, per-component sums
-    if (N > 0) {
-      const dim3 gp((unsigned)((N + 255) / 256));
-      const dim3 gk((unsigned)((d.K + 127) / 128));
-      switch (d.D) {
-#define VB_ST(DD)                                                                     \
-  case DD:                                                                            \
-    hipLaunchKernelGGL(k_over_stats<DD>, dim3(64), dim3(256), 0, s, a);               \
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, a.ccount, a.coffset, d.K); \
-    hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                      \
-    hipLaunchKernelGGL(k_comp_stats<DD>, gk, dim3(128), 0, s, a);                     \
-    break;
-        VB_ST(1) VB_ST(2) VB_ST(3) VB_ST(4) VB_ST(5) VB_ST(6)
-#undef VB_ST
-        default:
-          return hipErrorInvalidValue;
-      }
-    } else {
-      hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(a.spart),
-                         d.L->Kpad * FP);
-    }
-    return hipGetLastError();
-  }
+  if (c.exact) return launch_sparse_stats(a, d.D, N, s);
   const dim3 grid((unsigned)(d.L->Kpad / CT), (unsigned)c.nsplit);
 #define VB_P2(PP) hipLaunchKernelGGL((k_pass2<PP>), grid, dim3(256), 0, s, a)
   if (c.prec == VBGS_FP32) {

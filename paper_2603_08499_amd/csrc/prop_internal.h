@@ -1,0 +1,67 @@
+// Internal definitions of the learned candidate proposal.
+#pragma once
+
+#include <algorithm>
+
+#include "vbgs_internal.h"
+
+namespace vbgs {
+
+typedef EArgs EArgsLite;
+
+// Offsets of the six trainable arrays inside the flat FP32 parameter block (and its gradient
+// and Adam moment copies): W1 (H x D), b1 (H), W2 (H x H), b2 (H), E (K x H), beta (K).
+struct PropOffsets {
+  int64_t W1, b1, W2, b2, E, beta, n;
+  PropOffsets(int D, int64_t K) {
+    W1 = 0;
+    b1 = (int64_t)VBGS_H * D;
+    W2 = b1 + VBGS_H;
+    b2 = W2 + (int64_t)VBGS_H * VBGS_H;
+    E = b2 + VBGS_H;
+    beta = E + K * VBGS_H;
+    n = beta + K;
+  }
+};
+
+struct PArgs {
+  int64_t K, Kpad, Bpad, n_train;
+  int D, C;
+  // weights (state)
+  float* W;  // flat trainable block
+  const float *W1, *b1, *W2, *b2, *E, *beta, *mu_in, *inv_s_in;
+  float *m1, *m2;
+  double* step;
+  // MFMA operand copies (workspace)
+  uint16_t *Ebf, *EbfT;
+  float *betap, *W2T;
+  // pruned E-step
+  uint16_t* h2b;
+  float* tz;
+  int32_t *tk, *tcnt;
+  // training
+  float *th1, *th2, *txs, *tlse, *tdh2, *tdp1;
+  uint16_t *th2b, *th2T;
+  double* tloss;
+  float *grads, *gW1, *gb1, *gW2, *gb2, *gE, *gbeta;
+};
+
+struct MlpOut {
+  int64_t npad;  // rows written (rows >= n are zero)
+  float *h1, *h2, *xs;
+  uint16_t *h2b, *h2T;
+};
+
+hipError_t launch_prop_prepare(const PArgs& a, hipStream_t s);
+hipError_t launch_mlp_fwd(const PArgs& a, const float* X, const int32_t* idx, int64_t n, const MlpOut& o,
+                          hipStream_t s);
+hipError_t launch_topc(const PArgs& a, const EArgsLite& e, int64_t N, hipStream_t s);
+hipError_t launch_audit(const EArgsLite& e, int D, const int32_t* idx, int64_t n, double* aud, const double* lse2,
+                        double bound, double frac, int32_t* gate, double* report, hipStream_t s);
+hipError_t launch_topc_export(const EArgsLite& e, int64_t N, int C, int32_t* out, hipStream_t s);
+hipError_t launch_export_targets(const EArgsLite& e, int64_t N, int32_t* tk, float* tr, hipStream_t s);
+hipError_t launch_train(const PArgs& a, const float* X, const int32_t* tk, const float* tr, const int32_t* bidx,
+                        int64_t B, float lr, int apply, double* loss_out, float* grads_out, hipStream_t s);
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t s);
+
+}  // namespace vbgs

@@ -7,7 +7,7 @@
 #include <new>
 #include <string>
 
-#include "vbgs_internal.h"
+#include "prop_internal.h"
 
 using namespace vbgs;
 
@@ -26,6 +26,8 @@ struct vbgs_ctx {
   vbgs_params p;
   bool timing;
   bool timers_made;
+  bool prop_ready;     // the state holds network weights
+  bool prop_prepared;  // the workspace holds their MFMA operand copies
   PhaseTimer tm[VBGS_NPHASE];
   Layout L;
   void* state;
@@ -106,8 +108,20 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "n_split must be in 0..64";
     return VBGS_ERR_ARG;
   }
-  for (int i = 0; i < 6; ++i)
-    if (p->reserved[i] != 0 || p->reserved0 != 0) {
+  if (p->proposal != 0 && p->proposal != 1) {
+    if (why) *why = "proposal must be 0 or 1";
+    return VBGS_ERR_ARG;
+  }
+  if (p->proposal && (p->score_prec == VBGS_FP64 || p->exact != 1 || p->D > 6)) {
+    if (why) *why = "the proposal needs an MFMA precision with exact = 1 and D <= 6";
+    return VBGS_ERR_UNSUPPORTED;
+  }
+  if (p->C < 0 || p->C > 64 || p->train_batch < 0 || p->train_batch > 65536) {
+    if (why) *why = "C must be in 0..64 and train_batch in 0..65536 (0 = default)";
+    return VBGS_ERR_ARG;
+  }
+  for (int i = 0; i < 5; ++i)
+    if (p->reserved[i] != 0) {
       if (why) *why = "reserved fields must be zero";
       return VBGS_ERR_ARG;
     }
@@ -211,7 +225,44 @@ Layout make_layout(const vbgs_params& p) {
   L.coffset = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
   L.ccursor = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
   L.ent_n = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
+  // learned proposal
+  const bool pr = p.proposal == 1;
+  const int C = p.C > 0 ? p.C : 32;
+  const int64_t Bt = p.train_batch > 0 ? p.train_batch : 4096;
+  L.Bpad_max = (Bt + 63) / 64 * 64;
+  const size_t H = VBGS_H;
+  L.p_Ebf = take(pr ? (size_t)L.Kpad * H * 2 : 0);
+  L.p_EbfT = take(pr ? (size_t)L.Kpad * H * 2 : 0);
+  L.p_betap = take(pr ? (size_t)L.Kpad * 4 : 0);
+  L.p_W2T = take(pr ? H * H * 4 : 0);
+  L.p_h2b = take(pr ? (size_t)n * H * 2 : 0);
+  L.p_tz = take(pr ? (size_t)n * 4 * 2 * C * 4 : 0);
+  L.p_tk = take(pr ? (size_t)n * 4 * 2 * C * 4 : 0);
+  L.p_tcnt = take(pr ? (size_t)n * 4 * 4 : 0);
+  L.p_aud = take(pr ? (size_t)n * 8 : 0);
+  L.p_gate = take(pr ? 64 : 0);
+  const size_t Bp = (size_t)L.Bpad_max;
+  L.p_th1 = take(pr ? Bp * H * 4 : 0);
+  L.p_th2 = take(pr ? Bp * H * 4 : 0);
+  L.p_txs = take(pr ? Bp * MAXD * 4 : 0);
+  L.p_tlse = take(pr ? Bp * 4 : 0);
+  L.p_tdh2 = take(pr ? Bp * H * 4 : 0);
+  L.p_tdp1 = take(pr ? Bp * H * 4 : 0);
+  L.p_th2b = take(pr ? Bp * H * 2 : 0);
+  L.p_th2T = take(pr ? Bp * H * 2 : 0);
+  L.p_tloss = take(pr ? Bp * 8 : 0);
+  const PropOffsets po(p.D, p.K);
+  L.p_grads = take(pr ? (size_t)po.n * 4 : 0);
   L.total = o;
+  // state: header, frame prior, posterior, then the proposal block
+  size_t so = sizeof(StateHeader) + (size_t)2 * p.K * REC * 8;
+  L.s_W = so;
+  L.s_mu = so + (size_t)po.n * 4;
+  L.s_is = L.s_mu + MAXD * 4;
+  L.s_m1 = up(L.s_is + MAXD * 4);
+  L.s_m2 = up(L.s_m1 + (size_t)po.n * 4);
+  L.s_step = up(L.s_m2 + (size_t)po.n * 4);
+  L.state_total = pr ? L.s_step + 8 : so;
   return L;
 }
 }  // namespace vbgs
@@ -231,6 +282,8 @@ vbgs_status vbgs_default_params(vbgs_params* p, int32_t D, int64_t K, int64_t n_
   p->score_prec = D <= 6 ? VBGS_BF16X3 : VBGS_FP64;
   p->exact = 1;
   p->screen_margin = 0.0;
+  p->C = 32;
+  p->train_batch = 4096;
   return VBGS_OK;
 }
 
@@ -238,8 +291,9 @@ vbgs_status vbgs_query_sizes(const vbgs_params* p, size_t* state_bytes, size_t* 
   const vbgs_status st = check_params(p, nullptr);
   if (st != VBGS_OK) return st;
   if (!state_bytes || !workspace_bytes) return VBGS_ERR_ARG;
-  *state_bytes = sizeof(StateHeader) + (size_t)2 * p->K * REC * 8;
-  *workspace_bytes = make_layout(*p).total;
+  const Layout L = make_layout(*p);
+  *state_bytes = L.state_total;
+  *workspace_bytes = L.total;
   return VBGS_OK;
 }
 
@@ -256,6 +310,8 @@ static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   c->have_stats = false;
   c->timing = false;
   c->timers_made = false;
+  c->prop_ready = false;
+  c->prop_prepared = false;
   const int auto_ns = p->score_prec == VBGS_FP64 ? auto_split_direct(p->K) : auto_split_mfma(c->L.Kpad);
   c->nsplit = p->n_split > 0 ? p->n_split : auto_ns;
   const double T = p->screen_margin > 0 ? p->screen_margin : log((double)p->K) + log(1e12);
@@ -325,6 +381,7 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
   if (!out || !state || !workspace || !aligned(state) || !aligned(workspace)) return VBGS_ERR_ARG;
   vbgs_ctx* c = new_ctx(p, state, workspace);
   if (!c) return VBGS_ERR_ARG;
+  c->prop_ready = p->proposal == 1;  // a proposal state carries its weights
   *out = c;
   return VBGS_OK;
 }
@@ -450,6 +507,221 @@ vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[4], void* stream) {
   out[2] = c->last_N;
   out[3] = c->p.K;
   return VBGS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// learned proposal
+// ------------------------------------------------------------------------------------------
+static PArgs make_pargs(vbgs_ctx* c) {
+  const Layout& L = c->L;
+  char* ws = (char*)c->ws;
+  char* st = (char*)c->state;
+  const PropOffsets o(c->p.D, c->p.K);
+  PArgs a{};
+  a.K = c->p.K;
+  a.Kpad = L.Kpad;
+  a.Bpad = L.Bpad_max;
+  a.n_train = o.n;
+  a.D = c->p.D;
+  a.C = c->p.C > 0 ? c->p.C : 32;
+  a.W = reinterpret_cast<float*>(st + L.s_W);
+  a.W1 = a.W + o.W1;
+  a.b1 = a.W + o.b1;
+  a.W2 = a.W + o.W2;
+  a.b2 = a.W + o.b2;
+  a.E = a.W + o.E;
+  a.beta = a.W + o.beta;
+  a.mu_in = reinterpret_cast<float*>(st + L.s_mu);
+  a.inv_s_in = reinterpret_cast<float*>(st + L.s_is);
+  a.m1 = reinterpret_cast<float*>(st + L.s_m1);
+  a.m2 = reinterpret_cast<float*>(st + L.s_m2);
+  a.step = reinterpret_cast<double*>(st + L.s_step);
+  a.Ebf = reinterpret_cast<uint16_t*>(ws + L.p_Ebf);
+  a.EbfT = reinterpret_cast<uint16_t*>(ws + L.p_EbfT);
+  a.betap = reinterpret_cast<float*>(ws + L.p_betap);
+  a.W2T = reinterpret_cast<float*>(ws + L.p_W2T);
+  a.h2b = reinterpret_cast<uint16_t*>(ws + L.p_h2b);
+  a.tz = reinterpret_cast<float*>(ws + L.p_tz);
+  a.tk = reinterpret_cast<int32_t*>(ws + L.p_tk);
+  a.tcnt = reinterpret_cast<int32_t*>(ws + L.p_tcnt);
+  a.th1 = reinterpret_cast<float*>(ws + L.p_th1);
+  a.th2 = reinterpret_cast<float*>(ws + L.p_th2);
+  a.txs = reinterpret_cast<float*>(ws + L.p_txs);
+  a.tlse = reinterpret_cast<float*>(ws + L.p_tlse);
+  a.tdh2 = reinterpret_cast<float*>(ws + L.p_tdh2);
+  a.tdp1 = reinterpret_cast<float*>(ws + L.p_tdp1);
+  a.th2b = reinterpret_cast<uint16_t*>(ws + L.p_th2b);
+  a.th2T = reinterpret_cast<uint16_t*>(ws + L.p_th2T);
+  a.tloss = reinterpret_cast<double*>(ws + L.p_tloss);
+  a.grads = reinterpret_cast<float*>(ws + L.p_grads);
+  a.gW1 = a.grads + o.W1;
+  a.gb1 = a.grads + o.b1;
+  a.gW2 = a.grads + o.W2;
+  a.gb2 = a.grads + o.b2;
+  a.gE = a.grads + o.E;
+  a.gbeta = a.grads + o.beta;
+  return a;
+}
+
+vbgs_status vbgs_proposal_set(vbgs_ctx* c, const float* W1, const float* b1, const float* W2, const float* b2,
+                              const float* E, const float* beta, const float* mu_in, const float* inv_s_in,
+                              void* stream) {
+  if (!c || !W1 || !b1 || !W2 || !b2 || !E || !beta || !mu_in || !inv_s_in) return VBGS_ERR_ARG;
+  if (!c->p.proposal) return fail(c, VBGS_ERR_STATE, "params.proposal is 0");
+  PArgs a = make_pargs(c);
+  const PropOffsets o(c->p.D, c->p.K);
+  const hipStream_t s = S(stream);
+  const int64_t H = VBGS_H, D = c->p.D, K = c->p.K;
+  hipError_t e = hipMemcpyAsync(a.W + o.W1, W1, H * D * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(a.W + o.b1, b1, H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(a.W + o.W2, W2, H * H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(a.W + o.b2, b2, H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(a.W + o.E, E, K * H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(a.W + o.beta, beta, K * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_zero_f32((float*)a.mu_in, 2 * MAXD, s);
+  if (e == hipSuccess) e = hipMemcpyAsync((float*)a.mu_in, mu_in, D * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync((float*)a.inv_s_in, inv_s_in, D * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_zero_f32(a.m1, o.n, s);
+  if (e == hipSuccess) e = launch_zero_f32(a.m2, o.n, s);
+  if (e == hipSuccess) e = launch_zero_f32(reinterpret_cast<float*>(a.step), 2, s);
+  if (e == hipSuccess) e = launch_prop_prepare(a, s);
+  if (e != hipSuccess) return hipfail(c, e, "proposal_set");
+  c->prop_ready = true;
+  c->prop_prepared = true;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_proposal_get(vbgs_ctx* c, float* W1, float* b1, float* W2, float* b2, float* E, float* beta,
+                              void* stream) {
+  if (!c || !W1 || !b1 || !W2 || !b2 || !E || !beta) return VBGS_ERR_ARG;
+  if (!c->p.proposal) return fail(c, VBGS_ERR_STATE, "params.proposal is 0");
+  PArgs a = make_pargs(c);
+  const PropOffsets o(c->p.D, c->p.K);
+  const hipStream_t s = S(stream);
+  const int64_t H = VBGS_H, D = c->p.D, K = c->p.K;
+  hipError_t e = hipMemcpyAsync(W1, a.W + o.W1, H * D * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b1, a.W + o.b1, H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(W2, a.W + o.W2, H * H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b2, a.W + o.b2, H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(E, a.W + o.E, K * H * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(beta, a.W + o.beta, K * 4, hipMemcpyDeviceToDevice, s);
+  return hipfail(c, e, "proposal_get");
+}
+
+vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* c, const float* X, int64_t N, const int32_t* audit_idx, int64_t n_audit,
+                                    double logmass_bound, double frac_bound, double* lse_out, double* stats_out,
+                                    double* report, void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  if (!c->p.proposal || !c->prop_ready) return fail(c, VBGS_ERR_STATE, "the proposal has no weights (vbgs_proposal_set)");
+  if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+  if ((N > 0 && !X) || n_audit < 0 || n_audit > N || (n_audit > 0 && !audit_idx))
+    return fail(c, VBGS_ERR_ARG, "bad X / audit arguments");
+  if (!isfinite(logmass_bound) || !(frac_bound >= 0.0)) return fail(c, VBGS_ERR_ARG, "bad bounds");
+  const hipStream_t s = S(stream);
+  const DevPtrs d = c->dev();
+  EstepCfg cfg{c->p.score_prec, 1, c->T2, 1};
+  hipError_t e;
+  {
+    Phase ph(c, 0, s);
+    e = launch_frame_prep(d, X, N, s);
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 1, s);
+    e = launch_coeffs(d, s);
+  }
+  PArgs pa = make_pargs(c);
+  if (e == hipSuccess && !c->prop_prepared) {
+    e = launch_prop_prepare(pa, s);
+    c->prop_prepared = e == hipSuccess;
+  }
+  EArgs ea = make_eargs(d, cfg, X, N, lse_out);
+  int32_t* gate = reinterpret_cast<int32_t*>((char*)c->ws + c->L.p_gate);
+  if (e == hipSuccess) {
+    Phase ph(c, 7, s);
+    MlpOut o{};
+    o.npad = N;
+    o.h2b = pa.h2b;
+    e = launch_mlp_fwd(pa, X, nullptr, N, o, s);
+    if (e == hipSuccess) e = launch_topc(pa, ea, N, s);
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 2, s);
+    e = launch_point_lse(ea, c->p.D, N, s);  // exact scores of the candidates, LSE over them
+    if (e == hipSuccess)
+      e = launch_audit(ea, c->p.D, audit_idx, n_audit, reinterpret_cast<double*>((char*)c->ws + c->L.p_aud),
+                       ea.lse2, logmass_bound, frac_bound, gate, report, s);
+    if (e == hipSuccess) {  // dense exact E-step, executed only when the audit failed
+      EArgs eg = ea;
+      eg.gate = gate;
+      e = launch_exact_sweep(eg, c->p.score_prec, c->p.D, N, s);
+    }
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 3, s);
+    e = launch_sparse_stats(ea, c->p.D, N, s);
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 4, s);
+    EstepCfg fc = cfg;
+    e = launch_fold(d, fc, stats_out, s);
+  }
+  if (e != hipSuccess) return hipfail(c, e, "estep_stats_pruned");
+  c->last_N = N;
+  c->lse_version = c->post_version;
+  c->have_stats = true;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_proposal_candidates(vbgs_ctx* c, const float* X, int64_t N, int32_t* cand_out, void* stream) {
+  if (!c || !cand_out) return VBGS_ERR_ARG;
+  if (!c->p.proposal || !c->prop_ready) return fail(c, VBGS_ERR_STATE, "the proposal has no weights");
+  if (N < 0 || N > c->p.n_max || (N > 0 && !X)) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+  const hipStream_t s = S(stream);
+  PArgs pa = make_pargs(c);
+  hipError_t e = hipSuccess;
+  if (!c->prop_prepared) {
+    e = launch_prop_prepare(pa, s);
+    c->prop_prepared = e == hipSuccess;
+  }
+  EstepCfg cfg{c->p.score_prec, 1, c->T2, 1};
+  const EArgs ea = make_eargs(c->dev(), cfg, X, N, nullptr);
+  MlpOut o{};
+  o.npad = N;
+  o.h2b = pa.h2b;
+  if (e == hipSuccess) e = launch_mlp_fwd(pa, X, nullptr, N, o, s);
+  if (e == hipSuccess) e = launch_topc(pa, ea, N, s);
+  if (e == hipSuccess) e = launch_topc_export(ea, N, pa.C, cand_out, s);
+  c->have_stats = false;  // the candidate lists no longer belong to the last E-step
+  return hipfail(c, e, "proposal_candidates");
+}
+
+vbgs_status vbgs_export_targets(vbgs_ctx* c, int64_t N, int32_t* tk, float* tr, void* stream) {
+  if (!c || !tk || !tr) return VBGS_ERR_ARG;
+  if (c->p.score_prec == VBGS_FP64 || !c->p.exact) return fail(c, VBGS_ERR_UNSUPPORTED, "needs the exact MFMA mode");
+  if (!c->have_stats || N != c->last_N) return fail(c, VBGS_ERR_STATE, "N must match the last E-step");
+  EstepCfg cfg{c->p.score_prec, 1, c->T2, 1};
+  const EArgs ea = make_eargs(c->dev(), cfg, nullptr, N, nullptr);
+  return hipfail(c, launch_export_targets(ea, N, tk, tr, S(stream)), "export_targets");
+}
+
+vbgs_status vbgs_proposal_train_step(vbgs_ctx* c, const float* X, const int32_t* tk, const float* tr,
+                                     const int32_t* batch_idx, int32_t B, float lr, int32_t apply, double* loss_out,
+                                     float* grads_out, void* stream) {
+  if (!c || !X || !tk || !tr || !batch_idx) return VBGS_ERR_ARG;
+  if (!c->p.proposal || !c->prop_ready) return fail(c, VBGS_ERR_STATE, "the proposal has no weights");
+  const int64_t Bt = c->p.train_batch > 0 ? c->p.train_batch : 4096;
+  if (B < 1 || B > Bt) return fail(c, VBGS_ERR_SHAPE, "B outside 1..train_batch");
+  if ((apply != 0 && apply != 1) || !(lr >= 0.0f)) return fail(c, VBGS_ERR_ARG, "bad apply / lr");
+  PArgs a = make_pargs(c);
+  if (!c->prop_prepared) {
+    const hipError_t e = launch_prop_prepare(a, S(stream));
+    if (e != hipSuccess) return hipfail(c, e, "proposal_prepare");
+    c->prop_prepared = true;
+  }
+  a.Bpad = ((int64_t)B + 63) / 64 * 64;
+  Phase ph(c, 7, S(stream));
+  return hipfail(c, launch_train(a, X, tk, tr, batch_idx, B, lr, apply, loss_out, grads_out, S(stream)),
+                 "proposal_train_step");
 }
 
 vbgs_status vbgs_timing(vbgs_ctx* c, int32_t enable) {

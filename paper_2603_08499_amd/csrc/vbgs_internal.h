@@ -55,6 +55,12 @@ struct Layout {
       spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ccursor, ent_n, total;
   int64_t Kpad, n_lse_part;
   int nsplit_max;
+  // learned proposal (workspace)
+  size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
+      p_tdh2, p_tdp1, p_th2b, p_th2T, p_tloss, p_grads;
+  int64_t Bpad_max;
+  // learned proposal (state, byte offsets from the start of the state buffer)
+  size_t s_W, s_mu, s_is, s_m1, s_m2, s_step, state_total;
 };
 
 // State buffer: a header followed by the frame-prior and posterior records.
@@ -217,10 +223,47 @@ struct EstepCfg {
   int exact;     // 1: screen + exact rescoring
   float T2;      // screen margin in log2 units
   int nsplit;    // pass-2 point splits
+  const int32_t* gate = nullptr;  // device flag gating the exact dense kernels (proposal fallback)
 };
+
+struct EArgs {
+  const float* X;             // raw points N x D (FP32)
+  const float* phi32;         // N x 32
+  const uint16_t* phih;       // N x 32
+  const uint16_t* phil;       // N x 32
+  const float* nphi;          // N
+  const double* direct;       // Kpad x dts
+  const float* c32;           // Kpad x 32
+  const uint16_t* ch;         // Kpad x 32
+  const uint16_t* cl;         // Kpad x 32
+  const float* nc;            // Kpad
+  double* lse2;               // N (log2 units)
+  double* lse_part;           // pass-1 workgroups
+  double* lse_out;            // N (nats) or null
+  double* spart;              // nsplit x Kpad x 32
+  int32_t* cand_k;            // exact sweep: N x 4 x CS component indices
+  float* cand_s;              // N x 4 x CS exact scores (log2 units, rounded to FP32)
+  int32_t* cand_n;            // N x 4 list lengths, -1 = overflowed point
+  int32_t* over_list;         // overflowed points
+  unsigned long long* fx;     // Kpad x 32 x {lo, hi}: 128-bit fixed-point statistics (overflowed points)
+  int32_t* ccount;            // Kpad + 1: kept pairs per component
+  int32_t* coffset;           // Kpad + 1: exclusive scan of ccount
+  int32_t* ccursor;           // Kpad + 1: scatter cursors
+  int32_t* ent_n;             // kept pairs grouped by component: point index
+  FrameInfo* frame;
+  const int32_t* gate;        // when set, the exact dense kernels run only if gate[0] != 0
+  int64_t N, K, Kpad;
+  int D, dts, nsplit;
+  float T2, eps;
+};
+EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out);
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
                         hipStream_t s);
 hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s);
 hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, hipStream_t s);
+// exact statistics from candidate lists (transpose + per-component sums) and exact per-point LSE
+hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s);
+hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s);
+hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s);
 
 }  // namespace vbgs

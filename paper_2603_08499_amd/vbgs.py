@@ -29,7 +29,7 @@ def _stream(s=None):
 
 
 def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x3", exact=True,
-                screen_margin=0.0, n_split=0):
+                screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096):
     p = _lib.Params()
     L = _lib.load()
     st = L.vbgs_default_params(ctypes.byref(p), int(D), int(K), int(n_max))
@@ -42,6 +42,9 @@ def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x
     p.exact = 1 if exact else 0
     p.screen_margin = float(screen_margin)
     p.n_split = int(n_split)
+    p.proposal = 1 if proposal else 0
+    p.C = int(C)
+    p.train_batch = int(train_batch)
     return p
 
 
@@ -153,6 +156,70 @@ class VBGS:
         out = (ctypes.c_int64 * 4)()
         self._check(self.lib.vbgs_counters(self.ctx, out, _stream()))
         return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3])
+
+    # ---- learned candidate proposal -----------------------------------------------------
+    def _f32(self, a):
+        return torch.as_tensor(np.asarray(a, np.float32) if not torch.is_tensor(a) else a,
+                               dtype=torch.float32).to(self.device).contiguous()
+
+    def proposal_set(self, W1, b1, W2, b2, E, beta, mu_in, inv_s_in):
+        t = [self._f32(a) for a in (W1, b1, W2, b2, E, beta, mu_in, inv_s_in)]
+        self._keep = t
+        self._check(self.lib.vbgs_proposal_set(self.ctx, *[_ptr(a) for a in t], _stream()))
+
+    def proposal_get(self):
+        H, D, K, dev = _lib.H, self.D, self.K, self.device
+        o = dict(W1=torch.empty((H, D), device=dev), b1=torch.empty(H, device=dev),
+                 W2=torch.empty((H, H), device=dev), b2=torch.empty(H, device=dev),
+                 E=torch.empty((K, H), device=dev), beta=torch.empty(K, device=dev))
+        self._check(self.lib.vbgs_proposal_get(self.ctx, *[_ptr(o[k]) for k in ("W1", "b1", "W2", "b2", "E", "beta")],
+                                               _stream()))
+        return o
+
+    def estep_stats_pruned(self, X, audit_idx=None, bound=float(np.log1p(-1e-4)), frac=0.01, lse=True, stats=True):
+        X = self._points(X)
+        N = X.shape[0]
+        lse_out = torch.empty(N, dtype=torch.float64, device=self.device) if lse else None
+        stats_out = torch.empty((self.K, self.F), dtype=torch.float64, device=self.device) if stats else None
+        report = torch.zeros(4, dtype=torch.float64, device=self.device)
+        if audit_idx is not None:
+            audit_idx = torch.as_tensor(audit_idx, dtype=torch.int32).to(self.device).contiguous()
+            na = audit_idx.numel()
+        else:
+            na = 0
+        self._audit = audit_idx
+        self._check(self.lib.vbgs_estep_stats_pruned(self.ctx, _ptr(X), N, _ptr(audit_idx), na, float(bound),
+                                                     float(frac), _ptr(lse_out), _ptr(stats_out), _ptr(report),
+                                                     _stream()))
+        return lse_out, stats_out, report
+
+    def proposal_candidates(self, X):
+        X = self._points(X)
+        C = self.params.C if self.params.C > 0 else 32
+        out = torch.empty((X.shape[0], C), dtype=torch.int32, device=self.device)
+        self._check(self.lib.vbgs_proposal_candidates(self.ctx, _ptr(X), X.shape[0], _ptr(out), _stream()))
+        return out
+
+    def export_targets(self, N):
+        tk = torch.empty((N, 64), dtype=torch.int32, device=self.device)
+        tr = torch.empty((N, 64), dtype=torch.float32, device=self.device)
+        self._check(self.lib.vbgs_export_targets(self.ctx, int(N), _ptr(tk), _ptr(tr), _stream()))
+        return tk, tr
+
+    def n_train(self):
+        H = _lib.H
+        return H * self.D + H + H * H + H + self.K * H + self.K
+
+    def train_step(self, X, tk, tr, batch_idx, lr=1e-3, apply=True, loss=True, grads=False):
+        X = self._points(X)
+        bidx = torch.as_tensor(batch_idx, dtype=torch.int32).to(self.device).contiguous()
+        loss_out = torch.empty(1, dtype=torch.float64, device=self.device) if loss else None
+        g = torch.empty(self.n_train(), dtype=torch.float32, device=self.device) if grads else None
+        self._bidx = bidx
+        self._check(self.lib.vbgs_proposal_train_step(self.ctx, _ptr(X), _ptr(tk), _ptr(tr), _ptr(bidx),
+                                                      bidx.numel(), float(lr), 1 if apply else 0, _ptr(loss_out),
+                                                      _ptr(g), _stream()))
+        return loss_out, g
 
     def timing(self, enable=True):
         self._check(self.lib.vbgs_timing(self.ctx, 1 if enable else 0))

@@ -302,3 +302,34 @@ def random_problem(N: int, K: int, D: int, seed: int, spread: float = 0.08,
     ws = (1.0 / spread ** 2) if w_scale is None else w_scale
     pr = Prior(m0=m0, W0=np.eye(D) * ws, kappa0=kappa0, nu0=D + nu_extra, alpha0=alpha0)
     return X, pr
+
+
+# ---------------------------------------------------------------------------
+# proposal network initialisation (the random numbers the method draws, as inputs)
+# ---------------------------------------------------------------------------
+
+def mlp_init(D: int, H: int, K: int, seed: int, X0: np.ndarray | None = None):
+    """He-initialised weights of the D -> H -> H -> K-embedding proposal network (float32).
+
+    W1, W2 ~ N(0, 2 / fan_in); E ~ N(0, 1 / H); biases 0. The input normalisation
+    (mu_in, inv_s_in) is the per-dimension mean and inverse standard deviation of X0
+    (identity when X0 is None).
+    """
+    g = rng(77, seed, D, H, K)
+    out = dict(W1=g.normal(0.0, np.sqrt(2.0 / D), (H, D)), b1=np.zeros(H),
+               W2=g.normal(0.0, np.sqrt(2.0 / H), (H, H)), b2=np.zeros(H),
+               E=g.normal(0.0, np.sqrt(1.0 / H), (K, H)), beta=np.zeros(K))
+    if X0 is None:
+        out["mu_in"], out["inv_s_in"] = np.zeros(D), np.ones(D)
+    else:
+        X0 = np.asarray(X0, np.float64)
+        sd = X0.std(axis=0)
+        out["mu_in"], out["inv_s_in"] = X0.mean(axis=0), 1.0 / np.where(sd > 0, sd, 1.0)
+    return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in out.items()}
+
+
+def audit_indices(N: int, n_audit: int, frame: int, cfg: int = 0) -> np.ndarray:
+    """Seeded audit sample: n_audit distinct point indices of a frame of N points (sorted)."""
+    g = rng(88, frame, cfg)
+    n_audit = min(n_audit, N)
+    return np.sort(g.choice(N, size=n_audit, replace=False)).astype(np.int32)

@@ -55,13 +55,21 @@ def test_query_sizes_and_validation():
     p = P.make_params(6, 10, 10, nu0=4.0)
     with pytest.raises(P.VBGSError):
         P.query_sizes(p)
+    # the proposal needs the exact MFMA mode; its weights and Adam moments live in the state
+    with pytest.raises(P.VBGSError):
+        P.query_sizes(P.make_params(6, 10, 10, score_prec="fp64", proposal=True))
+    s0, w0 = P.query_sizes(P.make_params(6, 1000, 500))
+    s1, w1 = P.query_sizes(P.make_params(6, 1000, 500, proposal=True))
+    n_train = 128 * 6 + 128 + 128 * 128 + 128 + 1000 * 128 + 1000
+    assert s1 - s0 >= 3 * n_train * 4 and w1 > w0
 
 
 def test_params_struct_layout_matches_header():
     from paper_2603_08499_amd import _lib as L
     P = L.Params
     assert ctypes.sizeof(P) == 120
-    assert P.screen_margin.offset == 56 and P.n_split.offset == 64 and P.reserved.offset == 72
+    assert P.screen_margin.offset == 56 and P.n_split.offset == 64 and P.proposal.offset == 68
+    assert P.C.offset == 72 and P.train_batch.offset == 76 and P.reserved.offset == 80
 
 
 def test_null_context_calls_fail_cleanly():

@@ -1,0 +1,235 @@
+"""GPU tests of the learned candidate proposal against the FP64 oracle (proposal_ref).
+
+Top-C is an integer decision taken on BF16 logits, so the oracle takes it in that precision too
+(h2 rounded to FP32 then BF16, E rounded to BF16, exact products, FP64 sums) and the GPU set is
+checked for validity: every candidate is within the accumulation tolerance of the C-th logit and
+no clearly better component is missing. End-to-end parity of the pruned statistics uses logits
+whose top-C is unambiguous.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import proposal_ref as PR
+from oracle import vbgs_ref as R
+from synth import scenes
+
+gpu = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_08499_amd  # noqa: F401
+    return torch.device("cuda:0")
+
+
+def _model(dev, pr, n_max, C=32, **kw):
+    import paper_2603_08499_amd as P
+    return P.VBGS(pr.D, pr.K, n_max, pr.m0, pr.W0, device=dev, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
+                  score_prec="bf16x3", exact=True, proposal=True, C=C, **kw)
+
+
+def _bf16(a):
+    a = np.ascontiguousarray(np.asarray(a, np.float32))
+    b = a.view(np.uint32).astype(np.uint64)
+    r = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _oracle_mlp(w):
+    return PR.MLP(**{k: np.asarray(v, np.float64) for k, v in w.items()})
+
+
+def _blocks(F_packed, D):
+    return F_packed[:, :1], F_packed[:, 1:1 + D], F_packed[:, 1 + D:]
+
+
+def _stat_err(ref, got, D):
+    return max(R.relerr(a, b) for a, b in zip(_blocks(ref, D), _blocks(got, D)))
+
+
+def _separated_weights(D, K, seed, X):
+    """beta spaced by 1 and tiny embeddings: the top-C is the C largest beta for every point."""
+    w = scenes.mlp_init(D, 128, K, seed, X)
+    g = np.random.default_rng(seed)
+    w["E"] = (w["E"] * 1e-3).astype(np.float32)
+    w["beta"] = g.permutation(K).astype(np.float32)
+    return w
+
+
+@gpu
+def test_candidates_are_a_valid_top_c(dev):
+    X, pr = scenes.random_problem(1500, 300, 6, seed=41)
+    w = scenes.mlp_init(6, 128, pr.K, 42, X)
+    m = _model(dev, pr, X.shape[0], C=32)
+    m.proposal_set(**w)
+    cand = m.proposal_candidates(torch.from_numpy(X).to(dev)).cpu().numpy()
+    torch.cuda.synchronize()
+    mo = _oracle_mlp(w)
+    _, _, h2 = PR.forward(mo, X)
+    hb = _bf16(h2.astype(np.float32))
+    Eb = _bf16(w["E"])
+    z = hb @ Eb.T + w["beta"].astype(np.float64)
+    mag = np.abs(hb) @ np.abs(Eb).T
+    bad = 0
+    for n in range(X.shape[0]):
+        S = cand[n]
+        assert (S >= 0).all() and len(set(S.tolist())) == 32 and (np.diff(S) > 0).all()
+        zc = np.sort(z[n])[-32]
+        eps = 1e-5 * mag[n].max() + 2 ** -8 * np.abs(hb[n]).max() * np.abs(Eb).max()
+        inS = np.zeros(pr.K, bool)
+        inS[S] = True
+        bad += int((z[n][inS] < zc - eps).any() or (z[n][~inS] > zc + eps).any())
+    assert bad == 0
+
+
+@gpu
+def test_pruned_statistics_match_oracle(dev):
+    X, pr = scenes.random_problem(2000, 400, 6, seed=43)
+    w = _separated_weights(6, pr.K, 44, X)
+    m = _model(dev, pr, X.shape[0], C=24)
+    m.proposal_set(**w)
+    Xg = torch.from_numpy(X).to(dev)
+    lse, st, rep = m.estep_stats_pruned(Xg)
+    cand = m.proposal_candidates(Xg).cpu().numpy()
+    torch.cuda.synchronize()
+    order = np.argsort(-w["beta"].astype(np.float64), kind="stable")[:24]
+    ref_cand = np.tile(np.sort(order), (X.shape[0], 1))
+    assert (cand == ref_cand).all()
+    q = R.NW.from_prior(pr)
+    lse_c, ref = PR.pruned_estep(X, q, ref_cand)
+    assert np.abs(lse.cpu().numpy() - lse_c).max() < 1e-9
+    assert _stat_err(ref.packed(), st.cpu().numpy(), 6) < 1e-9
+
+
+@gpu
+def test_all_components_as_candidates_equals_dense(dev):
+    X, pr = scenes.random_problem(1200, 20, 6, seed=45)
+    w = scenes.mlp_init(6, 128, pr.K, 46, X)
+    m = _model(dev, pr, X.shape[0], C=32)
+    m.proposal_set(**w)
+    Xg = torch.from_numpy(X).to(dev)
+    lse, st, rep = m.estep_stats_pruned(Xg, audit_idx=np.arange(X.shape[0], dtype=np.int32))
+    torch.cuda.synchronize()
+    q = R.NW.from_prior(pr)
+    ls = R.lse(X, q)
+    ref = R.stats(X, q, ls, scatter=False).packed()
+    assert np.abs(lse.cpu().numpy() - ls).max() < 1e-9
+    assert _stat_err(ref, st.cpu().numpy(), 6) < 1e-9
+    r = rep.cpu().numpy()
+    assert r[0] == 0 and abs(r[1]) < 1e-12 and r[2] == 0.0
+
+
+@gpu
+@pytest.mark.parametrize("bound,expect_fallback", [(0.0, True), (-1e9, False)])
+def test_forced_fallback_and_audit_report(dev, bound, expect_fallback):
+    X, pr = scenes.random_problem(1800, 300, 6, seed=47)
+    w = _separated_weights(6, pr.K, 48, X)
+    m = _model(dev, pr, X.shape[0], C=16)
+    m.proposal_set(**w)
+    aud = scenes.audit_indices(X.shape[0], 500, frame=0)
+    lse, st, rep = m.estep_stats_pruned(torch.from_numpy(X).to(dev), audit_idx=aud, bound=bound, frac=0.01)
+    torch.cuda.synchronize()
+    q = R.NW.from_prior(pr)
+    cand = np.tile(np.sort(np.argsort(-w["beta"].astype(np.float64), kind="stable")[:16]), (X.shape[0], 1))
+    lse_c, pst = PR.pruned_estep(X, q, cand)
+    ls = R.lse(X, q)
+    cap = PR.captured_log_mass(lse_c[aud], ls[aud])
+    fall, agg, below = PR.fallback_decision(cap, bound=bound, frac=0.01)
+    r = rep.cpu().numpy()
+    assert bool(r[0]) == fall == expect_fallback
+    assert abs(r[1] - agg) < 1e-9 * max(1.0, abs(agg)) and abs(r[2] - below) < 1e-12
+    assert abs(r[3] - cap.min()) < 1e-9 * max(1.0, abs(cap.min()))
+    if expect_fallback:  # the dense exact E-step replaced the pruned one
+        ref = R.stats(X, q, ls, scatter=False).packed()
+        assert np.abs(lse.cpu().numpy() - ls).max() < 1e-9
+    else:
+        ref = pst.packed()
+        assert np.abs(lse.cpu().numpy() - lse_c).max() < 1e-9
+    assert _stat_err(ref, st.cpu().numpy(), 6) < 1e-9
+
+
+@gpu
+def test_exported_targets_are_the_exact_responsibilities(dev):
+    X, pr = scenes.random_problem(1500, 250, 6, seed=49)
+    m = _model(dev, pr, X.shape[0])
+    m.estep_stats(torch.from_numpy(X).to(dev), lse=False, stats=False)
+    tk, tr = m.export_targets(X.shape[0])
+    torch.cuda.synchronize()
+    tk, tr = tk.cpu().numpy(), tr.cpu().numpy()
+    Rr = R.responsibilities(X, R.NW.from_prior(pr))
+    for n in range(0, X.shape[0], 7):
+        ks = tk[n][tk[n] >= 0]
+        # the exported r come from exact scores stored as FP32 (about 1e-6 relative)
+        assert np.allclose(tr[n][:ks.size], Rr[n, ks], rtol=1e-5, atol=1e-30)
+        assert Rr[n, ks].sum() > 1 - 1e-9
+        assert len(set(ks.tolist())) == ks.size
+
+
+@gpu
+def test_training_gradients_match_oracle(dev):
+    g = np.random.default_rng(50)
+    D, K, B, M = 6, 300, 96, 8
+    X, pr = scenes.random_problem(400, K, D, seed=51)
+    w = scenes.mlp_init(D, 128, K, 52, X)
+    w["b1"] = np.full(128, 0.05, np.float32)
+    w["b2"] = np.full(128, 0.05, np.float32)
+    w["beta"] = g.normal(0, 0.5, K).astype(np.float32)
+    tk = np.stack([g.choice(K, M, replace=False) for _ in range(X.shape[0])]).astype(np.int32)
+    tk[:, 5:] = -1
+    tr = g.uniform(0.05, 1.0, (X.shape[0], M)).astype(np.float32)
+    tk64 = np.full((X.shape[0], 64), -1, np.int32)
+    tr64 = np.zeros((X.shape[0], 64), np.float32)
+    tk64[:, :M], tr64[:, :M] = tk, tr
+    bidx = np.sort(g.choice(X.shape[0], B, replace=False)).astype(np.int32)
+    m = _model(dev, pr, X.shape[0], train_batch=128)
+    m.proposal_set(**w)
+    loss, grads = m.train_step(torch.from_numpy(X).to(dev), torch.from_numpy(tk64).to(dev),
+                               torch.from_numpy(tr64).to(dev), bidx, apply=False, grads=True)
+    torch.cuda.synchronize()
+    L, ref = PR.loss_and_grads(_oracle_mlp(w), X[bidx], tk64[bidx].astype(np.int64), tr64[bidx].astype(np.float64))
+    gg = grads.cpu().numpy().astype(np.float64)
+    o = 0
+    errs = []
+    for rg in ref:
+        errs.append(R.relerr(rg.ravel(), gg[o:o + rg.size]))
+        o += rg.size
+    print("loss %.6f vs %.6f; grad relerr W1 b1 W2 b2 E beta:" % (loss.item(), L), ["%.2e" % e for e in errs])
+    assert abs(loss.item() - L) < 1e-3 * abs(L)
+    assert max(errs) < 2e-2
+
+
+@gpu
+def test_adam_step_matches_oracle(dev):
+    g = np.random.default_rng(53)
+    D, K, B = 6, 200, 64
+    X, pr = scenes.random_problem(300, K, D, seed=54)
+    w = scenes.mlp_init(D, 128, K, 55, X)
+    tk = np.full((X.shape[0], 64), -1, np.int32)
+    tr = np.zeros((X.shape[0], 64), np.float32)
+    tk[:, :3] = np.stack([g.choice(K, 3, replace=False) for _ in range(X.shape[0])])
+    tr[:, :3] = g.uniform(0.1, 1, (X.shape[0], 3))
+    bidx = np.arange(B, dtype=np.int32)
+    m = _model(dev, pr, X.shape[0], train_batch=64)
+    m.proposal_set(**w)
+    Xg, tkg, trg = torch.from_numpy(X).to(dev), torch.from_numpy(tk).to(dev), torch.from_numpy(tr).to(dev)
+    _, g1 = m.train_step(Xg, tkg, trg, bidx, lr=1e-2, apply=True, grads=True)
+    new = m.proposal_get()
+    torch.cuda.synchronize()
+    # oracle Adam from the same initial weights and the GPU step's own gradient input is not
+    # used: the oracle recomputes its FP64 gradient and steps; the first Adam step moves every
+    # weight by about lr * sign(gradient), so compare signs and magnitudes
+    mo = _oracle_mlp(w)
+    _, ref = PR.loss_and_grads(mo, X[bidx], tk[bidx].astype(np.int64), tr[bidx].astype(np.float64))
+    params = [p.copy() for p in mo.params()]
+    PR.adam_step(params, ref, [np.zeros_like(p) for p in params], [np.zeros_like(p) for p in params], 1,
+                 PR.Adam(lr=1e-2))
+    for name, p_new, p_ref, p_old, gr in zip(("W1", "b1", "W2", "b2", "E", "beta"),
+                                             [new[k].cpu().numpy() for k in ("W1", "b1", "W2", "b2", "E", "beta")],
+                                             params, mo.params(), ref):
+        d_gpu = p_new.astype(np.float64) - p_old
+        d_ref = p_ref - p_old
+        strong = np.abs(gr) > 1e-3 * np.abs(gr).max()
+        assert np.allclose(d_gpu[strong], d_ref[strong], rtol=2e-2, atol=1e-4), name
