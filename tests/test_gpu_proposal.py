@@ -233,3 +233,33 @@ def test_adam_step_matches_oracle(dev):
         d_ref = p_ref - p_old
         strong = np.abs(gr) > 1e-3 * np.abs(gr).max()
         assert np.allclose(d_gpu[strong], d_ref[strong], rtol=2e-2, atol=1e-4), name
+
+
+@gpu
+def test_trained_network_gains_over_untrained(dev):
+    """Train on the exact responsibilities of four frames of a c2-like stream, then compare the
+    trained and the untrained network on the next frame at the same posterior: captured mass of
+    an audit of every point, and whether the frame would fall back to the dense E-step."""
+    from paper_2603_08499_amd import driver
+    scene = scenes.gauss_scene(2, 2000, 0.005, 0.05)
+    frames = [scenes.c2_frame(t, N=6000, stationary=True, scene=scene) for t in range(5)]
+    pr = scenes.c2_prior(frames[0], K=700)
+    w0 = scenes.mlp_init(6, 128, pr.K, 60, frames[0])
+    m = _model(dev, pr, 6000, C=16, train_batch=1024)
+    m.proposal_set(**w0)
+    Xs = [torch.from_numpy(f).to(dev) for f in frames]
+    driver.run_stream(m, Xs[:4], n_exact=4, train_steps=400, batch=1024, lr=3e-3, seed=1)
+    every = np.arange(6000, dtype=np.int32)
+    _, _, rep_t = m.estep_stats_pruned(Xs[4], audit_idx=every)
+    trained = rep_t.cpu().numpy()
+    w_trained = m.proposal_get()
+    m.proposal_set(**w0)
+    _, _, rep_u = m.estep_stats_pruned(Xs[4], audit_idx=every)
+    untrained = rep_u.cpu().numpy()
+    torch.cuda.synchronize()
+    print("trained: ln mean captured %.3e, below-bound fraction %.4f, fallback %d" % (trained[1], trained[2], trained[0]))
+    print("untrained: ln mean captured %.3e, below-bound fraction %.4f, fallback %d" % (untrained[1], untrained[2],
+                                                                                         untrained[0]))
+    assert trained[1] > untrained[1] and trained[2] < untrained[2]
+    assert trained[1] > np.log(0.99)
+    assert np.isfinite(w_trained["E"].cpu().numpy()).all()
