@@ -45,6 +45,81 @@ def workload(name, n_frames):
     return frames, prior, desc
 
 
+def run_c4(args):
+    """Learned-proposal workload (c4): c3 frames; frames 0..n_exact-1 run the exact E-step and give
+    training targets, the network is trained on them, then the timed frames run the pruned E-step
+    (top-C candidates, audit of 4096 seeded points, dense fallback on the device when the captured
+    log-mass falls below ln(1 - 1e-4)); the exact E-step on the same frames and state is timed beside it."""
+    import torch
+    import paper_2603_08499_amd as P
+    from paper_2603_08499_amd import driver
+    from synth import scenes
+    dev = torch.device("cuda:0")
+    n_ex, n_t = args.c4_exact, args.steps
+    scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
+    frames = [scenes.c3_frame(t, scene=scene) for t in range(n_ex + n_t)]
+    pr = scenes.c3_prior(frames[0])
+    N, D, K, C = frames[0].shape[0], pr.D, pr.K, args.c4_C
+    Xs = [torch.from_numpy(f).to(dev) for f in frames]
+    m = P.VBGS(D, K, N, pr.m0, pr.W0, device=dev, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
+               score_prec=args.prec, exact=True, proposal=True, C=C, train_batch=4096)
+    m.proposal_set(**scenes.mlp_init(D, 128, K, 3, frames[0]))
+    print("bench c4: %d exact frames" % n_ex, file=sys.stderr, flush=True)
+    driver.run_stream(m, Xs[:n_ex], n_exact=n_ex, train_steps=0)
+    data = []
+    for t in range(n_ex):  # targets at the final prior of the exact frames
+        m.estep_stats(Xs[t], lse=False, stats=False)
+        data.append((Xs[t], *m.export_targets(N)))
+    torch.cuda.synchronize()
+    steps = args.c4_train_steps
+    print("bench c4: training %d steps" % steps, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    losses = driver.train_on_targets(m, data, steps, 4096, 1e-3, 7)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    state = m.state.clone()  # the exact comparator starts from the same posterior
+    logs = []
+    m.timing(True)
+    m.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_t):
+        g = np.random.default_rng([11, i])
+        idx = np.sort(g.choice(N, size=4096, replace=False)).astype(np.int32)
+        _, _, rep = m.estep_stats_pruned(Xs[n_ex + i], audit_idx=idx, lse=False, stats=False)
+        m.elbo()
+        m.update(commit=True)
+        logs.append(rep)
+    torch.cuda.synchronize()
+    t_pruned = (time.perf_counter() - t0) / n_t
+    phases = m.timing_read()
+    reps = np.stack([r.cpu().numpy() for r in logs])
+    mx = P.VBGS(D, K, N, None, None, device=dev, state=state, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
+                score_prec=args.prec, exact=True, proposal=True, C=C, train_batch=4096)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_t):
+        mx.estep_stats(Xs[n_ex + i], lse=False, stats=False)
+        mx.elbo()
+        mx.update(commit=True)
+    torch.cuda.synchronize()
+    t_exact = (time.perf_counter() - t0) / n_t
+    avg = {k: v[0] / v[1] for k, v in phases.items() if v[1]}
+    value = N * K / t_pruned
+    out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": n_t, "warmup": n_ex,
+           "ms_per_step": t_pruned * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16+f64", "data": "synthetic",
+           "config": {"workload": "c4: c3 frames with the learned top-C proposal; %d exact training frames, "
+                                  "%d pruned frames, C=%d, audit 4096, bound ln(1-1e-4)" % (n_ex, n_t, C),
+                      "N": N, "K": K, "D": D, "C": C},
+           "pairs_per_s_candidates": N * C / t_pruned, "exact_ms_per_step": t_exact * 1e3,
+           "speedup_vs_exact": t_exact / t_pruned, "fallback_rate": float(reps[:, 0].mean()),
+           "ln_captured_mass": reps[:, 1].tolist(), "below_bound_fraction": reps[:, 2].tolist(),
+           "train_steps": steps, "train_s": t_train, "train_loss_first_last": [losses[0], losses[-1]] if losses else None,
+           "phase_ms": {k: round(v, 5) for k, v in avg.items()}}
+    print(json.dumps(out))
+
+
 def run_steps(model, Xs, steps, torch):
     for i in range(steps):
         model.estep_stats(Xs[i % len(Xs)], lse=False, stats=False)
@@ -65,12 +140,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=4096)
+    ap.add_argument("--c4-exact", type=int, default=10)
+    ap.add_argument("--c4-train-steps", type=int, default=1500)
+    ap.add_argument("--c4-C", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this path runs on one GPU; --gpus %d is not supported (see the design notes on "
               "sharding)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c4":
+        return run_c4(args)
     import torch
     import paper_2603_08499_amd as P
 
