@@ -91,7 +91,11 @@ typedef struct {
   int32_t proposal;        /* 1: allocate the learned candidate proposal (MFMA precisions, D <= 6) */
   int32_t C;               /* candidates per point proposed by the network, 1..64 (default 32) */
   int32_t train_batch;     /* largest training minibatch, 0..65536 (default 4096) */
-  int64_t reserved[5];     /* must be zero */
+  int32_t cull;            /* exact MFMA mode: 1 (default) sorts points and components spatially and
+                              skips whole 64-component tiles whose score bound lies below the margin;
+                              0 screens every tile */
+  int32_t reserved1;       /* must be zero */
+  int64_t reserved[4];     /* must be zero */
 } vbgs_params;
 
 #define VBGS_H 128         /* hidden width of the proposal network (= embedding width) */
@@ -158,16 +162,22 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
 
 /* Synchronise `stream` and read counters of the last E-step (exact MFMA mode):
  * out[0] = pairs recorded by the screen sweep, out[1] = pairs kept for the statistics
- * (within the margin of their point's LSE), out[2] = number of points, out[3] = K. */
-vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[4], void* stream);
+ * (within the margin of their point's LSE), out[2] = number of points, out[3] = K,
+ * out[4] = blocks of 64 points x 16 components the sweep screened on MFMA, out[5] = the
+ * number of such blocks without culling (4 per 256-point workgroup and 16 components), out[6] =
+ * the blocks screened by all E-steps since vbgs_init or the last vbgs_clear_flags. */
+vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[7], void* stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each call.
- * Phases: 0 frame moments + features, 1 expectations + coefficient rows, 2 pass 1 (LSE),
- * 3 pass 2 (statistics), 4 fold, 5 update, 6 ELBO reduction, 7 reserved.
+ * Phases: 0 frame moments + features, 1 expectations + coefficient rows (with culling also the
+ * spatial sort of the components and the tile bounds), 2 the first pass over all pairs (in
+ * exact MFMA mode the screening sweep kernel alone), 3 pass 2 (statistics), 4 fold, 5 update,
+ * 6 ELBO reduction, 7 proposal network (forward, logits, top-C, audit), 8 spatial sort of the
+ * points and clearing of the transpose counters, 9 exact per-point LSE from the candidates.
  * vbgs_timing(ctx, 1) creates the events (host-side objects, no device memory) and records
  * every later phase; 0 stops recording. vbgs_timing_read synchronises `stream`, writes the
  * summed duration in ms and the number of recorded launches of each phase, and clears them. */
-#define VBGS_NPHASE 8  /* phase 7: proposal network (forward, logits, top-C, audit) */
+#define VBGS_NPHASE 10
 vbgs_status vbgs_timing(vbgs_ctx* ctx, int32_t enable);
 vbgs_status vbgs_timing_read(vbgs_ctx* ctx, double ms[VBGS_NPHASE], int64_t counts[VBGS_NPHASE], void* stream);
 

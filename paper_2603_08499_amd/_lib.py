@@ -10,8 +10,8 @@ LIB_PATH = os.path.join(HERE, "libvbgs.so")
 VBGS_ABI_VERSION = 1
 STATUS = {0: "VBGS_OK", -1: "VBGS_ERR_ARG", -2: "VBGS_ERR_SHAPE", -3: "VBGS_ERR_HIP", -4: "VBGS_ERR_NOT_PD",
           -5: "VBGS_ERR_NONFINITE", -6: "VBGS_ERR_STATE", -7: "VBGS_ERR_UNSUPPORTED"}
-NPHASE = 8
-PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "proposal"]
+NPHASE = 10
+PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "proposal", "sort", "lse"]
 H = 128
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
@@ -21,7 +21,8 @@ class Params(ctypes.Structure):
                 ("n_max", ctypes.c_int64), ("kappa0", ctypes.c_double), ("nu0", ctypes.c_double),
                 ("alpha0", ctypes.c_double), ("score_prec", ctypes.c_int32), ("exact", ctypes.c_int32),
                 ("screen_margin", ctypes.c_double), ("n_split", ctypes.c_int32), ("proposal", ctypes.c_int32),
-                ("C", ctypes.c_int32), ("train_batch", ctypes.c_int32), ("reserved", ctypes.c_int64 * 5)]
+                ("C", ctypes.c_int32), ("train_batch", ctypes.c_int32), ("cull", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("reserved", ctypes.c_int64 * 4)]
 
 
 _lib = None

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvbgs.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["k_model.hip", "k_estep.hip", "k_proposal.hip", "vbgs_api.hip"]
+SOURCES = ["k_model.hip", "k_estep.hip", "k_sort.hip", "k_proposal.hip", "vbgs_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

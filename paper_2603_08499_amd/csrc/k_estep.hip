@@ -313,6 +313,10 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
       }
     }
     count_refined(&a.frame->refined1, nref);
+    if (lane == 0) {
+      atomicAdd(&a.frame->blocks, (unsigned long long)(ntiles * (CT / 16)));
+      atomicAdd(&a.frame->blocks_cum, (unsigned long long)(ntiles * (CT / 16)));
+    }
   } else {
 #pragma unroll
     for (int b = 0; b < P1_PB; ++b) {
@@ -339,6 +343,247 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
       for (int i = 0; i < 256; ++i) sacc += red[i];
       a.lse_part[blockIdx.x] = sacc;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exact mode, culled sweep over spatially sorted points and components
+// ---------------------------------------------------------------------------
+// Points are taken in Morton order (a wave holds 64 spatially close points) and the coefficient
+// rows in the order of (curvature class, Morton code of the mean), 64 rows per tile. Bounds on
+// the score of a pair with a point x (first min(D, 3) raw coordinates S):
+//   tile t:  G_t - Lam_t dist^2(x_S, box_t)       (TileInfo: max G, min lambda, box of the means)
+//   row k:   G_k - lambda_k |x_S - m_k,S|^2       (RowBound)
+// A pair whose bound lies below the point's running lower bound M minus the margin T is one the
+// per-pair screen would drop, so it is never screened. Each wave works on its own:
+//   1. pilot: its seed tiles (those around the Morton positions of its first and last point)
+//      are screened without recording, which brings every M close to its final value;
+//   2. the seed tiles again, now recording candidates;
+//   3. every other tile, 64 at a time (one per lane): a tile is screened when its bound reaches
+//      M - T for at least one point of the wave; within it, a 16-row block is screened when one
+//      of its row bounds, taken over the wave's box, reaches the wave's smallest M - T.
+// Rows and bounds of a tile are loaded straight into registers (they stay resident in the
+// caches, being read by every wave), so waves never wait for one another.
+__device__ __forceinline__ float box_d2(const TileInfo& t, const float* lo, const float* hi) {
+  float d2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float gap = fmaxf(fmaxf(t.lo[i] - hi[i], lo[i] - t.hi[i]), 0.0f);
+    d2 = fmaf(gap, gap, d2);
+  }
+  return d2;
+}
+
+// last tile whose first code is <= code (0 when there is none): a 64-way search, one probe per lane
+__device__ __forceinline__ int64_t find_tile(const TileInfo* __restrict__ ti, int64_t ntiles, uint32_t code,
+                                             int lane) {
+  int64_t L = 0, R = ntiles - 1;
+  while (L < R) {
+    const int64_t span = R - L + 1;
+    const int64_t pos = L + span * lane / 64;
+    const unsigned long long m = __ballot(ti[pos].code <= code);
+    if (m == 0ull) return L;  // only when L = 0 and code is below the first tile's
+    const int last = 63 - __clzll(m);
+    const int64_t nl = L + span * last / 64;
+    const int64_t nr = last == 63 ? R : L + span * (last + 1) / 64 - 1;
+    L = nl;
+    R = nr > nl ? nr : nl;
+  }
+  return L;
+}
+
+template <int P>
+struct SweepWave {
+  Opnd<P> B[P1_PB];
+  float nphE[P1_PB], M[P1_PB];
+  int cn[P1_PB];
+  bool val[P1_PB], ovf[P1_PB];
+  float lo[3], hi[3];
+  unsigned nref, nblk;
+};
+
+// screen tile t for the wave's points (see above); rec: record candidates
+template <int P>
+__device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int64_t t, bool rec, int lane,
+                                            float* __restrict__ mv, const int32_t* __restrict__ pid) {
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t r0 = t * CT;
+  const RowBound rb = a.rowb[r0 + lane];
+  Opnd<P> A[CT / 16];
+#pragma unroll
+  for (int cb = 0; cb < CT / 16; ++cb) {
+    const int64_t r = r0 + cb * 16 + c;
+    A[cb] = load_op<P>(a.c32 + r * FP, a.ch + r * FP, a.cl + r * FP, g);
+  }
+  // largest coefficient norm over the four rows 4j..4j+3 (lane j holds row j's)
+  float nc4 = fmaxf(rb.nc, __shfl_xor(rb.nc, 1));
+  nc4 = fmaxf(nc4, __shfl_xor(nc4, 2));
+  float mw = INFINITY;
+#pragma unroll
+  for (int b = 0; b < P1_PB; ++b)
+    if (S.val[b]) mw = fminf(mw, S.M[b]);
+  for (int o = 1; o < 64; o <<= 1) mw = fminf(mw, __shfl_xor(mw, o));
+  const float margin = a.T2 + 1.0f;
+  float d2 = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    // the mean is rounded to FP32: shrink the gap by a bound on that rounding
+    const float gap =
+        fmaxf(fmaxf(rb.m[q] - S.hi[q], S.lo[q] - rb.m[q]) - fabsf(rb.m[q]) * 2.384185791015625e-7f, 0.0f);
+    d2 = fmaf(gap, gap, d2);
+  }
+  const unsigned long long rmask = __ballot(rb.G - rb.Lam * d2 >= mw - margin);
+#pragma unroll
+  for (int cb = 0; cb < CT / 16; ++cb) {
+    if (((rmask >> (16 * cb)) & 0xFFFFull) == 0ull) continue;  // wave-uniform
+    ++S.nblk;
+    const float ncm = __shfl(nc4, 16 * cb + 4 * g);  // rows 16 cb + 4 g + i, i < 4
+#pragma unroll
+    for (int b = 0; b < P1_PB; ++b) {
+      const f32x4 sv = mfma_scores<P>(A[cb], S.B[b]);
+      const float mx = fmaxf(fmaxf(sv[0], sv[1]), fmaxf(sv[2], sv[3]));
+      const float e = S.nphE[b] * ncm;
+      S.M[b] = fmaxf(S.M[b], mx - e);
+      const float thr = S.M[b] - a.T2 - e;
+      if (rec && S.val[b] && mx >= thr) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t r = r0 + cb * 16 + 4 * g + q;
+          if (sv[q] >= thr && r < a.K) {
+            record_candidate(a, pid[16 * b + c], g, a.corder[r], sv[q] + e, S.M[b] - a.T2, S.cn[b], S.ovf[b]);
+            ++S.nref;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < P1_PB; ++b) {
+    S.M[b] = fmaxf(S.M[b], __shfl_xor(S.M[b], 16));
+    S.M[b] = fmaxf(S.M[b], __shfl_xor(S.M[b], 32));
+    if (g == 0 && S.val[b]) mv[16 * b + c] = S.M[b];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep(const EArgs a) {
+  if (a.gate && a.gate[0] == 0) return;
+  __shared__ float4 pts[4][64];   // per wave: first three raw coordinates of its points
+  __shared__ float mvs[4][64];    // their current lower bounds M (+inf for empty slots)
+  __shared__ int32_t pids[4][64]; // their original indices
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t j0 = (int64_t)blockIdx.x * P1_PTS + w * (P1_PB * 16);  // sorted positions
+  const int ns = a.D < 3 ? a.D : 3;
+  float* mv = mvs[w];
+  const int32_t* pid = pids[w];
+
+  SweepWave<P> S;
+  S.nref = 0;
+  S.nblk = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    S.lo[i] = INFINITY;
+    S.hi[i] = -INFINITY;
+  }
+#pragma unroll
+  for (int b = 0; b < P1_PB; ++b) {
+    const int64_t j = j0 + 16 * b + c;
+    S.val[b] = j < a.N;
+    const int64_t p = S.val[b] ? a.porder[j] : 0;
+    float v[3] = {0.0f, 0.0f, 0.0f};
+    if (S.val[b]) {
+      S.B[b] = load_op<P>(a.phi32 + p * FP, a.phih + p * FP, a.phil + p * FP, g);
+      S.nphE[b] = a.eps * a.nphi[p];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        v[i] = i < ns ? a.X[p * a.D + i] : 0.0f;
+        S.lo[i] = fminf(S.lo[i], v[i]);
+        S.hi[i] = fmaxf(S.hi[i], v[i]);
+      }
+    } else {
+      S.B[b] = zero_op<P>();
+      S.nphE[b] = 0.0f;
+    }
+    if (g == 0) {
+      pts[w][16 * b + c] = make_float4(v[0], v[1], v[2], 0.0f);
+      mvs[w][16 * b + c] = S.val[b] ? -INFINITY : INFINITY;
+      pids[w][16 * b + c] = (int32_t)p;
+    }
+    S.M[b] = -INFINITY;
+    S.cn[b] = 0;
+    S.ovf[b] = false;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    for (int off = 1; off < 64; off <<= 1) {
+      S.lo[i] = fminf(S.lo[i], __shfl_xor(S.lo[i], off));
+      S.hi[i] = fmaxf(S.hi[i], __shfl_xor(S.hi[i], off));
+    }
+  __builtin_amdgcn_wave_barrier();
+  if (j0 < a.N) {
+    const int64_t ntiles = a.Kpad / CT;
+    // seeds: tiles around the Morton positions of the wave's first and last point
+    const int64_t jl = min(j0 + 63, a.N - 1);
+    const int64_t tf = find_tile(a.tinfo, ntiles, a.pcode[j0], lane);
+    const int64_t tl = find_tile(a.tinfo, ntiles, a.pcode[jl], lane);
+    const bool span = tl - tf <= 6;
+    auto is_seed = [&](int64_t t) {
+      return (t >= tf - 1 && t <= tf + 1) || (t >= tl - 1 && t <= tl + 1) || (span && t >= tf && t <= tl);
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int64_t t = max(tf - 1, (int64_t)0); t <= min(tl + 1, ntiles - 1); ++t)
+        if (is_seed(t)) screen_tile<P>(a, S, t, pass == 1, lane, mv, pid);
+    }
+    const float margin = a.T2 + 1.0f;
+    for (int64_t base = 0; base < ntiles; base += 64) {
+      const int64_t t = base + lane;
+      bool need = false;
+      if (t < ntiles && !is_seed(t)) {
+        const TileInfo ti = a.tinfo[t];
+        float mw = INFINITY;
+#pragma unroll
+        for (int b = 0; b < P1_PB; ++b)
+          if (S.val[b]) mw = fminf(mw, S.M[b]);
+        for (int o = 1; o < 64; o <<= 1) mw = fminf(mw, __shfl_xor(mw, o));
+        if (ti.G - ti.Lam * box_d2(ti, S.lo, S.hi) >= mw - margin) {
+          // some point of the wave within reach of this tile
+          for (int q = 0; q < 64 && !need; ++q) {
+            const float4 x = pts[w][q];
+            float d2 = 0.0f;
+            const float xq[3] = {x.x, x.y, x.z};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              const float gap = fmaxf(fmaxf(ti.lo[i] - xq[i], xq[i] - ti.hi[i]), 0.0f);
+              d2 = fmaf(gap, gap, d2);
+            }
+            need = ti.G - ti.Lam * d2 >= mv[q] - margin;
+          }
+        }
+      }
+      unsigned long long m = __ballot(need);
+      while (m) {
+        const int i = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        screen_tile<P>(a, S, base + i, true, lane, mv, pid);
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < P1_PB; ++b) {
+    int o = S.ovf[b] ? 1 : 0;
+    o |= __shfl_xor(o, 16);
+    o |= __shfl_xor(o, 32);
+    if (S.val[b]) {
+      const int32_t p = pid[16 * b + c];
+      a.cand_n[(int64_t)p * 4 + g] = o ? -1 : S.cn[b];
+      if (o && g == 0) a.over_list[atomicAdd(&a.frame->n_over, 1)] = p;
+    }
+  }
+  count_refined(&a.frame->refined1, S.nref);
+  if (lane == 0 && S.nblk) {
+    atomicAdd(&a.frame->blocks, (unsigned long long)S.nblk);
+    atomicAdd(&a.frame->blocks_cum, (unsigned long long)S.nblk);
   }
 }
 
@@ -829,29 +1074,49 @@ __global__ void k_fold(const double* __restrict__ spart, int nsplit, int64_t Kpa
 // ---------------------------------------------------------------------------
 // exact mode: screen sweep recording candidates, then the exact LSE (overflowed points first);
 // every kernel honours a.gate
-hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s) {
+// the three stages of the exact E-step over all pairs: clear the transpose counters, screen
+// (sweep), exact per-point LSE from the candidate lists
+static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull, int stage) {
   if (N <= 0) return hipSuccess;
-  const int64_t Kp1 = a.Kpad + 1;
-  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, a.gate);
-  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1, a.gate);
-  hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, a.gate);
-  const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
-  if (prec == VBGS_FP32) hipLaunchKernelGGL((k_pass1<VBGS_FP32, true>), grid, dim3(256), 0, s, a);
-  else if (prec == VBGS_BF16) hipLaunchKernelGGL((k_pass1<VBGS_BF16, true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_pass1<VBGS_BF16X3, true>), grid, dim3(256), 0, s, a);
-  const dim3 gp((unsigned)((N + 255) / 256));
-  switch (D) {
+  if (stage == 0) {
+    const int64_t Kp1 = a.Kpad + 1;
+    hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, a.gate);
+    hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1, a.gate);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, a.gate);
+  } else if (stage == 1) {
+    const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
+    if (cull) {
+      if (prec == VBGS_FP32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), grid, dim3(256), 0, s, a);
+      else if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), grid, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), grid, dim3(256), 0, s, a);
+    } else if (prec == VBGS_FP32) {
+      hipLaunchKernelGGL((k_pass1<VBGS_FP32, true>), grid, dim3(256), 0, s, a);
+    } else if (prec == VBGS_BF16) {
+      hipLaunchKernelGGL((k_pass1<VBGS_BF16, true>), grid, dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_pass1<VBGS_BF16X3, true>), grid, dim3(256), 0, s, a);
+    }
+  } else {
+    const dim3 gp((unsigned)((N + 255) / 256));
+    switch (D) {
 #define VB_LSE(DD)                                                    \
   case DD:                                                            \
     hipLaunchKernelGGL(k_over_lse<DD>, dim3(64), dim3(256), 0, s, a); \
     hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, a);      \
     break;
-    VB_LSE(1) VB_LSE(2) VB_LSE(3) VB_LSE(4) VB_LSE(5) VB_LSE(6)
+      VB_LSE(1) VB_LSE(2) VB_LSE(3) VB_LSE(4) VB_LSE(5) VB_LSE(6)
 #undef VB_LSE
-    default:
-      return hipErrorInvalidValue;
+      default:
+        return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
+}
+
+hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull) {
+  hipError_t e = hipSuccess;
+  for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) e = exact_stage(a, prec, D, N, s, cull, stage);
+  return e;
 }
 
 // exact LSE of externally provided candidate lists (counts are zeroed here, ungated)
@@ -929,6 +1194,11 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.ent_n = d.at<int32_t>(L.ent_n);
   a.frame = d.frame();
   a.gate = c.gate;
+  a.porder = d.at<int32_t>(L.porder);
+  a.pcode = d.at<uint32_t>(L.pcode);
+  a.corder = d.at<int32_t>(L.corder);
+  a.tinfo = d.at<TileInfo>(L.tinfo);
+  a.rowb = d.at<RowBound>(L.rowb);
   a.N = N;
   a.K = d.K;
   a.Kpad = L.Kpad;
@@ -941,9 +1211,14 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
 }
 
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
-                        hipStream_t s) {
+                        hipStream_t s, int stage) {
   if (N <= 0) return hipSuccess;
   const EArgs a = make_eargs(d, c, X, N, lse_out);
+  if (c.prec != VBGS_FP64 && c.exact) {
+    if (stage >= 0) return exact_stage(a, c.prec, d.D, N, s, c.cull, stage);
+    return launch_exact_sweep(a, c.prec, d.D, N, s, c.cull);
+  }
+  if (stage == 0 || stage == 2) return hipSuccess;
   if (c.prec == VBGS_FP64) {
     const dim3 grid((unsigned)((N + 255) / 256));
     switch (d.D) {
@@ -963,9 +1238,7 @@ hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int
     if (c.prec == VBGS_FP32) VB_P1(VBGS_FP32, false);
     else if (c.prec == VBGS_BF16) VB_P1(VBGS_BF16, false);
     else VB_P1(VBGS_BF16X3, false);
-    return hipGetLastError();
   }
-  return launch_exact_sweep(a, c.prec, d.D, N, s);
 #undef VB_P1
   return hipGetLastError();
 }

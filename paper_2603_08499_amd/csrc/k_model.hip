@@ -100,6 +100,7 @@ __global__ void k_moments_final(const double* __restrict__ part, int64_t N, int 
     fr->refined1 = 0;
     fr->refined2 = 0;
     fr->n_over = 0;
+    fr->blocks = 0;
   }
 }
 
@@ -214,6 +215,10 @@ __device__ void load_winv(const double* r, double A[D][D]) {
 }
 
 struct CoefOut {
+  int64_t K;
+  const int32_t* cinv;  // component -> row of the expanded tables (null: identity)
+  RowBound* rowb;       // per-row bounds in the order of cinv (only with cinv)
+  float* lam;           // lower bound on the score curvature in the first min(D, 3) coordinates
   double* direct;
   float* c32;
   uint16_t* ch;
@@ -223,14 +228,20 @@ struct CoefOut {
 };
 
 __device__ void write_dead_row(const CoefOut& o, int64_t k, int dts, bool expanded) {
+  const int64_t row = (o.cinv && k < o.K) ? (int64_t)o.cinv[k] : k;
   for (int i = 0; i < (expanded ? FP : 0); ++i) {
     const float v = i == 0 ? DEAD_C0 : 0.0f;
-    o.c32[k * FP + i] = v;
+    o.c32[row * FP + i] = v;
     const uint16_t h = f2bf(v);
-    o.ch[k * FP + i] = h;
-    o.cl[k * FP + i] = f2bf(v - bf2f(h));
+    o.ch[row * FP + i] = h;
+    o.cl[row * FP + i] = f2bf(v - bf2f(h));
   }
-  if (expanded) o.nc[k] = 0.0f;
+  if (expanded) o.nc[row] = 0.0f;
+  if (o.rowb) {
+    RowBound rb{};
+    rb.G = -FLT_MAX;
+    o.rowb[row] = rb;
+  }
   for (int i = 0; i < dts; ++i) o.direct[k * dts + i] = i == 0 ? -1.0e300 : 0.0;
 }
 
@@ -248,6 +259,8 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
   const double* q = post + k * REC;
   const double* p = prior + k * REC;
   const double alpha = q[0], kappa = q[1], nu = q[2];
+  const float lam = comp_lambda(q, D);
+  o.lam[k] = lam;
   double m[D];
   for (int i = 0; i < D; ++i) m[i] = q[3 + i];
   double L[D][D];
@@ -256,6 +269,7 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     atomicOr(flags, FLAG_NOT_PD);
     write_dead_row(o, k, dts, D <= 6);
     o.kl[k] = 0.0;
+    o.lam[k] = 0.0f;
     return;
   }
   double lndetW = 0.0;
@@ -317,15 +331,24 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
       c[oo++] = (a == b ? -0.5 : -1.0) * LOG2E * nu * wab;
     }
   double nn = 0.0;
+  const int64_t row = o.cinv ? (int64_t)o.cinv[k] : k;
   for (int i = 0; i < FP; ++i) {
     const float v = (float)c[i];
-    o.c32[k * FP + i] = v;
+    o.c32[row * FP + i] = v;
     const uint16_t h = f2bf(v);
-    o.ch[k * FP + i] = h;
-    o.cl[k * FP + i] = f2bf(v - bf2f(h));
+    o.ch[row * FP + i] = h;
+    o.cl[row * FP + i] = f2bf(v - bf2f(h));
     nn += c[i] * c[i];
   }
-  o.nc[k] = (float)(sqrt(nn) * (1.0 + 1e-6));
+  o.nc[row] = (float)(sqrt(nn) * (1.0 + 1e-6));
+  if (o.rowb) {
+    RowBound rb{};
+    rb.G = f_up(T[0]);
+    rb.Lam = lam;
+    for (int i = 0; i < (D < 3 ? D : 3); ++i) rb.m[i] = (float)m[i];
+    rb.nc = o.nc[row];
+    o.rowb[row] = rb;
+  }
   }
 
   // KL(NW(q_k) || NW(p_k)) + the per-component part of KL(Dir(alpha) || Dir(alpha_p))
@@ -358,11 +381,11 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
   o.kl[k] = klnw + kd;
 }
 
-hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s) {
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
   const Layout& L = *d.L;
   hipLaunchKernelGGL(k_alpha_sums, dim3(1), dim3(1024), 0, s, d.prior(), d.post(), d.K, d.frame());
-  CoefOut o{d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch), d.at<uint16_t>(L.cl),
-            d.at<float>(L.nc), d.at<double>(L.kl)};
+  CoefOut o{d.K, cinv, cinv ? d.at<RowBound>(L.rowb) : nullptr, d.at<float>(L.lam), d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch),
+            d.at<uint16_t>(L.cl), d.at<float>(L.nc), d.at<double>(L.kl)};
   const dim3 grid((unsigned)((L.Kpad + 127) / 128)), blk(128);
   int* fl = &d.frame()->flags;
   switch (d.D) {
@@ -494,6 +517,8 @@ __global__ void k_clear_flags(FrameInfo* fr) {
   fr->flags = 0;
   fr->refined1 = 0;
   fr->refined2 = 0;
+  fr->blocks = 0;
+  fr->blocks_cum = 0;
 }
 
 hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s) {

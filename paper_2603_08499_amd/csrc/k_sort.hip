@@ -1,0 +1,254 @@
+// Spatial ordering for the culled exact sweep: 3-D Morton keys of points and component means,
+// a bitonic sort of 64-bit keys (key = code << 32 | index, so every key is unique and the order
+// is deterministic), and per-tile bounds of the sorted component rows.
+#include "vbgs_internal.h"
+
+namespace vbgs {
+
+// spread the low 10 bits of v so that bit i moves to bit 3i
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// Morton code of the first min(D, 3) coordinates, each quantised to 10 bits over the frame's
+// window mu +- 4 s (clamped): the same map for points and component means
+__device__ __forceinline__ uint32_t morton_code(const float* x, const double* xd, int D, const FrameInfo* fr) {
+  uint32_t code = 0;
+  const int ns = D < 3 ? D : 3;
+  for (int i = 0; i < ns; ++i) {
+    const double v = x ? (double)x[i] : xd[i];
+    double u = (v - (double)fr->mu[i]) / (8.0 * fr->s[i]) + 0.5;
+    u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+    const uint32_t q = (uint32_t)(u * 1023.0);
+    code |= spread3(q) << i;
+  }
+  return code;
+}
+
+__global__ void k_point_keys(const float* __restrict__ X, int64_t N, int64_t Npow, int D, const FrameInfo* fr,
+                             unsigned long long* __restrict__ keys) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= Npow) return;
+  keys[n] = n < N ? ((unsigned long long)morton_code(X + n * D, nullptr, D, fr) << 32) | (unsigned long long)n
+                  : ~0ull;
+}
+
+// Components are sorted by (curvature class, Morton code of the mean): a tile bound uses the
+// smallest curvature lambda of its rows, so rows of very different lambda are kept apart. The
+// classes are octave pairs (factor 4 in lambda) below an anchor, the half-octave bin of the 90th
+// percentile of lambda over the components: class 0 holds lambda >= anchor / 4, class 3 the
+// broadest components (and degenerate ones).
+__global__ void k_lam_hist(const double* __restrict__ post, int64_t K, int D, int* __restrict__ hist) {
+  __shared__ int h[LAM_BINS];
+  for (int i = threadIdx.x; i < LAM_BINS; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&h[lam_bin(comp_lambda(post + k * REC, D))], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < LAM_BINS; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+__global__ void k_lam_anchor(int* __restrict__ hist, int64_t K, FrameInfo* fr) {
+  if (threadIdx.x != 0) return;
+  int64_t above = 0;
+  int b = LAM_BINS - 1;
+  for (; b > 0; --b) {
+    above += hist[b];
+    if (above * 10 >= K) break;
+  }
+  fr->lam_anchor = b;
+}
+
+__global__ void k_zero_hist(int* hist) {
+  if (threadIdx.x < LAM_BINS) hist[threadIdx.x] = 0;
+}
+
+__global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t Kpow, int D, const FrameInfo* fr,
+                            unsigned long long* __restrict__ keys) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Kpow) return;
+  if (k >= K) {
+    keys[k] = ~0ull;
+    return;
+  }
+  const double* q = post + k * REC;
+  const int b = lam_bin(comp_lambda(q, D));
+  const int gap = fr->lam_anchor - b;
+  const uint32_t cls = b == 0 ? 3u : (gap < 4 ? 0u : (uint32_t)min(gap / 4, 3));
+  const uint32_t code = (cls << 30) | morton_code(nullptr, q + 3, D, fr);
+  keys[k] = ((unsigned long long)code << 32) | (unsigned long long)k;
+}
+
+// ---- bitonic sort ---------------------------------------------------------------------------
+constexpr int BS_LOCAL = 2048;  // elements per workgroup in the LDS stages (1024 threads)
+
+__device__ __forceinline__ void cmp_swap(unsigned long long& a, unsigned long long& b, bool up) {
+  if ((a > b) == up) {
+    const unsigned long long t = a;
+    a = b;
+    b = t;
+  }
+}
+
+// all stages k <= BS_LOCAL (full sort of each 2048-chunk, alternating directions like the global network)
+__global__ __launch_bounds__(1024) void k_bitonic_local_sort(unsigned long long* keys) {
+  __shared__ unsigned long long s[BS_LOCAL];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * BS_LOCAL;
+  s[t] = keys[base + t];
+  s[t + 1024] = keys[base + t + 1024];
+  __syncthreads();
+  for (int k = 2; k <= BS_LOCAL; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int i = 2 * t - (t & (j - 1));  // lower index of this thread's pair
+      const int64_t gi = base + i;
+      const bool up = (gi & k) == 0;
+      cmp_swap(s[i], s[i + j], up);
+      __syncthreads();
+    }
+  }
+  keys[base + t] = s[t];
+  keys[base + t + 1024] = s[t + 1024];
+}
+
+// stage k > BS_LOCAL, the passes with j < BS_LOCAL inside each chunk
+__global__ __launch_bounds__(1024) void k_bitonic_local_merge(unsigned long long* keys, int64_t k) {
+  __shared__ unsigned long long s[BS_LOCAL];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * BS_LOCAL;
+  s[t] = keys[base + t];
+  s[t + 1024] = keys[base + t + 1024];
+  __syncthreads();
+  for (int j = BS_LOCAL >> 1; j > 0; j >>= 1) {
+    const int i = 2 * t - (t & (j - 1));
+    const bool up = ((base + i) & k) == 0;
+    cmp_swap(s[i], s[i + j], up);
+    __syncthreads();
+  }
+  keys[base + t] = s[t];
+  keys[base + t + 1024] = s[t + 1024];
+}
+
+// one global pass (stage k, distance j >= BS_LOCAL): one thread per pair
+__global__ __launch_bounds__(256) void k_bitonic_global(unsigned long long* keys, int64_t n, int64_t k, int64_t j) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n / 2) return;
+  const int64_t i = 2 * t - (t & (j - 1));
+  const bool up = (i & k) == 0;
+  unsigned long long a = keys[i], b = keys[i + j];
+  if ((a > b) == up) {
+    keys[i] = b;
+    keys[i + j] = a;
+  }
+}
+
+hipError_t launch_sort_keys(unsigned long long* keys, int64_t npow, hipStream_t s) {
+  // npow: a power of two >= BS_LOCAL
+  hipLaunchKernelGGL(k_bitonic_local_sort, dim3((unsigned)(npow / BS_LOCAL)), dim3(1024), 0, s, keys);
+  for (int64_t k = 2 * BS_LOCAL; k <= npow; k <<= 1) {
+    for (int64_t j = k >> 1; j >= BS_LOCAL; j >>= 1)
+      hipLaunchKernelGGL(k_bitonic_global, dim3((unsigned)((npow / 2 + 255) / 256)), dim3(256), 0, s, keys, npow, k,
+                         j);
+    hipLaunchKernelGGL(k_bitonic_local_merge, dim3((unsigned)(npow / BS_LOCAL)), dim3(1024), 0, s, keys, k);
+  }
+  return hipGetLastError();
+}
+
+// sorted keys -> order (sorted position -> index), inverse (index -> sorted position), codes
+__global__ void k_unpack_order(const unsigned long long* __restrict__ keys, int64_t n, int32_t* __restrict__ order,
+                               int32_t* __restrict__ inverse, uint32_t* __restrict__ codes) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const unsigned long long v = keys[j];
+  const int32_t idx = (int32_t)(v & 0xFFFFFFFFull);
+  order[j] = idx;
+  if (inverse) inverse[idx] = (int32_t)j;
+  if (codes) codes[j] = (uint32_t)(v >> 32);
+}
+
+// Per 64-row tile of the sorted component table: G = max g2, Lambda = min lambda (a lower bound on
+// the curvature of the score in the first three raw coordinates), box of those coordinates of the
+// means, and the Morton code of the first row. G and the box are rounded outward, so the bound
+// formed from them in FP32 stays above every score of the tile. Empty (padding) tiles get G = -inf.
+__global__ void k_tile_info(const int32_t* __restrict__ corder, const uint32_t* __restrict__ ccode, int64_t K,
+                            int64_t ntiles, int D, const double* __restrict__ direct, int dts,
+                            const float* __restrict__ lam, TileInfo* __restrict__ info) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  TileInfo ti;
+  ti.G = -INFINITY;
+  ti.Lam = INFINITY;
+  for (int i = 0; i < 3; ++i) {
+    ti.lo[i] = INFINITY;
+    ti.hi[i] = -INFINITY;
+  }
+  const int ns = D < 3 ? D : 3;
+  for (int r = 0; r < CT; ++r) {
+    const int64_t j = t * CT + r;
+    if (j >= K) break;
+    const int64_t k = corder[j];
+    const double* T = direct + k * dts;
+    ti.G = fmaxf(ti.G, f_up(T[0]));
+    ti.Lam = fminf(ti.Lam, lam[k]);
+    for (int i = 0; i < ns; ++i) {
+      ti.lo[i] = fminf(ti.lo[i], f_down(T[1 + i]));
+      ti.hi[i] = fmaxf(ti.hi[i], f_up(T[1 + i]));
+    }
+  }
+  for (int i = ns; i < 3; ++i) {
+    ti.lo[i] = 0.0f;
+    ti.hi[i] = 0.0f;
+  }
+  ti.code = t * CT < K ? ccode[t * CT] : 0xFFFFFFFFu;
+  info[t] = ti;
+}
+
+hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s) {
+  const Layout& L = *d.L;
+  if (N <= 0) return hipSuccess;
+  int64_t npow = BS_LOCAL;
+  while (npow < N) npow <<= 1;
+  unsigned long long* keys = d.at<unsigned long long>(L.pkeys);
+  hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, s, X, N, npow, d.D, d.frame(),
+                     keys);
+  hipError_t e = launch_sort_keys(keys, npow, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, keys, N,
+                     d.at<int32_t>(L.porder), (int32_t*)nullptr, d.at<uint32_t>(L.pcode));
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
+  const Layout& L = *d.L;
+  int64_t kpow = BS_LOCAL;
+  while (kpow < d.K) kpow <<= 1;
+  unsigned long long* keys = d.at<unsigned long long>(L.ckeys);
+  int* hist = d.at<int>(L.lhist);
+  hipLaunchKernelGGL(k_zero_hist, dim3(1), dim3(LAM_BINS), 0, s, hist);
+  hipLaunchKernelGGL(k_lam_hist, dim3(64), dim3(256), 0, s, d.post(), d.K, d.D, hist);
+  hipLaunchKernelGGL(k_lam_anchor, dim3(1), dim3(64), 0, s, hist, d.K, d.frame());
+  hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((kpow + 255) / 256)), dim3(256), 0, s, d.post(), d.K, kpow, d.D,
+                     d.frame(), keys);
+  hipError_t e = launch_sort_keys(keys, kpow, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, keys, d.K,
+                     d.at<int32_t>(L.corder), d.at<int32_t>(L.cinv), d.at<uint32_t>(L.ccode));
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s) {
+  const Layout& L = *d.L;
+  const int64_t ntiles = L.Kpad / CT;
+  hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((ntiles + 127) / 128)), dim3(128), 0, s, d.at<int32_t>(L.corder),
+                     d.at<uint32_t>(L.ccode), d.K, ntiles, d.D, d.at<double>(L.direct), direct_stride(d.D),
+                     d.at<float>(L.lam), d.at<TileInfo>(L.tinfo));
+  return hipGetLastError();
+}
+
+}  // namespace vbgs

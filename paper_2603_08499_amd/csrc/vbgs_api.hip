@@ -120,8 +120,12 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "C must be in 0..64 and train_batch in 0..65536 (0 = default)";
     return VBGS_ERR_ARG;
   }
-  for (int i = 0; i < 5; ++i)
-    if (p->reserved[i] != 0) {
+  if (p->cull != 0 && p->cull != 1) {
+    if (why) *why = "cull must be 0 or 1";
+    return VBGS_ERR_ARG;
+  }
+  for (int i = 0; i < 4; ++i)
+    if (p->reserved[i] != 0 || p->reserved1 != 0) {
       if (why) *why = "reserved fields must be zero";
       return VBGS_ERR_ARG;
     }
@@ -225,6 +229,20 @@ Layout make_layout(const vbgs_params& p) {
   L.coffset = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
   L.ccursor = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
   L.ent_n = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
+  int64_t npow = 2048, kpow = 2048;
+  while (npow < n) npow <<= 1;
+  while (kpow < K) kpow <<= 1;
+  L.pkeys = take(sparse ? (size_t)npow * 8 : 0);
+  L.porder = take(sparse ? (size_t)n * 4 : 0);
+  L.pcode = take(sparse ? (size_t)n * 4 : 0);
+  L.ckeys = take(sparse ? (size_t)kpow * 8 : 0);
+  L.corder = take(sparse ? (size_t)L.Kpad * 4 : 0);
+  L.cinv = take(sparse ? (size_t)L.Kpad * 4 : 0);
+  L.ccode = take(sparse ? (size_t)L.Kpad * 4 : 0);
+  L.lam = take((size_t)L.Kpad * 4);
+  L.tinfo = take(sparse ? (size_t)(L.Kpad / CT) * sizeof(TileInfo) : 0);
+  L.rowb = take(sparse ? (size_t)L.Kpad * sizeof(RowBound) : 0);
+  L.lhist = take(sparse ? (size_t)LAM_BINS * 4 : 0);
   // learned proposal
   const bool pr = p.proposal == 1;
   const int C = p.C > 0 ? p.C : 32;
@@ -284,6 +302,7 @@ vbgs_status vbgs_default_params(vbgs_params* p, int32_t D, int64_t K, int64_t n_
   p->screen_margin = 0.0;
   p->C = 32;
   p->train_batch = 4096;
+  p->cull = 1;
   return VBGS_OK;
 }
 
@@ -386,21 +405,47 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
   return VBGS_OK;
 }
 
+static bool use_cull(const vbgs_ctx* c) {
+  return c->p.score_prec != VBGS_FP64 && c->p.exact == 1 && c->p.cull == 1;
+}
+
+// expectations and coefficient rows; with culling the MFMA rows are written in spatial order and
+// per-tile bounds are built
+static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s) {
+  const DevPtrs d = c->dev();
+  if (!use_cull(c)) return launch_coeffs(d, s);
+  hipError_t e = launch_sort_comps(d, s);
+  if (e == hipSuccess) e = launch_coeffs(d, s, d.at<int32_t>(c->L.cinv));
+  if (e == hipSuccess) e = launch_tile_info(d, s);
+  return e;
+}
+
 static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, void* stream) {
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
+  cfg.cull = use_cull(c) ? 1 : 0;
   hipError_t e;
   {
     Phase ph(c, 0, S(stream));
     e = launch_frame_prep(d, X, N, S(stream));
   }
+  const bool cull = use_cull(c);
   if (e == hipSuccess) {
     Phase ph(c, 1, S(stream));
-    e = launch_coeffs(d, S(stream));
+    e = prepare_components(c, S(stream));
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 8, S(stream));
+    if (cull) e = launch_sort_points(d, X, N, S(stream));
+    if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 0);
   }
   if (e == hipSuccess) {
     Phase ph(c, 2, S(stream));
-    e = launch_pass1(d, cfg, X, N, lse_out, S(stream));
+    e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 1);
+  }
+  if (e == hipSuccess) {
+    Phase ph(c, 9, S(stream));
+    e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 2);
   }
   return hipfail(c, e, "pass 1");
 }
@@ -495,17 +540,19 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* c, void* stream) {
   return hipfail(c, launch_clear_flags(c->dev(), S(stream)), "clear_flags");
 }
 
-vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[4], void* stream) {
+vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[7], void* stream) {
   if (!c || !out) return VBGS_ERR_ARG;
-  unsigned long long v[2] = {0, 0};
+  FrameInfo f;
   hipError_t e = hipStreamSynchronize(S(stream));
-  if (e == hipSuccess)
-    e = hipMemcpy(v, (char*)c->ws + c->L.frame + offsetof(FrameInfo, refined1), sizeof v, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&f, (char*)c->ws + c->L.frame, sizeof f, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hipfail(c, e, "counters");
-  out[0] = (int64_t)v[0];
-  out[1] = (int64_t)v[1];
+  out[0] = (int64_t)f.refined1;
+  out[1] = (int64_t)f.refined2;
   out[2] = c->last_N;
   out[3] = c->p.K;
+  out[4] = (int64_t)f.blocks;
+  out[5] = c->last_N > 0 ? (c->last_N + P1_PTS - 1) / P1_PTS * (P1_PTS / 64) * (c->L.Kpad / 16) : 0;
+  out[6] = (int64_t)f.blocks_cum;
   return VBGS_OK;
 }
 
@@ -625,9 +672,11 @@ vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* c, const float* X, int64_t N, cons
     Phase ph(c, 0, s);
     e = launch_frame_prep(d, X, N, s);
   }
+  const bool cull = use_cull(c);
+  cfg.cull = cull ? 1 : 0;
   if (e == hipSuccess) {
     Phase ph(c, 1, s);
-    e = launch_coeffs(d, s);
+    e = prepare_components(c, s);
   }
   PArgs pa = make_pargs(c);
   if (e == hipSuccess && !c->prop_prepared) {
@@ -650,10 +699,11 @@ vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* c, const float* X, int64_t N, cons
     if (e == hipSuccess)
       e = launch_audit(ea, c->p.D, audit_idx, n_audit, reinterpret_cast<double*>((char*)c->ws + c->L.p_aud),
                        ea.lse2, logmass_bound, frac_bound, gate, report, s);
+    if (e == hipSuccess && cull) e = launch_sort_points(d, X, N, s);  // (cheap; only used on fallback)
     if (e == hipSuccess) {  // dense exact E-step, executed only when the audit failed
       EArgs eg = ea;
       eg.gate = gate;
-      e = launch_exact_sweep(eg, c->p.score_prec, c->p.D, N, s);
+      e = launch_exact_sweep(eg, c->p.score_prec, c->p.D, N, s, cull ? 1 : 0);
     }
   }
   if (e == hipSuccess) {

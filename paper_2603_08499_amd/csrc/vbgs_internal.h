@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cfloat>
+
 #include "../../include/vbgs.h"
 
 namespace vbgs {
@@ -45,9 +47,59 @@ struct FrameInfo {
   int32_t pad0;
   unsigned long long refined1, refined2;
   int32_t n_over;        // points whose candidate lists overflowed in the sweep
-  int32_t pad2;
-  double pad1[3];
+  int32_t lam_anchor;    // curvature class anchor of the component sort (bin of lambda, see lam_bin)
+  unsigned long long blocks;      // 64-point x 64-component blocks screened by the exact sweep
+  unsigned long long blocks_cum;  // the same, summed since the last clear of the flags
+  double pad1[1];
 };
+
+// Bound of a 64-row tile of the spatially sorted component table (culled exact sweep).
+struct TileInfo {
+  float G;          // max over the tile of the score constant g2 (log2 units)
+  float Lam;        // min over the tile of lambda_k: s2 <= g2 - lambda_k |x_S - m_k,S|^2
+  float lo[3], hi[3];  // box of the means in the first min(D, 3) raw coordinates
+  uint32_t code;    // Morton code of the tile's first row
+  uint32_t pad;
+};
+
+// Bound of one row of the sorted component table: s2 <= G - Lam |x_S - m_S|^2 (m rounded to
+// nearest), and the norm of the row's expanded coefficients (the screen's error scale)
+struct RowBound {
+  float G, Lam;
+  float m[3];
+  float nc;
+  float pad[2];
+};
+
+// float roundings of a double that stay below / above it
+__device__ __forceinline__ float f_down(double v) {
+  float f = (float)v;
+  return (double)f > v ? nextafterf(f, -INFINITY) : f;
+}
+__device__ __forceinline__ float f_up(double v) {
+  float f = (float)v;
+  return (double)f < v ? nextafterf(f, INFINITY) : f;
+}
+
+// lambda_k, a lower bound on the curvature of the score (log2 units) in the first min(D, 3)
+// raw coordinates: s2 = g2 - (nu log2e / 2) d^T W d and, with d restricted to those coordinates
+// S, d^T W d >= d_S^T ((W^-1)_SS)^-1 d_S >= |d_S|^2 / tr (W^-1)_SS. Slightly reduced so that its
+// FP32 rounding stays below the bound. q: the component's record (alpha, kappa, nu, m, packed
+// upper triangle of W^-1). Returns 0 when the trace is not positive.
+__device__ __forceinline__ float comp_lambda(const double* q, int D) {
+  const int ns = D < 3 ? D : 3;
+  double tr = 0.0;
+  for (int i = 0; i < ns; ++i) tr += q[3 + D + i * D - i * (i - 1) / 2];
+  return tr > 0.0 ? (float)(0.5 * q[2] * LOG2E / tr * (1.0 - 1e-6)) : 0.0f;
+}
+
+// histogram bin of lambda in half-octaves, 0..127 (lambda <= 0 maps to bin 0)
+constexpr int LAM_BINS = 128;
+__device__ __forceinline__ int lam_bin(float lam) {
+  if (!(lam > 0.0f)) return 0;
+  const int b = (int)floorf(2.0f * log2f(lam)) + 64;
+  return b < 0 ? 0 : (b > LAM_BINS - 1 ? LAM_BINS - 1 : b);
+}
 
 // Offsets (bytes) into the caller's workspace.
 struct Layout {
@@ -55,6 +107,8 @@ struct Layout {
       spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ccursor, ent_n, total;
   int64_t Kpad, n_lse_part;
   int nsplit_max;
+  // spatial ordering (culled exact sweep)
+  size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, lhist;
   // learned proposal (workspace)
   size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
       p_tdh2, p_tdp1, p_th2b, p_th2T, p_tloss, p_grads;
@@ -211,12 +265,15 @@ struct Init0 {
 
 hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& init, hipStream_t s);
 hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
-hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s);
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv = nullptr);
 hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s);
 hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStream_t s);
 hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, double* kappa, double* m,
                           double* Winv, double* nu, hipStream_t s);
 hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s);
+hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
+hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s);
+hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s);
 
 struct EstepCfg {
   int prec;      // vbgs_prec
@@ -224,6 +281,7 @@ struct EstepCfg {
   float T2;      // screen margin in log2 units
   int nsplit;    // pass-2 point splits
   const int32_t* gate = nullptr;  // device flag gating the exact dense kernels (proposal fallback)
+  int cull = 0;                   // culled sweep over spatially sorted points and components
 };
 
 struct EArgs {
@@ -252,17 +310,24 @@ struct EArgs {
   int32_t* ent_n;             // kept pairs grouped by component: point index
   FrameInfo* frame;
   const int32_t* gate;        // when set, the exact dense kernels run only if gate[0] != 0
+  const int32_t* porder;      // culled sweep: sorted position -> point index
+  const uint32_t* pcode;      // Morton codes of the sorted points
+  const int32_t* corder;      // sorted row -> component index
+  const TileInfo* tinfo;      // per-tile bounds of the sorted component table
+  const RowBound* rowb;       // per-row bounds of the sorted component table
   int64_t N, K, Kpad;
   int D, dts, nsplit;
   float T2, eps;
 };
 EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out);
+// stage -1: the whole first pass; exact MFMA mode in stages 0 (clear the transpose counters),
+// 1 (the screening sweep) and 2 (exact per-point LSE); other modes run everything in stage 1
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
-                        hipStream_t s);
+                        hipStream_t s, int stage = -1);
 hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s);
 hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, hipStream_t s);
 // exact statistics from candidate lists (transpose + per-component sums) and exact per-point LSE
-hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s);
+hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull = 0);
 hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s);
 hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s);
 

@@ -29,7 +29,7 @@ def _stream(s=None):
 
 
 def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x3", exact=True,
-                screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096):
+                screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096, cull=True):
     p = _lib.Params()
     L = _lib.load()
     st = L.vbgs_default_params(ctypes.byref(p), int(D), int(K), int(n_max))
@@ -45,6 +45,7 @@ def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x
     p.proposal = 1 if proposal else 0
     p.C = int(C)
     p.train_batch = int(train_batch)
+    p.cull = 1 if cull else 0
     return p
 
 
@@ -153,9 +154,10 @@ class VBGS:
         self._check(self.lib.vbgs_clear_flags(self.ctx, _stream()))
 
     def counters(self):
-        out = (ctypes.c_int64 * 4)()
+        out = (ctypes.c_int64 * 7)()
         self._check(self.lib.vbgs_counters(self.ctx, out, _stream()))
-        return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3])
+        return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3], blocks=out[4],
+                    blocks_dense=out[5], blocks_cum=out[6])
 
     # ---- learned candidate proposal -----------------------------------------------------
     def _f32(self, a):

@@ -69,7 +69,7 @@ def test_params_struct_layout_matches_header():
     P = L.Params
     assert ctypes.sizeof(P) == 120
     assert P.screen_margin.offset == 56 and P.n_split.offset == 64 and P.proposal.offset == 68
-    assert P.C.offset == 72 and P.train_batch.offset == 76 and P.reserved.offset == 80
+    assert P.C.offset == 72 and P.train_batch.offset == 76 and P.cull.offset == 80 and P.reserved.offset == 88
 
 
 def test_null_context_calls_fail_cleanly():

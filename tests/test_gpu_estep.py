@@ -56,7 +56,7 @@ def _set(m, which, nw):
 
 @gpu
 @pytest.mark.parametrize("prec,exact", EXACT_TIERS)
-@pytest.mark.parametrize("N,K,D", [(3001, 301, 6), (777, 90, 5), (1000, 1, 6)])
+@pytest.mark.parametrize("N,K,D", [(3001, 301, 6), (777, 90, 5), (1000, 1, 6), (1500, 120, 2)])
 def test_estep_parity_exact(dev, prec, exact, N, K, D):
     print("case", prec, N, K, D, flush=True)
     X, pr = scenes.random_problem(N, K, D, seed=N + K)
@@ -273,3 +273,35 @@ def test_candidate_overflow_fallback(dev):
     es = _stat_err(ref, st.cpu().numpy(), D)
     print("overflow case: max|dLSE| %.2e stats relerr %.2e" % (dl, es), m.counters())
     assert dl < 2e-6 and es < 1e-9
+
+
+@gpu
+@pytest.mark.parametrize("case", ["c3_slice", "random"])
+def test_cull_matches_unculled(dev, case):
+    """Tile culling over spatially sorted points and components drops only pairs the per-pair
+    screen would drop, so culled and unculled sweeps agree to FP64 rounding (each is also
+    checked against the oracle elsewhere)."""
+    print("cull case", case, flush=True)
+    if case == "c3_slice":
+        scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
+        X0 = scenes.c3_frame(0, scene=scene)
+        pr = scenes.c3_prior(X0)
+        X = np.ascontiguousarray(X0[100000:140000])
+    else:
+        X, pr = scenes.random_problem(20000, 2000, 6, seed=77)
+    Xd = torch.from_numpy(X).to(dev)
+    out = []
+    for cull in (0, 1):
+        m = _model(dev, pr, X.shape[0], "bf16x3", True, cull=cull)
+        lse, st = m.estep_stats(Xd)
+        F = m.elbo()
+        torch.cuda.synchronize()
+        assert m.sync_status() == 0
+        out.append((lse.cpu().numpy(), st.cpu().numpy(), F.item(), m.counters()))
+        m.close()
+    (l0, s0, F0, c0), (l1, s1, F1, c1) = out
+    dl = np.abs(l0 - l1).max()
+    es = _stat_err(s0, s1, 6)
+    print("  culled vs unculled: max|dLSE| %.2e stats relerr %.2e dF %.2e" % (dl, es, abs(F0 - F1)),
+          "counters unculled", c0, "culled", c1)
+    assert dl < 1e-9 and es < 1e-9 and abs(F0 - F1) <= 1e-11 * abs(F0)
