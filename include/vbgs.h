@@ -165,8 +165,9 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
  * (within the margin of their point's LSE), out[2] = number of points, out[3] = K,
  * out[4] = blocks of 64 points x 16 components the sweep screened on MFMA, out[5] = the
  * number of such blocks without culling (4 per 256-point workgroup and 16 components), out[6] =
- * the blocks screened by all E-steps since vbgs_init or the last vbgs_clear_flags. */
-vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[7], void* stream);
+ * the blocks screened by all E-steps since vbgs_init or the last vbgs_clear_flags, out[7] = the
+ * points whose candidate lists overflowed (their LSE and statistics come from a full rescan). */
+vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[8], void* stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each call.
  * Phases: 0 frame moments + features, 1 expectations + coefficient rows (with culling also the

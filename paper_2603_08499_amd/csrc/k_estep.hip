@@ -356,8 +356,9 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
 //   row k:   G_k - lambda_k |x_S - m_k,S|^2       (RowBound)
 // A pair whose bound lies below the point's running lower bound M minus the margin T is one the
 // per-pair screen would drop, so it is never screened. Each wave works on its own:
-//   1. pilot: its seed tiles (those around the Morton positions of its first and last point)
-//      are screened without recording, which brings every M close to its final value;
+//   1. pilot: its seed tiles (in each curvature class, those around the Morton positions of its
+//      first and last point) are screened without recording, which brings every M close to its
+//      final value;
 //   2. the seed tiles again, now recording candidates;
 //   3. every other tile, 64 at a time (one per lane): a tile is screened when its bound reaches
 //      M - T for at least one point of the wave; within it, a 16-row block is screened when one
@@ -374,22 +375,39 @@ __device__ __forceinline__ float box_d2(const TileInfo& t, const float* lo, cons
   return d2;
 }
 
-// last tile whose first code is <= code (0 when there is none): a 64-way search, one probe per lane
-__device__ __forceinline__ int64_t find_tile(const TileInfo* __restrict__ ti, int64_t ntiles, uint32_t code,
-                                             int lane) {
+// Eight searches at once, one per group of eight lanes (lane >> 3 = q): the last tile whose
+// first code is <= code_q (0 when there is none), eight probes per group and step.
+__device__ __forceinline__ int64_t find_tiles8(const TileInfo* __restrict__ ti, int64_t ntiles, uint32_t code,
+                                               int lane) {
+  const int q = lane >> 3, r = lane & 7;
   int64_t L = 0, R = ntiles - 1;
-  while (L < R) {
+  for (;;) {
+    const bool active = L < R;
+    if (__ballot(active) == 0ull) break;
     const int64_t span = R - L + 1;
-    const int64_t pos = L + span * lane / 64;
-    const unsigned long long m = __ballot(ti[pos].code <= code);
-    if (m == 0ull) return L;  // only when L = 0 and code is below the first tile's
-    const int last = 63 - __clzll(m);
-    const int64_t nl = L + span * last / 64;
-    const int64_t nr = last == 63 ? R : L + span * (last + 1) / 64 - 1;
-    L = nl;
-    R = nr > nl ? nr : nl;
+    const int64_t pos = L + span * r / 8;
+    const bool le = active && ti[pos].code <= code;
+    const unsigned gm = (unsigned)(__ballot(le) >> (8 * q)) & 0xFFu;
+    if (active) {
+      if (gm == 0u) {
+        R = L;  // only when L = 0 and code is below the first tile's
+      } else {
+        const int last = 31 - __clz(gm);
+        const int64_t nl = L + span * last / 8;
+        const int64_t nr = last == 7 ? R : L + span * (last + 1) / 8 - 1;
+        L = nl;
+        R = nr > nl ? nr : nl;
+      }
+    }
   }
   return L;
+}
+
+// Workgroups are dealt to the eight XCDs in turn; renumber them so that each XCD takes one
+// contiguous range of the Morton order, whose component tiles then stay in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b % 8, q = b / 8, per = nb / 8, rem = nb % 8;
+  return x * per + (x < rem ? x : rem) + q;
 }
 
 template <int P>
@@ -467,13 +485,15 @@ __device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int
 }
 
 template <int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep(const EArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep(const EArgs a) {
+  // one wave per workgroup, so that a finished wave frees its slot at once
   if (a.gate && a.gate[0] == 0) return;
-  __shared__ float4 pts[4][64];   // per wave: first three raw coordinates of its points
-  __shared__ float mvs[4][64];    // their current lower bounds M (+inf for empty slots)
-  __shared__ int32_t pids[4][64]; // their original indices
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
-  const int64_t j0 = (int64_t)blockIdx.x * P1_PTS + w * (P1_PB * 16);  // sorted positions
+  __shared__ float4 pts[1][64];   // first three raw coordinates of the wave's points
+  __shared__ float mvs[1][64];    // their current lower bounds M (+inf for empty slots)
+  __shared__ int32_t pids[1][64]; // their original indices
+  __shared__ int32_t seeds[1][24];
+  const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
+  const int64_t j0 = xcd_block(blockIdx.x, gridDim.x) * (P1_PB * 16);  // sorted positions
   const int ns = a.D < 3 ? a.D : 3;
   float* mv = mvs[w];
   const int32_t* pid = pids[w];
@@ -523,45 +543,72 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __builtin_amdgcn_wave_barrier();
   if (j0 < a.N) {
     const int64_t ntiles = a.Kpad / CT;
-    // seeds: tiles around the Morton positions of the wave's first and last point
+    // seeds: in each curvature class, the tiles around the Morton positions of the wave's first
+    // and last point (eight centres c_q, q = 2 class + end)
     const int64_t jl = min(j0 + 63, a.N - 1);
-    const int64_t tf = find_tile(a.tinfo, ntiles, a.pcode[j0], lane);
-    const int64_t tl = find_tile(a.tinfo, ntiles, a.pcode[jl], lane);
-    const bool span = tl - tf <= 6;
-    auto is_seed = [&](int64_t t) {
-      return (t >= tf - 1 && t <= tf + 1) || (t >= tl - 1 && t <= tl + 1) || (span && t >= tf && t <= tl);
+    const int qq = lane >> 3;
+    const uint32_t pc = a.pcode[(qq & 1) ? jl : j0] & 0x3FFFFFFFu;
+    const int32_t cen = (int32_t)find_tiles8(a.tinfo, ntiles, ((uint32_t)(qq >> 1) << 30) | pc, lane);
+    int32_t cq[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cq[q] = __builtin_amdgcn_readfirstlane(__shfl(cen, 8 * q));
+    auto near_centre = [&](int64_t t, int upto) {
+      bool r = false;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) r |= q < upto && t >= cq[q] - 1 && t <= cq[q] + 1;
+      return r;
     };
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int64_t t = max(tf - 1, (int64_t)0); t <= min(tl + 1, ntiles - 1); ++t)
-        if (is_seed(t)) screen_tile<P>(a, S, t, pass == 1, lane, mv, pid);
-    }
-    const float margin = a.T2 + 1.0f;
-    for (int64_t base = 0; base < ntiles; base += 64) {
-      const int64_t t = base + lane;
-      bool need = false;
-      if (t < ntiles && !is_seed(t)) {
-        const TileInfo ti = a.tinfo[t];
-        float mw = INFINITY;
+    int nseed = 0;
 #pragma unroll
-        for (int b = 0; b < P1_PB; ++b)
-          if (S.val[b]) mw = fminf(mw, S.M[b]);
-        for (int o = 1; o < 64; o <<= 1) mw = fminf(mw, __shfl_xor(mw, o));
-        if (ti.G - ti.Lam * box_d2(ti, S.lo, S.hi) >= mw - margin) {
-          // some point of the wave within reach of this tile
-          for (int q = 0; q < 64 && !need; ++q) {
-            const float4 x = pts[w][q];
-            float d2 = 0.0f;
-            const float xq[3] = {x.x, x.y, x.z};
+    for (int q = 0; q < 8; ++q)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-              const float gap = fmaxf(fmaxf(ti.lo[i] - xq[i], xq[i] - ti.hi[i]), 0.0f);
-              d2 = fmaf(gap, gap, d2);
-            }
-            need = ti.G - ti.Lam * d2 >= mv[q] - margin;
-          }
+      for (int d = -1; d <= 1; ++d) {
+        const int64_t t = (int64_t)cq[q] + d;
+        if (t >= 0 && t < ntiles && !near_centre(t, q)) {
+          if (lane == 0) seeds[w][nseed] = (int32_t)t;
+          ++nseed;
         }
       }
-      unsigned long long m = __ballot(need);
+    __builtin_amdgcn_wave_barrier();
+    for (int i = 0; i < 2 * nseed; ++i) {
+      const int64_t t = __builtin_amdgcn_readfirstlane(seeds[w][i % nseed]);
+      screen_tile<P>(a, S, t, i >= nseed, lane, mv, pid);
+    }
+    const float margin = a.T2 + 1.0f;
+    const float4 xme = pts[w][lane];  // this lane's point (lane = point of the wave)
+    for (int64_t base = 0; base < ntiles; base += 64) {
+      // lane = tile: the wave's box against the tile bound
+      const int64_t t = base + lane;
+      float mw = INFINITY;
+#pragma unroll
+      for (int b = 0; b < P1_PB; ++b)
+        if (S.val[b]) mw = fminf(mw, S.M[b]);
+      for (int o = 1; o < 64; o <<= 1) mw = fminf(mw, __shfl_xor(mw, o));
+      TileInfo ti{};
+      bool cand = false;
+      if (t < ntiles && !near_centre(t, 8)) {
+        ti = a.tinfo[t];
+        cand = ti.G - ti.Lam * box_d2(ti, S.lo, S.hi) >= mw - margin;
+      }
+      // lane = point: each candidate tile against every point's own bound and M
+      const float thr_me = mv[lane] - margin;
+      unsigned long long cm = __ballot(cand), m = 0ull;
+      while (cm) {
+        const int i = __ffsll((long long)cm) - 1;
+        cm &= cm - 1ull;
+        const float tG = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ti.G), i));
+        const float tL = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ti.Lam), i));
+        const float xq[3] = {xme.x, xme.y, xme.z};
+        float d2 = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const float tlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ti.lo[q]), i));
+          const float thi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ti.hi[q]), i));
+          const float gap = fmaxf(fmaxf(tlo - xq[q], xq[q] - thi), 0.0f);
+          d2 = fmaf(gap, gap, d2);
+        }
+        if (__ballot(tG - tL * d2 >= thr_me) != 0ull) m |= 1ull << i;
+      }
       while (m) {
         const int i = __ffsll((long long)m) - 1;
         m &= m - 1ull;
@@ -577,7 +624,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (S.val[b]) {
       const int32_t p = pid[16 * b + c];
       a.cand_n[(int64_t)p * 4 + g] = o ? -1 : S.cn[b];
-      if (o && g == 0) a.over_list[atomicAdd(&a.frame->n_over, 1)] = p;
+      if (o && g == 0) {
+        a.over_list[atomicAdd(&a.frame->n_over, 1)] = p;
+        a.lse2[p] = (double)S.M[b];  // lower bound on the point's largest score, for the rescan's culling
+      }
     }
   }
   count_refined(&a.frame->refined1, S.nref);
@@ -775,6 +825,52 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
 }
 
 // ---- overflowed points: exact LSE over all K (one workgroup per point) --------------------------
+// After the culled sweep the rescan visits only the rows whose bound reaches thr (the sweep's
+// lower bound on the point's largest score minus the margin; tiles first, then rows); without
+// culling it scores every component.
+__device__ __forceinline__ float point_tile_d2(const TileInfo& t, const float* x3) {
+  float d2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float gap = fmaxf(fmaxf(t.lo[i] - x3[i], x3[i] - t.hi[i]), 0.0f);
+    d2 = fmaf(gap, gap, d2);
+  }
+  return d2;
+}
+
+__device__ __forceinline__ float point_row_d2(const RowBound& r, const float* x3) {
+  float d2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float gap = fmaxf(fabsf(x3[i] - r.m[i]) - fabsf(r.m[i]) * 2.384185791015625e-7f, 0.0f);
+    d2 = fmaf(gap, gap, d2);
+  }
+  return d2;
+}
+
+// call f(k) for every component whose bound with x reaches thr (culled) or for every component
+template <int DT, typename F>
+__device__ __forceinline__ void over_rows(const EArgs& a, const float* x, float thr, F&& f) {
+  if (a.cull) {
+    float x3[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x3[i] = i < DT ? x[i] : 0.0f;
+    const int64_t ntiles = a.Kpad / CT;
+    for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+      const TileInfo ti = a.tinfo[t];
+      if (ti.G - ti.Lam * point_tile_d2(ti, x3) < thr) continue;
+      for (int r = 0; r < CT; ++r) {
+        const int64_t row = t * CT + r;
+        if (row >= a.K) break;
+        const RowBound rb = a.rowb[row];
+        if (rb.G - rb.Lam * point_row_d2(rb, x3) >= thr) f((int64_t)a.corder[row]);
+      }
+    }
+  } else {
+    for (int64_t k = threadIdx.x; k < a.K; k += blockDim.x) f(k);
+  }
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_over_lse(const EArgs a) {
   __shared__ double sm[256], sl[256];
@@ -784,10 +880,11 @@ __global__ __launch_bounds__(256) void k_over_lse(const EArgs a) {
     const int64_t p = a.over_list[i];
     const float* x = a.X + p * DT;
     double m = -INFINITY, l = 0.0;
-    for (int64_t k = threadIdx.x; k < a.K; k += 256) {
+    const float thr = a.cull ? (float)a.lse2[p] - a.T2 - 1.0f : 0.0f;
+    over_rows<DT>(a, x, thr, [&](int64_t k) {
       double d[DT];
       online_add(m, l, direct_score2_dt<DT>(a.direct + k * a.dts, x, d));
-    }
+    });
     sm[threadIdx.x] = m;
     sl[threadIdx.x] = l;
     __syncthreads();
@@ -816,37 +913,84 @@ __global__ __launch_bounds__(256) void k_over_stats(const EArgs a) {
     const int64_t p = a.over_list[i];
     const double L2 = a.lse2[p];
     const float* x = a.X + p * DT;
-    for (int64_t k = threadIdx.x; k < a.K; k += 256) {
+    over_rows<DT>(a, x, (float)L2 - a.T2 - 1.0f, [&](int64_t k) {
       double d[DT];
       const double s2 = direct_score2_dt<DT>(a.direct + k * a.dts, x, d);
       if (s2 >= L2 - (double)a.T2) fx_pair<DT>(a.fx, k, exp2(s2 - L2), d, is);
-    }
+    });
   }
 }
 
 // ---- transpose of the kept pairs: exclusive scan of the per-component counts (one workgroup) ----
-__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t* __restrict__ cnt, int32_t* __restrict__ off,
-                                                      int64_t K) {
-  __shared__ int32_t part[1024];
+// exclusive scan of the per-component pair counts (off[K] = total) in three coalesced steps:
+// block sums, a scan of the block sums, and the local scans with their block offsets
+constexpr int SCAN_B = 1024;
+__global__ __launch_bounds__(256) void k_scan_blocks(const int32_t* __restrict__ cnt, int64_t K,
+                                                     int32_t* __restrict__ bsum) {
+  __shared__ int32_t red[256];
   const int t = threadIdx.x;
-  const int64_t per = (K + 1023) / 1024;
-  const int64_t a0 = t * per, a1 = min(K, a0 + per);
-  int32_t sum = 0;
-  for (int64_t k = a0; k < a1; ++k) sum += cnt[k];
-  part[t] = sum;
+  const int64_t k0 = (int64_t)blockIdx.x * SCAN_B + 4 * t;
+  int32_t v = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v += k0 + i < K ? cnt[k0 + i] : 0;
+  red[t] = v;
   __syncthreads();
-  for (int w = 1; w < 1024; w <<= 1) {  // inclusive Hillis-Steele scan
-    const int32_t v = t >= w ? part[t - w] : 0;
-    __syncthreads();
-    part[t] += v;
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
     __syncthreads();
   }
-  int32_t run = part[t] - sum;
-  for (int64_t k = a0; k < a1; ++k) {
-    off[k] = run;
-    run += cnt[k];
+  if (t == 0) bsum[blockIdx.x] = red[0];
+}
+
+__device__ __forceinline__ int32_t block_excl_scan256(int32_t v, int32_t* sh, int32_t& total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 1; w < 256; w <<= 1) {
+    const int32_t u = t >= w ? sh[t - w] : 0;
+    __syncthreads();
+    sh[t] += u;
+    __syncthreads();
   }
-  if (t == 1023) off[K] = part[1023];
+  total = sh[255];
+  const int32_t r = sh[t] - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tops(int32_t* __restrict__ bsum, int64_t nb, int32_t* __restrict__ off,
+                                                   int64_t K) {
+  __shared__ int32_t sh[256];
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    const int64_t b = b0 + threadIdx.x;
+    const int32_t v = b < nb ? bsum[b] : 0;
+    int32_t total;
+    const int32_t e = block_excl_scan256(v, sh, total);
+    if (b < nb) bsum[b] = carry + e;
+    carry += total;
+  }
+  if (threadIdx.x == 0) off[K] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ cnt, int64_t K,
+                                                    const int32_t* __restrict__ bsum, int32_t* __restrict__ off) {
+  __shared__ int32_t sh[256];
+  const int t = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * SCAN_B + 4 * t;
+  int32_t c[4], v = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    c[i] = k0 + i < K ? cnt[k0 + i] : 0;
+    v += c[i];
+  }
+  int32_t total;
+  int32_t run = bsum[blockIdx.x] + block_excl_scan256(v, sh, total);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (k0 + i < K) off[k0 + i] = run;
+    run += c[i];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
@@ -1086,9 +1230,10 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
   } else if (stage == 1) {
     const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
     if (cull) {
-      if (prec == VBGS_FP32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), grid, dim3(256), 0, s, a);
-      else if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), grid, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), grid, dim3(256), 0, s, a);
+      const dim3 gw((unsigned)((N + 63) / 64));  // one 64-point wave per workgroup
+      if (prec == VBGS_FP32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), gw, dim3(64), 0, s, a);
+      else if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), gw, dim3(64), 0, s, a);
+      else hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), gw, dim3(64), 0, s, a);
     } else if (prec == VBGS_FP32) {
       hipLaunchKernelGGL((k_pass1<VBGS_FP32, true>), grid, dim3(256), 0, s, a);
     } else if (prec == VBGS_BF16) {
@@ -1101,7 +1246,7 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     switch (D) {
 #define VB_LSE(DD)                                                    \
   case DD:                                                            \
-    hipLaunchKernelGGL(k_over_lse<DD>, dim3(64), dim3(256), 0, s, a); \
+    hipLaunchKernelGGL(k_over_lse<DD>, dim3(256), dim3(256), 0, s, a); \
     hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, a);      \
     break;
       VB_LSE(1) VB_LSE(2) VB_LSE(3) VB_LSE(4) VB_LSE(5) VB_LSE(6)
@@ -1146,11 +1291,15 @@ hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) 
   if (N > 0) {
     const dim3 gp((unsigned)((N + 255) / 256));
     const dim3 gk((unsigned)((a.K + 127) / 128));
+    const int64_t nsb = (a.K + SCAN_B - 1) / SCAN_B;
     switch (D) {
 #define VB_ST(DD)                                                                         \
   case DD:                                                                                \
-    hipLaunchKernelGGL(k_over_stats<DD>, dim3(64), dim3(256), 0, s, a);                   \
-    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, a.ccount, a.coffset, a.K); \
+    hipLaunchKernelGGL(k_over_stats<DD>, dim3(256), dim3(256), 0, s, a);                  \
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part); \
+    hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(256), 0, s, a.scan_part, nsb, a.coffset, a.K);         \
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part,   \
+                       a.coffset);                                                                       \
     hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                          \
     hipLaunchKernelGGL(k_comp_stats<DD>, gk, dim3(128), 0, s, a);                         \
     break;
@@ -1199,6 +1348,7 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.corder = d.at<int32_t>(L.corder);
   a.tinfo = d.at<TileInfo>(L.tinfo);
   a.rowb = d.at<RowBound>(L.rowb);
+  a.scan_part = d.at<int32_t>(L.scan_part);
   a.N = N;
   a.K = d.K;
   a.Kpad = L.Kpad;
@@ -1206,6 +1356,7 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.dts = direct_stride(d.D);
   a.nsplit = c.nsplit;
   a.T2 = c.T2;
+  a.cull = c.cull;
   a.eps = screen_eps(c.prec);
   return a;
 }

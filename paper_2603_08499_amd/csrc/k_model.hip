@@ -149,21 +149,43 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ X, i
   nphi[n] = (float)(sqrt(nn) * (1.0 + 1e-6));
 }
 
-// sum of alpha over the posterior and the frame prior (fixed-order tree)
-__global__ __launch_bounds__(1024) void k_alpha_sums(const double* __restrict__ prior,
-                                                     const double* __restrict__ post, int64_t K,
-                                                     FrameInfo* fr) {
-  __shared__ double sq[1024], sp[1024];
+// sum of alpha over the posterior and the frame prior: per-block partial sums over fixed ranges,
+// then a fixed-order tree over the partials (deterministic)
+constexpr int ALPHA_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_alpha_part(const double* __restrict__ prior, const double* __restrict__ post,
+                                                    int64_t K, double* __restrict__ part) {
+  __shared__ double sq[256], sp[256];
   const int t = threadIdx.x;
+  const int64_t per = (K + ALPHA_BLOCKS - 1) / ALPHA_BLOCKS;
+  const int64_t k0 = blockIdx.x * per, k1 = min(K, k0 + per);
   double a = 0.0, b = 0.0;
-  for (int64_t k = t; k < K; k += 1024) {
+  for (int64_t k = k0 + t; k < k1; k += 256) {
     a += post[k * REC];
     b += prior[k * REC];
   }
   sq[t] = a;
   sp[t] = b;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      sq[t] += sq[t + w];
+      sp[t] += sp[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blockIdx.x] = sq[0];
+    part[2 * blockIdx.x + 1] = sp[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_alpha_final(const double* __restrict__ part, FrameInfo* fr) {
+  __shared__ double sq[256], sp[256];
+  const int t = threadIdx.x;
+  sq[t] = part[2 * t];
+  sp[t] = part[2 * t + 1];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
     if (t < w) {
       sq[t] += sq[t + w];
       sp[t] += sp[t + w];
@@ -383,7 +405,9 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
 
 hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
   const Layout& L = *d.L;
-  hipLaunchKernelGGL(k_alpha_sums, dim3(1), dim3(1024), 0, s, d.prior(), d.post(), d.K, d.frame());
+  double* apart = d.at<double>(L.mom_part);  // free again once the frame moments are final
+  hipLaunchKernelGGL(k_alpha_part, dim3(ALPHA_BLOCKS), dim3(256), 0, s, d.prior(), d.post(), d.K, apart);
+  hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(256), 0, s, apart, d.frame());
   CoefOut o{d.K, cinv, cinv ? d.at<RowBound>(L.rowb) : nullptr, d.at<float>(L.lam), d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch),
             d.at<uint16_t>(L.cl), d.at<float>(L.nc), d.at<double>(L.kl)};
   const dim3 grid((unsigned)((L.Kpad + 127) / 128)), blk(128);

@@ -176,37 +176,55 @@ __global__ void k_unpack_order(const unsigned long long* __restrict__ keys, int6
 // the curvature of the score in the first three raw coordinates), box of those coordinates of the
 // means, and the Morton code of the first row. G and the box are rounded outward, so the bound
 // formed from them in FP32 stays above every score of the tile. Empty (padding) tiles get G = -inf.
-__global__ void k_tile_info(const int32_t* __restrict__ corder, const uint32_t* __restrict__ ccode, int64_t K,
-                            int64_t ntiles, int D, const double* __restrict__ direct, int dts,
-                            const float* __restrict__ lam, TileInfo* __restrict__ info) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ corder,
+                                                   const uint32_t* __restrict__ ccode, int64_t K, int64_t ntiles,
+                                                   int D, const double* __restrict__ direct, int dts,
+                                                   const float* __restrict__ lam, TileInfo* __restrict__ info) {
+  // one wave per tile, lane = row
+  const int lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
-  TileInfo ti;
-  ti.G = -INFINITY;
-  ti.Lam = INFINITY;
-  for (int i = 0; i < 3; ++i) {
-    ti.lo[i] = INFINITY;
-    ti.hi[i] = -INFINITY;
-  }
+  const int64_t j = t * CT + lane;
   const int ns = D < 3 ? D : 3;
-  for (int r = 0; r < CT; ++r) {
-    const int64_t j = t * CT + r;
-    if (j >= K) break;
+  float G = -INFINITY, Lm = INFINITY, lo[3], hi[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    lo[i] = INFINITY;
+    hi[i] = -INFINITY;
+  }
+  if (j < K) {
     const int64_t k = corder[j];
     const double* T = direct + k * dts;
-    ti.G = fmaxf(ti.G, f_up(T[0]));
-    ti.Lam = fminf(ti.Lam, lam[k]);
-    for (int i = 0; i < ns; ++i) {
-      ti.lo[i] = fminf(ti.lo[i], f_down(T[1 + i]));
-      ti.hi[i] = fmaxf(ti.hi[i], f_up(T[1 + i]));
+    G = f_up(T[0]);
+    Lm = lam[k];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (i < ns) {
+        lo[i] = f_down(T[1 + i]);
+        hi[i] = f_up(T[1 + i]);
+      }
+  }
+  for (int o = 1; o < 64; o <<= 1) {
+    G = fmaxf(G, __shfl_xor(G, o));
+    Lm = fminf(Lm, __shfl_xor(Lm, o));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      lo[i] = fminf(lo[i], __shfl_xor(lo[i], o));
+      hi[i] = fmaxf(hi[i], __shfl_xor(hi[i], o));
     }
   }
-  for (int i = ns; i < 3; ++i) {
-    ti.lo[i] = 0.0f;
-    ti.hi[i] = 0.0f;
+  if (lane == 0) {
+    TileInfo ti;
+    ti.G = G;
+    ti.Lam = Lm;
+    for (int i = 0; i < 3; ++i) {
+      ti.lo[i] = i < ns ? lo[i] : 0.0f;
+      ti.hi[i] = i < ns ? hi[i] : 0.0f;
+    }
+    ti.code = t * CT < K ? ccode[t * CT] : 0xFFFFFFFFu;
+    ti.pad = 0;
+    info[t] = ti;
   }
-  ti.code = t * CT < K ? ccode[t * CT] : 0xFFFFFFFFu;
-  info[t] = ti;
 }
 
 hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s) {
@@ -245,7 +263,7 @@ hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
 hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s) {
   const Layout& L = *d.L;
   const int64_t ntiles = L.Kpad / CT;
-  hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((ntiles + 127) / 128)), dim3(128), 0, s, d.at<int32_t>(L.corder),
+  hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, d.at<int32_t>(L.corder),
                      d.at<uint32_t>(L.ccode), d.K, ntiles, d.D, d.at<double>(L.direct), direct_stride(d.D),
                      d.at<float>(L.lam), d.at<TileInfo>(L.tinfo));
   return hipGetLastError();

@@ -243,6 +243,7 @@ Layout make_layout(const vbgs_params& p) {
   L.tinfo = take(sparse ? (size_t)(L.Kpad / CT) * sizeof(TileInfo) : 0);
   L.rowb = take(sparse ? (size_t)L.Kpad * sizeof(RowBound) : 0);
   L.lhist = take(sparse ? (size_t)LAM_BINS * 4 : 0);
+  L.scan_part = take(sparse ? (size_t)((L.Kpad + 1023) / 1024 + 1) * 4 : 0);
   // learned proposal
   const bool pr = p.proposal == 1;
   const int C = p.C > 0 ? p.C : 32;
@@ -459,6 +460,7 @@ vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse
   if (st != VBGS_OK) return st;
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
+  cfg.cull = use_cull(c) ? 1 : 0;
   hipError_t e;
   {
     Phase ph(c, 3, S(stream));
@@ -540,7 +542,7 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* c, void* stream) {
   return hipfail(c, launch_clear_flags(c->dev(), S(stream)), "clear_flags");
 }
 
-vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[7], void* stream) {
+vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[8], void* stream) {
   if (!c || !out) return VBGS_ERR_ARG;
   FrameInfo f;
   hipError_t e = hipStreamSynchronize(S(stream));
@@ -553,6 +555,7 @@ vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[7], void* stream) {
   out[4] = (int64_t)f.blocks;
   out[5] = c->last_N > 0 ? (c->last_N + P1_PTS - 1) / P1_PTS * (P1_PTS / 64) * (c->L.Kpad / 16) : 0;
   out[6] = (int64_t)f.blocks_cum;
+  out[7] = f.n_over;
   return VBGS_OK;
 }
 

@@ -154,10 +154,10 @@ class VBGS:
         self._check(self.lib.vbgs_clear_flags(self.ctx, _stream()))
 
     def counters(self):
-        out = (ctypes.c_int64 * 7)()
+        out = (ctypes.c_int64 * 8)()
         self._check(self.lib.vbgs_counters(self.ctx, out, _stream()))
         return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3], blocks=out[4],
-                    blocks_dense=out[5], blocks_cum=out[6])
+                    blocks_dense=out[5], blocks_cum=out[6], n_over=out[7])
 
     # ---- learned candidate proposal -----------------------------------------------------
     def _f32(self, a):

@@ -254,15 +254,17 @@ def test_full_k_c3_slice(dev):
 
 
 @gpu
-def test_candidate_overflow_fallback(dev):
+@pytest.mark.parametrize("cull", [0, 1])
+def test_candidate_overflow_fallback(dev, cull):
     """Hundreds of near-identical components: every point has far more relevant pairs than the
-    sweep's per-point lists hold, so the statistics come from the exact rescan fallback."""
+    sweep's per-point lists hold, so the statistics come from the exact rescan fallback (over
+    every component, or over the rows whose bounds reach the margin after the culled sweep)."""
     g = np.random.default_rng(31)
     D, K, N = 6, 320, 700
     X = (0.5 + g.normal(0, 0.05, (N, D))).astype(np.float32)
     m0 = 0.5 + g.normal(0, 1e-4, (K, D))
     pr = scenes.Prior(m0=m0, W0=np.eye(D) * 50.0, kappa0=1.0, nu0=D + 2.0, alpha0=1.0)
-    m = _model(dev, pr, N, "bf16x3", True)
+    m = _model(dev, pr, N, "bf16x3", True, cull=bool(cull))
     lse, st = m.estep_stats(torch.from_numpy(X).to(dev))
     torch.cuda.synchronize()
     p = R.NW.from_prior(pr)
@@ -271,7 +273,9 @@ def test_candidate_overflow_fallback(dev):
     ref = R.stats(X, p, ls, e, scatter=False).packed()
     dl = np.abs(lse.cpu().numpy() - ls).max()
     es = _stat_err(ref, st.cpu().numpy(), D)
-    print("overflow case: max|dLSE| %.2e stats relerr %.2e" % (dl, es), m.counters())
+    cnt = m.counters()
+    print("overflow case: max|dLSE| %.2e stats relerr %.2e" % (dl, es), cnt)
+    assert cnt["n_over"] > 0
     assert dl < 2e-6 and es < 1e-9
 
 
