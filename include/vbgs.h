@@ -37,8 +37,8 @@
  *    that vbgs_sync_status reports.
  *  - A context is not thread-safe; separate contexts are independent.
  */
-#ifndef VBGS_H
-#define VBGS_H
+#ifndef VBGS_C_ABI_H_
+#define VBGS_C_ABI_H_
 
 #include <stddef.h>
 #include <stdint.h>
@@ -244,4 +244,4 @@ void vbgs_destroy(vbgs_ctx* ctx);
 }
 #endif
 
-#endif /* VBGS_H */
+#endif /* VBGS_C_ABI_H_ */

@@ -82,6 +82,20 @@ __device__ __forceinline__ Opnd<P> zero_op() {
   return o;
 }
 
+// Empty asm that reads the operand registers: it makes the compiler wait for their loads at this
+// point, so loads issued together stay together instead of being sunk next to each use.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <int P>
+__device__ __forceinline__ void operands_ready(const Opnd<P>& o) {
+  if constexpr (P == VBGS_FP32) {
+    asm volatile("" ::"v"(__builtin_bit_cast(u32x4, o.a)), "v"(__builtin_bit_cast(u32x4, o.b)));
+  } else if constexpr (P == VBGS_BF16) {
+    asm volatile("" ::"v"(__builtin_bit_cast(u32x4, o.h)));
+  } else {
+    asm volatile("" ::"v"(__builtin_bit_cast(u32x4, o.h)), "v"(__builtin_bit_cast(u32x4, o.l)));
+  }
+}
+
 // 16 x 16 tile of scores: D[m][n] = sum_slots A_row(m) . B_row(n)
 template <int P>
 __device__ __forceinline__ f32x4 mfma_scores(const Opnd<P>& A, const Opnd<P>& B) {
@@ -418,29 +432,27 @@ struct SweepWave {
   bool val[P1_PB], ovf[P1_PB];
   float lo[3], hi[3];
   unsigned nref, nblk;
+  float mw;  // the wave's smallest M when last taken (seeds: -inf)
 };
 
 // screen tile t for the wave's points (see above); rec: record candidates
 template <int P>
+// tk: the wave's LDS slot for the tile's component indices (lane = row)
 __device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int64_t t, bool rec, int lane,
-                                            float* __restrict__ mv, const int32_t* __restrict__ pid) {
+                                            unsigned bm, float* __restrict__ mv, const int32_t* __restrict__ pid,
+                                            int32_t* __restrict__ tk) {
   const int g = lane >> 4, c = lane & 15;
   const int64_t r0 = t * CT;
   const RowBound rb = a.rowb[r0 + lane];
+  const int32_t krow = a.corder[r0 + lane];  // rows past K hold no component (never recorded)
+  const f32x4 ncq = a.ncg[t * 4 + g];        // largest norm of this lane's four rows, per block
   Opnd<P> A[CT / 16];
 #pragma unroll
   for (int cb = 0; cb < CT / 16; ++cb) {
     const int64_t r = r0 + cb * 16 + c;
     A[cb] = load_op<P>(a.c32 + r * FP, a.ch + r * FP, a.cl + r * FP, g);
   }
-  // largest coefficient norm over the four rows 4j..4j+3 (lane j holds row j's)
-  float nc4 = fmaxf(rb.nc, __shfl_xor(rb.nc, 1));
-  nc4 = fmaxf(nc4, __shfl_xor(nc4, 2));
-  float mw = INFINITY;
-#pragma unroll
-  for (int b = 0; b < P1_PB; ++b)
-    if (S.val[b]) mw = fminf(mw, S.M[b]);
-  for (int o = 1; o < 64; o <<= 1) mw = fminf(mw, __shfl_xor(mw, o));
+  const float mw = S.mw;  // stale lower bound on the wave's smallest M (M only grows)
   const float margin = a.T2 + 1.0f;
   float d2 = 0.0f;
 #pragma unroll
@@ -451,14 +463,25 @@ __device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int
     d2 = fmaf(gap, gap, d2);
   }
   const unsigned long long rmask = __ballot(rb.G - rb.Lam * d2 >= mw - margin);
+  // the four blocks' rows were requested together with the bounds: one wait for all of them
+#pragma unroll
+  for (int cb = 0; cb < CT / 16; ++cb) operands_ready<P>(A[cb]);
+  tk[lane] = krow;
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int cb = 0; cb < CT / 16; ++cb) {
     if (((rmask >> (16 * cb)) & 0xFFFFull) == 0ull) continue;  // wave-uniform
     ++S.nblk;
-    const float ncm = __shfl(nc4, 16 * cb + 4 * g);  // rows 16 cb + 4 g + i, i < 4
+    const float ncm = ncq[cb];  // rows 16 cb + 4 g + i, i < 4
+    // the four point blocks' products first (independent MFMA chains), then their screens
+    f32x4 svb[P1_PB];
+#pragma unroll
+    for (int b = 0; b < P1_PB; ++b)
+      if (bm & (1u << b)) svb[b] = mfma_scores<P>(A[cb], S.B[b]);
 #pragma unroll
     for (int b = 0; b < P1_PB; ++b) {
-      const f32x4 sv = mfma_scores<P>(A[cb], S.B[b]);
+      if (!(bm & (1u << b))) continue;  // no point of this block within reach (wave-uniform)
+      const f32x4 sv = svb[b];
       const float mx = fmaxf(fmaxf(sv[0], sv[1]), fmaxf(sv[2], sv[3]));
       const float e = S.nphE[b] * ncm;
       S.M[b] = fmaxf(S.M[b], mx - e);
@@ -468,13 +491,20 @@ __device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int
         for (int q = 0; q < 4; ++q) {
           const int64_t r = r0 + cb * 16 + 4 * g + q;
           if (sv[q] >= thr && r < a.K) {
-            record_candidate(a, pid[16 * b + c], g, a.corder[r], sv[q] + e, S.M[b] - a.T2, S.cn[b], S.ovf[b]);
+            record_candidate(a, pid[16 * b + c], g, tk[cb * 16 + 4 * g + q], sv[q] + e, S.M[b] - a.T2, S.cn[b],
+                             S.ovf[b]);
             ++S.nref;
           }
         }
       }
     }
   }
+}
+
+// make each point's M the largest over its four lane groups and publish it for the tile tests
+template <int P>
+__device__ __forceinline__ void share_m(SweepWave<P>& S, int lane, float* __restrict__ mv) {
+  const int g = lane >> 4, c = lane & 15;
 #pragma unroll
   for (int b = 0; b < P1_PB; ++b) {
     S.M[b] = fmaxf(S.M[b], __shfl_xor(S.M[b], 16));
@@ -492,6 +522,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ float mvs[1][64];    // their current lower bounds M (+inf for empty slots)
   __shared__ int32_t pids[1][64]; // their original indices
   __shared__ int32_t seeds[1][24];
+  __shared__ uint8_t bms[1][64];  // per tile of the current chunk: the 16-point blocks it reaches
+  __shared__ int32_t tks[1][64];  // component indices of the tile being screened
   const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
   const int64_t j0 = xcd_block(blockIdx.x, gridDim.x) * (P1_PB * 16);  // sorted positions
   const int ns = a.D < 3 ? a.D : 3;
@@ -499,6 +531,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   const int32_t* pid = pids[w];
 
   SweepWave<P> S;
+  S.mw = -INFINITY;
   S.nref = 0;
   S.nblk = 0;
 #pragma unroll
@@ -572,11 +605,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __builtin_amdgcn_wave_barrier();
     for (int i = 0; i < 2 * nseed; ++i) {
       const int64_t t = __builtin_amdgcn_readfirstlane(seeds[w][i % nseed]);
-      screen_tile<P>(a, S, t, i >= nseed, lane, mv, pid);
+      screen_tile<P>(a, S, t, i >= nseed, lane, 0xFu, mv, pid, tks[w]);
+      share_m<P>(S, lane, mv);
     }
     const float margin = a.T2 + 1.0f;
     const float4 xme = pts[w][lane];  // this lane's point (lane = point of the wave)
     for (int64_t base = 0; base < ntiles; base += 64) {
+      share_m<P>(S, lane, mv);
       // lane = tile: the wave's box against the tile bound
       const int64_t t = base + lane;
       float mw = INFINITY;
@@ -584,6 +619,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       for (int b = 0; b < P1_PB; ++b)
         if (S.val[b]) mw = fminf(mw, S.M[b]);
       for (int o = 1; o < 64; o <<= 1) mw = fminf(mw, __shfl_xor(mw, o));
+      S.mw = mw;
       TileInfo ti{};
       bool cand = false;
       if (t < ntiles && !near_centre(t, 8)) {
@@ -607,14 +643,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
           const float gap = fmaxf(fmaxf(tlo - xq[q], xq[q] - thi), 0.0f);
           d2 = fmaf(gap, gap, d2);
         }
-        if (__ballot(tG - tL * d2 >= thr_me) != 0ull) m |= 1ull << i;
+        const unsigned long long pm = __ballot(tG - tL * d2 >= thr_me);
+        if (pm != 0ull) {
+          m |= 1ull << i;
+          // which 16-point blocks (lane = point, block = lane / 16) reach the tile
+          const unsigned bmi = ((pm & 0xFFFFull) ? 1u : 0u) | ((pm & 0xFFFF0000ull) ? 2u : 0u) |
+                               ((pm & 0xFFFF00000000ull) ? 4u : 0u) | ((pm >> 48) ? 8u : 0u);
+          if (lane == 0) bms[w][i] = (uint8_t)bmi;
+        }
       }
+      __builtin_amdgcn_wave_barrier();
       while (m) {
         const int i = __ffsll((long long)m) - 1;
         m &= m - 1ull;
-        screen_tile<P>(a, S, base + i, true, lane, mv, pid);
+        screen_tile<P>(a, S, base + i, true, lane, __builtin_amdgcn_readfirstlane(bms[w][i]), mv, pid, tks[w]);
       }
     }
+    share_m<P>(S, lane, mv);
   }
 #pragma unroll
   for (int b = 0; b < P1_PB; ++b) {
@@ -1348,6 +1393,7 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.corder = d.at<int32_t>(L.corder);
   a.tinfo = d.at<TileInfo>(L.tinfo);
   a.rowb = d.at<RowBound>(L.rowb);
+  a.ncg = d.at<f32x4>(L.ncg);
   a.scan_part = d.at<int32_t>(L.scan_part);
   a.N = N;
   a.K = d.K;

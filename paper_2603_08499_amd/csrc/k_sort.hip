@@ -179,7 +179,8 @@ __global__ void k_unpack_order(const unsigned long long* __restrict__ keys, int6
 __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ corder,
                                                    const uint32_t* __restrict__ ccode, int64_t K, int64_t ntiles,
                                                    int D, const double* __restrict__ direct, int dts,
-                                                   const float* __restrict__ lam, TileInfo* __restrict__ info) {
+                                                   const float* __restrict__ lam, const RowBound* __restrict__ rowb,
+                                                   TileInfo* __restrict__ info, float* __restrict__ ncg) {
   // one wave per tile, lane = row
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -212,6 +213,15 @@ __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ c
       lo[i] = fminf(lo[i], __shfl_xor(lo[i], o));
       hi[i] = fmaxf(hi[i], __shfl_xor(hi[i], o));
     }
+  }
+  // norms of the four-row groups, stored [tile][g][cb] (row 16 cb + 4 g + i): each lane of the
+  // sweep reads its four values with one 16-byte load
+  float nc = rowb[t * CT + lane].nc;
+  nc = fmaxf(nc, __shfl_xor(nc, 1));
+  nc = fmaxf(nc, __shfl_xor(nc, 2));
+  if ((lane & 3) == 0) {
+    const int cb = lane >> 4, g = (lane >> 2) & 3;
+    ncg[t * CT / 4 + g * 4 + cb] = nc;
   }
   if (lane == 0) {
     TileInfo ti;
@@ -265,7 +275,7 @@ hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s) {
   const int64_t ntiles = L.Kpad / CT;
   hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, d.at<int32_t>(L.corder),
                      d.at<uint32_t>(L.ccode), d.K, ntiles, d.D, d.at<double>(L.direct), direct_stride(d.D),
-                     d.at<float>(L.lam), d.at<TileInfo>(L.tinfo));
+                     d.at<float>(L.lam), d.at<RowBound>(L.rowb), d.at<TileInfo>(L.tinfo), d.at<float>(L.ncg));
   return hipGetLastError();
 }
 

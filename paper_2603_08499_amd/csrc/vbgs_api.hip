@@ -242,6 +242,7 @@ Layout make_layout(const vbgs_params& p) {
   L.lam = take((size_t)L.Kpad * 4);
   L.tinfo = take(sparse ? (size_t)(L.Kpad / CT) * sizeof(TileInfo) : 0);
   L.rowb = take(sparse ? (size_t)L.Kpad * sizeof(RowBound) : 0);
+  L.ncg = take(sparse ? (size_t)L.Kpad / 4 * sizeof(float) : 0);
   L.lhist = take(sparse ? (size_t)LAM_BINS * 4 : 0);
   L.scan_part = take(sparse ? (size_t)((L.Kpad + 1023) / 1024 + 1) * 4 : 0);
   // learned proposal

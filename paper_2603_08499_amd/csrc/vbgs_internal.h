@@ -108,7 +108,7 @@ struct Layout {
   int64_t Kpad, n_lse_part;
   int nsplit_max;
   // spatial ordering (culled exact sweep)
-  size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, lhist, scan_part;
+  size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
   // learned proposal (workspace)
   size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
       p_tdh2, p_tdp1, p_th2b, p_th2T, p_tloss, p_grads;
@@ -315,6 +315,8 @@ struct EArgs {
   const int32_t* corder;      // sorted row -> component index
   const TileInfo* tinfo;      // per-tile bounds of the sorted component table
   const RowBound* rowb;       // per-row bounds of the sorted component table
+  const f32x4* ncg;           // per tile and lane group g: for each 16-row block cb, the largest
+                              // coefficient norm of rows 16 cb + 4 g .. 16 cb + 4 g + 3
   int32_t* scan_part;         // block sums of the pair-count scan
   int64_t N, K, Kpad;
   int D, dts, nsplit;
