@@ -120,6 +120,20 @@ def run_c4(args):
     print(json.dumps(out))
 
 
+def sweep_traffic(args):
+    """HBM bytes per launch of the screening sweep from the committed counter summary, or None when
+    the summary was taken on another workload or precision or the kernel source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c3_sweep_traffic.json")
+    src = os.path.join(ROOT, "paper_2603_08499_amd", "csrc", "k_estep.hip")
+    if not os.path.exists(path) or args.workload != "c3" or args.prec != "bf16x3" or not args.exact or not args.cull:
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def run_steps(model, Xs, steps, torch):
     for i in range(steps):
         model.estep_stats(Xs[i % len(Xs)], lse=False, stats=False)
@@ -140,7 +154,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-points", type=int, default=4096)
+    ap.add_argument("--cpu-points", type=int, default=8192)
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="copy this many MiB device to device once before the timed loop (a kernel of known "
+                         "traffic for scaling the HBM byte counters of a profiled run)")
     ap.add_argument("--c4-exact", type=int, default=10)
     ap.add_argument("--c4-train-steps", type=int, default=1500)
     ap.add_argument("--c4-C", type=int, default=32)
@@ -186,6 +203,14 @@ def main():
     del mm
     torch.cuda.synchronize()
     print("bench: accuracy done", acc, file=sys.stderr, flush=True)
+
+    if args.copy_calib_mb > 0:
+        nb = args.copy_calib_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- timed mixed-precision updates --------------------------------------------------------
     model = new_model(args.prec, args.exact)
@@ -234,7 +259,8 @@ def main():
     peak = PEAK.get(args.prec, PEAK["bf16"])
     roof = {"bound": "mfma", "kernel": "screening sweep" if dom == "pass1" else dom,
             "achieved": algo_flops / t_dom / 1e12, "peak": peak / 1e12,
-            "unit": "TFLOP/s", "frac": algo_flops / t_dom / peak, "traffic": None,
+            "unit": "TFLOP/s", "frac": algo_flops / t_dom / peak,
+            "traffic": sweep_traffic(args) if dom == "pass1" else None,
             "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": avg[dom],
             "blocks_screened_per_launch": blocks, "blocks_dense": cnt_run["blocks_dense"],
             "dense_equivalent_tflops": 2.0 * F * N * K / t_dom / 1e12,
