@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=8192)
+    ap.add_argument("--reassign-n", type=int, default=1000,
+                    help="components moved by the reassignment step timed after the main loop (0: skip)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="copy this many MiB device to device once before the timed loop (a kernel of known "
                          "traffic for scaling the HBM byte counters of a profiled run)")
@@ -233,6 +235,24 @@ def main():
     print("bench: mixed %.3f ms/step, phases %s" % (ms, {k: round(v[0] / max(v[1], 1), 4) for k, v in
                                                         phases.items() if v[1]}), file=sys.stderr, flush=True)
 
+    # ---- reassignment step (Alg. 1, `reassign`), after the timed loop -------------------------
+    reas = None
+    if args.reassign_n > 0:
+        from synth import scenes
+        lse_r, _ = model.estep_stats(Xs[0], stats=False)
+        gm = torch.from_numpy(scenes.gumbel_noise(N, 0, cfg=3)).to(dev)
+        model.reassign(Xs[0], lse_r, gm, args.reassign_n)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            model.reassign(Xs[0], lse_r, gm, args.reassign_n)
+        e1.record()
+        torch.cuda.synchronize()
+        reas = {"n": args.reassign_n, "ms": e0.elapsed_time(e1) / 5,
+                "what": "Gumbel-top-n over N points and least-alpha over K components (two 64-bit key sorts) "
+                        "and the mean moves; the E-step giving the LSE is not included"}
+
     # ---- plain FP64 GPU comparator --------------------------------------------------------------
     fp64 = None
     if not args.no_fp64 and args.fp64_steps > 0:
@@ -291,7 +311,7 @@ def main():
                       "exact": bool(args.exact), "frames_cycled": args.frames},
            "phase_ms": {k: round(v, 5) for k, v in avg.items()},
            "fp64_gpu": fp64, "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
-           "device_status": status, "roofline": roof, "cpu_baseline": cpu}
+           "device_status": status, "roofline": roof, "cpu_baseline": cpu, "reassign": reas}
     out.update(acc)
     print(json.dumps(out))
 

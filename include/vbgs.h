@@ -155,6 +155,21 @@ vbgs_status vbgs_get_params(vbgs_ctx* ctx, int32_t which, double* alpha, double*
 vbgs_status vbgs_set_params(vbgs_ctx* ctx, int32_t which, const double* alpha, const double* kappa,
                             const double* m, const double* Winv, const double* nu, void* stream);
 
+/* Reassignment of under-used components (Alg. 1, `reassign`; Sec. 3.1): sample n points biased
+ * towards a low evidence bound and move the means of the n least-used components onto them.
+ * X: device N x D FP32 (the frame); lse: device N FP64, the points' log normalisers in nats (the
+ * lse_out of a vbgs_estep_stats on X); gumbel: device N FP64 standard Gumbel draws supplied by the
+ * caller. Points are taken in decreasing order of gumbel[n] - lse[n] (Gumbel-top-n, i.e. sampling
+ * without replacement with probabilities proportional to exp(-lse)), components in increasing
+ * order of the posterior alpha; both orders compare the values through their order-preserving
+ * 64-bit images with the low 25 bits replaced by the index (ties to the lower index). The i-th
+ * point becomes the mean m of the i-th component in the frame prior and in the posterior; no other
+ * parameter changes. out_points / out_comps (device int32 n, or NULL) receive the pairs.
+ * Requires 0 <= n <= min(N, K) and N, K < 2^25 (VBGS_ERR_SHAPE / VBGS_ERR_UNSUPPORTED);
+ * n = 0 does nothing. Invalidates the ELBO of the last E-step, like vbgs_update. */
+vbgs_status vbgs_reassign(vbgs_ctx* ctx, const float* X, int64_t N, const double* lse, const double* gumbel,
+                          int64_t n, int32_t* out_points, int32_t* out_comps, void* stream);
+
 /* Synchronise `stream` and return the sticky device flags (VBGS_ERR_NOT_PD,
  * VBGS_ERR_NONFINITE) or VBGS_OK. Clears nothing; vbgs_clear_flags does. */
 vbgs_status vbgs_sync_status(vbgs_ctx* ctx, void* stream);

@@ -279,4 +279,70 @@ hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---- reassignment of under-used components ---------------------------------------------------
+// Sort keys: the order-preserving 64-bit image of an FP64 value (complemented for a descending
+// order) with the low 25 bits replaced by the element's index; padding keys are all ones.
+constexpr int RA_IDX_BITS = 25;
+constexpr unsigned long long RA_IDX_MASK = (1ull << RA_IDX_BITS) - 1ull;
+
+__device__ __forceinline__ unsigned long long ord64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | (1ull << 63));
+}
+
+// points: value g_n - LSE_n (largest first)
+__global__ void k_reassign_point_keys(const double* __restrict__ lse, const double* __restrict__ gumbel, int64_t N,
+                                      int64_t Npow, unsigned long long* __restrict__ keys) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= Npow) return;
+  keys[n] = n < N ? ((~ord64(gumbel[n] - lse[n])) & ~RA_IDX_MASK) | (unsigned long long)n : ~0ull;
+}
+
+// components: posterior alpha (smallest first)
+__global__ void k_reassign_comp_keys(const double* __restrict__ post, int64_t K, int64_t Kpow,
+                                     unsigned long long* __restrict__ keys) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Kpow) return;
+  keys[k] = k < K ? (ord64(post[k * REC]) & ~RA_IDX_MASK) | (unsigned long long)k : ~0ull;
+}
+
+// the i-th sampled point becomes the mean of the i-th least-used component (prior and posterior)
+__global__ void k_reassign_apply(const unsigned long long* __restrict__ pkeys,
+                                 const unsigned long long* __restrict__ ckeys, int64_t n, const float* __restrict__ X,
+                                 int D, double* __restrict__ prior, double* __restrict__ post,
+                                 int32_t* __restrict__ out_pts, int32_t* __restrict__ out_comps) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = (int64_t)(pkeys[i] & RA_IDX_MASK), k = (int64_t)(ckeys[i] & RA_IDX_MASK);
+  for (int d = 0; d < D; ++d) {
+    const double x = (double)X[p * D + d];
+    prior[k * REC + 3 + d] = x;
+    post[k * REC + 3 + d] = x;
+  }
+  if (out_pts) out_pts[i] = (int32_t)p;
+  if (out_comps) out_comps[i] = (int32_t)k;
+}
+
+hipError_t launch_reassign(const DevPtrs& d, const float* X, int64_t N, const double* lse, const double* gumbel,
+                           int64_t n, int32_t* out_pts, int32_t* out_comps, hipStream_t s) {
+  const Layout& L = *d.L;
+  if (n <= 0) return hipSuccess;
+  int64_t npow = BS_LOCAL, kpow = BS_LOCAL;
+  while (npow < N) npow <<= 1;
+  while (kpow < d.K) kpow <<= 1;
+  unsigned long long* pk = d.at<unsigned long long>(L.pkeys);
+  unsigned long long* ck = d.at<unsigned long long>(L.ckeys);
+  hipLaunchKernelGGL(k_reassign_point_keys, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, s, lse, gumbel, N,
+                     npow, pk);
+  hipError_t e = launch_sort_keys(pk, npow, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reassign_comp_keys, dim3((unsigned)((kpow + 255) / 256)), dim3(256), 0, s, d.post(), d.K,
+                     kpow, ck);
+  e = launch_sort_keys(ck, kpow, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reassign_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pk, ck, n, X, d.D,
+                     d.prior(), d.post(), out_pts, out_comps);
+  return hipGetLastError();
+}
+
 }  // namespace vbgs

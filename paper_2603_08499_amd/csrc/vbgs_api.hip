@@ -232,10 +232,10 @@ Layout make_layout(const vbgs_params& p) {
   int64_t npow = 2048, kpow = 2048;
   while (npow < n) npow <<= 1;
   while (kpow < K) kpow <<= 1;
-  L.pkeys = take(sparse ? (size_t)npow * 8 : 0);
+  L.pkeys = take((size_t)npow * 8);  // also used by the reassignment step in every mode
   L.porder = take(sparse ? (size_t)n * 4 : 0);
   L.pcode = take(sparse ? (size_t)n * 4 : 0);
-  L.ckeys = take(sparse ? (size_t)kpow * 8 : 0);
+  L.ckeys = take((size_t)kpow * 8);
   L.corder = take(sparse ? (size_t)L.Kpad * 4 : 0);
   L.cinv = take(sparse ? (size_t)L.Kpad * 4 : 0);
   L.ccode = take(sparse ? (size_t)L.Kpad * 4 : 0);
@@ -521,6 +521,20 @@ vbgs_status vbgs_set_params(vbgs_ctx* c, int32_t which, const double* alpha, con
   hipError_t e = launch_get_set(c->dev(), which, 1, (double*)alpha, (double*)kappa, (double*)m, (double*)Winv,
                                 (double*)nu, S(stream));
   if (e != hipSuccess) return hipfail(c, e, "set_params");
+  c->post_version++;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_reassign(vbgs_ctx* c, const float* X, int64_t N, const double* lse, const double* gumbel,
+                          int64_t n, int32_t* out_points, int32_t* out_comps, void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+  if (n < 0 || n > N || n > c->p.K) return fail(c, VBGS_ERR_SHAPE, "n outside 0..min(N, K)");
+  if (N >= (1ll << 25) || c->p.K >= (1ll << 25)) return fail(c, VBGS_ERR_UNSUPPORTED, "N and K must be below 2^25");
+  if (n == 0) return VBGS_OK;
+  if (!X || !lse || !gumbel) return VBGS_ERR_ARG;
+  hipError_t e = launch_reassign(c->dev(), X, N, lse, gumbel, n, out_points, out_comps, S(stream));
+  if (e != hipSuccess) return hipfail(c, e, "reassign");
   c->post_version++;
   return VBGS_OK;
 }

@@ -274,6 +274,8 @@ hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s);
 hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
 hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s);
 hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s);
+hipError_t launch_reassign(const DevPtrs& d, const float* X, int64_t N, const double* lse, const double* gumbel,
+                           int64_t n, int32_t* out_pts, int32_t* out_comps, hipStream_t s);
 
 struct EstepCfg {
   int prec;      // vbgs_prec

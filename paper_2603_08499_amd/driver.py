@@ -50,14 +50,21 @@ def train_on_targets(model: VBGS, data, steps: int, batch: int, lr: float, seed:
 
 def run_stream(model: VBGS, frames: List[torch.Tensor], n_exact: int, train_steps: int = 0, batch: int = 4096,
                lr: float = 1e-3, audit: int = 4096, bound: float = float(np.log1p(-1e-4)), frac: float = 0.01,
-               steps_per_frame: int = 1, seed: int = 0, retrain_steps: int = 0) -> List[FrameLog]:
-    """Process the frames in order. Frames < n_exact: exact E-step, targets kept for training;
-    after frame n_exact - 1 the proposal is trained for `train_steps`. Later frames: pruned
-    E-step with an audit of `audit` seeded points; frames that fall back are added to the
-    training data and trigger `retrain_steps` more steps."""
+               steps_per_frame: int = 1, seed: int = 0, retrain_steps: int = 0,
+               reassign_n: int = 0) -> List[FrameLog]:
+    """Process the frames in order. With reassign_n > 0 each frame starts with Alg. 1's `reassign`:
+    the frame's per-point LSE under the current posterior, then the reassignment of reassign_n
+    components (Gumbel draws from a generator seeded by (seed, frame)). Frames < n_exact: exact
+    E-step, targets kept for training; after frame n_exact - 1 the proposal is trained for
+    `train_steps`. Later frames: pruned E-step with an audit of `audit` seeded points; frames that
+    fall back are added to the training data and trigger `retrain_steps` more steps."""
     logs, data = [], []
     for t, X in enumerate(frames):
         N = X.shape[0]
+        if reassign_n > 0:
+            lse, _ = model.estep_stats(X, stats=False)
+            gm = np.random.default_rng([seed, t, 1]).gumbel(size=N)
+            model.reassign(X, lse, gm, min(reassign_n, N, model.K))
         exact = t < n_exact or not model.params.proposal
         for s in range(steps_per_frame):
             last = s == steps_per_frame - 1

@@ -159,6 +159,22 @@ class VBGS:
         return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3], blocks=out[4],
                     blocks_dense=out[5], blocks_cum=out[6], n_over=out[7])
 
+    def reassign(self, X, lse, gumbel, n):
+        """Move the means of the n least-used components onto n points drawn with probabilities
+        proportional to exp(-lse) (Gumbel-top-n with the given draws). lse: FP64 log normalisers
+        in nats from estep_stats on X. Returns (points, comps) int32 device tensors."""
+        X = self._points(X)
+        N = X.shape[0]
+        lse = torch.as_tensor(lse, dtype=torch.float64).to(self.device).contiguous()
+        gumbel = torch.as_tensor(gumbel, dtype=torch.float64).to(self.device).contiguous()
+        if lse.shape != (N,) or gumbel.shape != (N,):
+            raise ValueError("lse and gumbel must have one FP64 value per point")
+        pts = torch.empty(max(int(n), 0), dtype=torch.int32, device=self.device)
+        comps = torch.empty_like(pts)
+        self._check(self.lib.vbgs_reassign(self.ctx, _ptr(X), N, _ptr(lse), _ptr(gumbel), int(n),
+                                           _ptr(pts) if n > 0 else None, _ptr(comps) if n > 0 else None, _stream()))
+        return pts, comps
+
     # ---- learned candidate proposal -----------------------------------------------------
     def _f32(self, a):
         return torch.as_tensor(np.asarray(a, np.float32) if not torch.is_tensor(a) else a,

@@ -333,3 +333,11 @@ def audit_indices(N: int, n_audit: int, frame: int, cfg: int = 0) -> np.ndarray:
     g = rng(88, frame, cfg)
     n_audit = min(n_audit, N)
     return np.sort(g.choice(N, size=n_audit, replace=False)).astype(np.int32)
+
+
+def gumbel_noise(N: int, frame: int, cfg: int = 0) -> np.ndarray:
+    """Standard Gumbel draws -ln(-ln u), u ~ U(0, 1), FP64, for the biased point sampling of the
+    reassignment step (one draw per point)."""
+    u = rng(cfg, frame, 11).random(N)
+    u = np.clip(u, 1e-300, 1.0 - 1e-16)
+    return -np.log(-np.log(u))
