@@ -9,7 +9,8 @@ frame's prior after every update. Frames are generated on the host, copied to HB
 the timed region and cycled. A step is one whole fit step over one frame.
 
 Prints one JSON line. Options: --gpus N (only 1: the path runs on one GPU),
---steps K, --warmup W, --prec, --exact, --workload {c3,c2}, --no-cpu, --no-fp64.
+--steps K, --warmup W, --prec, --exact, --cull, --modal-split S, --workload {c3,c2,c4,search},
+--reassign-n, --no-cpu, --no-fp64.
 """
 import argparse
 import json
@@ -126,7 +127,8 @@ def sweep_traffic(args):
     import hashlib
     path = os.path.join(ROOT, "profiles", "c3_sweep_traffic.json")
     src = os.path.join(ROOT, "paper_2603_08499_amd", "csrc", "k_estep.hip")
-    if not os.path.exists(path) or args.workload != "c3" or args.prec != "bf16x3" or not args.exact or not args.cull:
+    if (not os.path.exists(path) or args.workload != "c3" or args.prec != "bf16x3" or not args.exact or not args.cull
+            or args.modal_split):
         return None
     rec = json.load(open(path))
     if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
@@ -176,6 +178,8 @@ def main():
     ap.add_argument("--prec", default="bf16x3")
     ap.add_argument("--exact", type=int, default=1)
     ap.add_argument("--cull", type=int, default=1)
+    ap.add_argument("--modal-split", type=int, default=0,
+                    help="s > 0: two-factor likelihood over coordinates [0, s) and [s, D) (Sec. 2.1.2)")
     ap.add_argument("--frames", type=int, default=4)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
@@ -206,13 +210,15 @@ def main():
     dev = torch.device("cuda:0")
     frames, pr, desc = workload(args.workload, args.frames)
     N, D, K = frames[0].shape[0], pr.D, pr.K
+    if args.modal_split:
+        desc += "; two-factor likelihood over coordinates [0,%d) and [%d,%d)" % (args.modal_split, args.modal_split, D)
     Xs = [torch.from_numpy(f).to(dev) for f in frames]
     print("bench: workload %s N=%d K=%d D=%d prec=%s exact=%d" % (args.workload, N, K, D, args.prec, args.exact),
           file=sys.stderr, flush=True)
 
     def new_model(prec, exact):
         return P.VBGS(D, K, N, pr.m0, pr.W0, device=dev, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
-                      score_prec=prec, exact=bool(exact), cull=bool(args.cull))
+                      score_prec=prec, exact=bool(exact), cull=bool(args.cull), modal_split=args.modal_split)
 
     # ---- accuracy on frame 0 at the prior: mixed vs plain FP64 GPU path ------------------------
     acc = {}
@@ -322,22 +328,30 @@ def main():
         ns = min(args.cpu_points, N)
         idx = np.linspace(0, N - 1, ns).astype(np.int64)
         Xc = frames[0][idx]
-        p = R.NW.from_prior(pr)
         c0 = time.perf_counter()
-        res = R.cavi_step(Xc, p, p)
+        if args.modal_split:
+            from oracle import factorised_ref as FR
+            p = FR.NW2.from_prior(pr, args.modal_split)
+            e = FR.expectations(p)
+            lse_c = FR.lse(Xc, p, e)
+            FR.elbo(lse_c.sum(), p, p, e)
+            FR.update(p, FR.stats(Xc, p, lse_c, e))
+        else:
+            p = R.NW.from_prior(pr)
+            lse_c = R.cavi_step(Xc, p, p).lse
         tc = time.perf_counter() - c0
         cpu = {"value": ns * K / tc, "unit": "pairs/s", "cores": int(R.lib().oracle_threads()), "kind": "oracle",
                "sample": "%d evenly strided points of frame 0 x all K=%d components, one full FP64 step "
                          "(expectations, LSE, statistics with centred scatter, update, ELBO) in %.1f s"
                          % (ns, K, tc),
-               "lse_maxabs_vs_gpu_mixed": float(np.abs(res.lse - lse_m_host[idx]).max())}
+               "lse_maxabs_vs_gpu_mixed": float(np.abs(lse_c - lse_m_host[idx]).max())}
         print("bench: cpu oracle %.1f s" % tc, file=sys.stderr, flush=True)
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": args.prec + ("+f64" if args.exact else ""), "data": "synthetic",
            "config": {"workload": desc, "N": N, "K": K, "D": D, "score_prec": args.prec, "cull": args.cull,
-                      "exact": bool(args.exact), "frames_cycled": args.frames},
+                      "modal_split": args.modal_split, "exact": bool(args.exact), "frames_cycled": args.frames},
            "phase_ms": {k: round(v, 5) for k, v in avg.items()},
            "fp64_gpu": fp64, "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
            "device_status": status, "roofline": roof, "cpu_baseline": cpu, "reassign": reas}

@@ -94,7 +94,13 @@ typedef struct {
   int32_t cull;            /* exact MFMA mode: 1 (default) sorts points and components spatially and
                               skips whole 64-component tiles whose score bound lies below the margin;
                               0 screens every tile */
-  int32_t reserved1;       /* must be zero */
+  int32_t modal_split;     /* 0 (default): one joint Normal-Wishart over all D coordinates.
+                              s in 1..D-1: the model of Sec. 2.1.2 with two independent modalities,
+                              coordinates [0, s) (spatial) and [s, D) (colour), each with its own
+                              Normal-Wishart (kappa, nu, W; both blocks start from kappa0, nu0 and
+                              the matching diagonal block of W0, entries of W0 across the blocks are
+                              ignored). nu0 must exceed the block sizes minus 1. Needs D <= 7 and
+                              proposal = 0 (else VBGS_ERR_UNSUPPORTED). */
   int64_t reserved[4];     /* must be zero */
 } vbgs_params;
 
@@ -147,9 +153,10 @@ vbgs_status vbgs_update(vbgs_ctx* ctx, int32_t commit, void* stream);
 vbgs_status vbgs_elbo(vbgs_ctx* ctx, const float* X, int64_t N, double* elbo_dev, void* stream);
 
 /* Copy the posterior (which = 0) or the frame prior (which = 1) out of / into
- * the state. Device buffers: alpha, kappa, nu: K; m: K x D; Winv: K x D x D
- * (full, symmetric). Setting does not check positive definiteness (the next
- * E-step flags it). */
+ * the state. Device buffers: alpha: K; kappa, nu: K (one block) or K x 2 (modal_split > 0:
+ * spatial, colour); m: K x D; Winv: K x D x D (full, symmetric; with two blocks the entries
+ * across the blocks read as zero and are ignored when set). Setting does not check positive
+ * definiteness (the next E-step flags it). */
 vbgs_status vbgs_get_params(vbgs_ctx* ctx, int32_t which, double* alpha, double* kappa, double* m,
                             double* Winv, double* nu, void* stream);
 vbgs_status vbgs_set_params(vbgs_ctx* ctx, int32_t which, const double* alpha, const double* kappa,

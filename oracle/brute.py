@@ -9,6 +9,8 @@ disagreement:
 * ``elbo_bishop``: the evidence lower bound assembled from the seven
   expectation terms of PRML eqs. 10.70-10.77 with the responsibilities written
   out, instead of sum_n LSE_n - KL(q||p).
+* ``elbo_bishop_blocks``: the same seven terms for the two-factor (spatial / colour)
+  model, with the responsibilities from explicit-inverse block scores.
 * ``update_natural``: the posterior through natural parameters
   (kappa m, W^{-1} + kappa m m^T), instead of the centred scatter form.
 * ``log_marginal_k1``: the closed-form Normal-Wishart marginal likelihood of a
@@ -55,20 +57,17 @@ def _lnC(a):
     return gammaln(a.sum()) - gammaln(a).sum()
 
 
-def elbo_bishop(X, q, p):
-    """PRML 10.70: E[ln p(X|Z,mu,Lam)] + E[ln p(Z|pi)] + E[ln p(pi)] + E[ln p(mu,Lam)]
-    - E[ln q(Z)] - E[ln q(pi)] - E[ln q(mu,Lam)], with per-component prior parameters."""
-    X = np.asarray(X, np.float64)
+def _nw_terms(X, R, kq, mq, Winvq, nuq, kp, mp, Winvp, nup):
+    """E[ln p(X|Z,mu,Lam)] + E[ln p(mu,Lam)] - E[ln q(mu,Lam)] of PRML 10.71, 10.74, 10.77 for one
+    Normal-Wishart factor over the coordinates in X (per-component parameters, responsibilities R)."""
     N, D = X.shape
-    K = q.m.shape[0]
-    R, _ = responsibilities(X, q)
+    K = mq.shape[0]
     Nk = R.sum(0)
-    Elnpi = digamma(q.alpha) - digamma(q.alpha.sum())
-    t_lik = t_z = t_ppi = t_pml = t_qz = t_qpi = t_qml = 0.0
+    t_lik = t_pml = t_qml = 0.0
     for k in range(K):
-        W = np.linalg.inv(q.Winv[k])
-        Wp = np.linalg.inv(p.Winv[k])
-        ElnL = sum(digamma((q.nu[k] + 1 - i) / 2.0) for i in range(1, D + 1)) + D * np.log(2) \
+        W = np.linalg.inv(Winvq[k])
+        Wp = np.linalg.inv(Winvp[k])
+        ElnL = sum(digamma((nuq[k] + 1 - i) / 2.0) for i in range(1, D + 1)) + D * np.log(2) \
             + np.linalg.slogdet(W)[1]
         if Nk[k] > 0:
             xb = (R[:, k:k + 1] * X).sum(0) / Nk[k]
@@ -76,21 +75,55 @@ def elbo_bishop(X, q, p):
         else:
             xb = np.zeros(D)
             S = np.zeros((D, D))
-        dx = xb - q.m[k]
-        t_lik += 0.5 * Nk[k] * (ElnL - D / q.kappa[k] - q.nu[k] * np.trace(S @ W)
-                                - q.nu[k] * dx @ W @ dx - D * np.log(2 * np.pi))
-        dm = q.m[k] - p.m[k]
-        t_pml += 0.5 * (D * np.log(p.kappa[k] / (2 * np.pi)) + ElnL - D * p.kappa[k] / q.kappa[k]
-                        - p.kappa[k] * q.nu[k] * dm @ W @ dm) \
-            + _lnB(Wp, p.nu[k]) + 0.5 * (p.nu[k] - D - 1) * ElnL - 0.5 * q.nu[k] * np.trace(p.Winv[k] @ W)
-        H = -_lnB(W, q.nu[k]) - 0.5 * (q.nu[k] - D - 1) * ElnL + 0.5 * q.nu[k] * D
-        t_qml += 0.5 * ElnL + 0.5 * D * np.log(q.kappa[k] / (2 * np.pi)) - 0.5 * D - H
+        dx = xb - mq[k]
+        t_lik += 0.5 * Nk[k] * (ElnL - D / kq[k] - nuq[k] * np.trace(S @ W)
+                                - nuq[k] * dx @ W @ dx - D * np.log(2 * np.pi))
+        dm = mq[k] - mp[k]
+        t_pml += 0.5 * (D * np.log(kp[k] / (2 * np.pi)) + ElnL - D * kp[k] / kq[k]
+                        - kp[k] * nuq[k] * dm @ W @ dm) \
+            + _lnB(Wp, nup[k]) + 0.5 * (nup[k] - D - 1) * ElnL - 0.5 * nuq[k] * np.trace(Winvp[k] @ W)
+        H = -_lnB(W, nuq[k]) - 0.5 * (nuq[k] - D - 1) * ElnL + 0.5 * nuq[k] * D
+        t_qml += 0.5 * ElnL + 0.5 * D * np.log(kq[k] / (2 * np.pi)) - 0.5 * D - H
+    return t_lik + t_pml - t_qml
+
+
+def _mix_terms(R, alpha_q, alpha_p):
+    """E[ln p(Z|pi)] + E[ln p(pi)] - E[ln q(Z)] - E[ln q(pi)] of PRML 10.72, 10.73, 10.75, 10.76."""
+    Elnpi = digamma(alpha_q) - digamma(alpha_q.sum())
     t_z = (R * Elnpi[None, :]).sum()
-    t_ppi = _lnC(p.alpha) + ((p.alpha - 1) * Elnpi).sum()
+    t_ppi = _lnC(alpha_p) + ((alpha_p - 1) * Elnpi).sum()
     with np.errstate(divide="ignore", invalid="ignore"):
         t_qz = np.where(R > 0, R * np.log(R), 0.0).sum()
-    t_qpi = ((q.alpha - 1) * Elnpi).sum() + _lnC(q.alpha)
-    return t_lik + t_z + t_ppi + t_pml - t_qz - t_qpi - t_qml
+    t_qpi = ((alpha_q - 1) * Elnpi).sum() + _lnC(alpha_q)
+    return t_z + t_ppi - t_qz - t_qpi
+
+
+def elbo_bishop(X, q, p):
+    """PRML 10.70: E[ln p(X|Z,mu,Lam)] + E[ln p(Z|pi)] + E[ln p(pi)] + E[ln p(mu,Lam)]
+    - E[ln q(Z)] - E[ln q(pi)] - E[ln q(mu,Lam)], with per-component prior parameters."""
+    X = np.asarray(X, np.float64)
+    R, _ = responsibilities(X, q)
+    return (_nw_terms(X, R, q.kappa, q.m, q.Winv, q.nu, p.kappa, p.m, p.Winv, p.nu)
+            + _mix_terms(R, q.alpha, p.alpha))
+
+
+def elbo_bishop_blocks(X, q, p, split):
+    """The same seven-term bound for the two-factor model of Sec. 2.1.2: coordinates [0, split) and
+    [split, D) each carry their own Normal-Wishart factor (kappa, nu of shape (K, 2)), the
+    log-responsibility is the sum of the two factors' terms with E[ln pi] counted once, and the
+    likelihood and parameter terms are summed over the factors."""
+    X = np.asarray(X, np.float64)
+    idx = [np.arange(0, split), np.arange(split, X.shape[1])]
+    Elnpi = digamma(q.alpha) - digamma(q.alpha.sum())
+    r = -Elnpi[None, :]
+    for b, i in enumerate(idx):
+        r = r + rho(X[:, i], q.alpha, q.kappa[:, b], q.m[:, i], q.Winv[:, i][:, :, i], q.nu[:, b])
+    R = np.exp(r - logsumexp(r, axis=1, keepdims=True))
+    t = _mix_terms(R, q.alpha, p.alpha)
+    for b, i in enumerate(idx):
+        t += _nw_terms(X[:, i], R, q.kappa[:, b], q.m[:, i], q.Winv[:, i][:, :, i], q.nu[:, b],
+                       p.kappa[:, b], p.m[:, i], p.Winv[:, i][:, :, i], p.nu[:, b])
+    return t
 
 
 def update_natural(p, R, X):

@@ -28,9 +28,14 @@ __global__ void k_init_state(StateHeader* hdr, double* prior, double* post, cons
   r[0] = in.alpha0;
   r[1] = in.kappa0;
   r[2] = in.nu0;
+  if (in.split > 0) {  // second block: the same kappa0 and nu0
+    r[rec_kc(D)] = in.kappa0;
+    r[rec_kc(D) + 1] = in.nu0;
+  }
   for (int i = 0; i < D; ++i) r[3 + i] = m0[k * D + i];
   for (int i = 0; i < D; ++i)
-    for (int j = i; j < D; ++j) r[3 + D + tri_up(i, j, D)] = in.W0inv[i * D + j];
+    for (int j = i; j < D; ++j)
+      r[3 + D + tri_up(i, j, D)] = coord_block(i, in.split) == coord_block(j, in.split) ? in.W0inv[i * D + j] : 0.0;
   for (int i = 0; i < REC; ++i) {
     prior[k * REC + i] = r[i];
     post[k * REC + i] = r[i];
@@ -270,7 +275,7 @@ __device__ void write_dead_row(const CoefOut& o, int64_t k, int dts, bool expand
 template <int D>
 __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior, const double* __restrict__ post,
                                                 int64_t K, int64_t Kpad, const FrameInfo* __restrict__ fr,
-                                                CoefOut o, int* flags) {
+                                                CoefOut o, int* flags, int split) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
   constexpr int dts = D <= 6 ? 32 : 48;
@@ -280,8 +285,16 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
   }
   const double* q = post + k * REC;
   const double* p = prior + k * REC;
-  const double alpha = q[0], kappa = q[1], nu = q[2];
-  const float lam = comp_lambda(q, D);
+  // one block (split = 0) or two independent Normal-Wishart blocks (see coord_block)
+  const int nb = split > 0 ? 2 : 1;
+  const double alpha = q[0];
+  double kap[2], nuv[2];
+  int Db[2] = {split > 0 ? split : D, split > 0 ? D - split : 0};
+  for (int b = 0; b < 2; ++b) {
+    kap[b] = rec_kappa(q, D, b < nb ? b : 0);
+    nuv[b] = rec_nu(q, D, b < nb ? b : 0);
+  }
+  const float lam = comp_lambda(q, D, split);
   o.lam[k] = lam;
   double m[D];
   for (int i = 0; i < D; ++i) m[i] = q[3 + i];
@@ -294,8 +307,8 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     o.lam[k] = 0.0f;
     return;
   }
-  double lndetW = 0.0;
-  for (int i = 0; i < D; ++i) lndetW -= 2.0 * log(L[i][i]);
+  double lndet_b[2] = {0.0, 0.0};
+  for (int i = 0; i < D; ++i) lndet_b[coord_block(i, split)] -= 2.0 * log(L[i][i]);
   // Linv = L^{-1} (lower triangular)
   double Li[D][D];
   for (int j = 0; j < D; ++j) {
@@ -315,42 +328,49 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
       for (int t = b; t < D; ++t) v += Li[t][a] * Li[t][b];
       W[a][b] = W[b][a] = v;
     }
-  double ElnLam = D * LN2 + lndetW;
-  for (int i = 1; i <= D; ++i) ElnLam += vb_digamma(0.5 * (nu + 1.0 - i));
+  double ElnLam_b[2] = {0.0, 0.0};
+  for (int b = 0; b < nb; ++b) {
+    ElnLam_b[b] = Db[b] * LN2 + lndet_b[b];
+    for (int i = 1; i <= Db[b]; ++i) ElnLam_b[b] += vb_digamma(0.5 * (nuv[b] + 1.0 - i));
+  }
   const double psi_sum = vb_digamma(fr->sum_alpha_q);
   const double psi_a = vb_digamma(alpha);
   const double Elnpi = psi_a - psi_sum;
-  const double g = Elnpi + 0.5 * ElnLam - 0.5 * D * LN2PI - 0.5 * D / kappa;
+  double g = Elnpi;
+  for (int b = 0; b < nb; ++b) g += 0.5 * ElnLam_b[b] - 0.5 * Db[b] * LN2PI - 0.5 * Db[b] / kap[b];
 
   // direct-form row (raw coordinates, log2 units)
   double* T = o.direct + k * dts;
   T[0] = LOG2E * g;
   for (int i = 0; i < D; ++i) T[1 + i] = m[i];
-  const double us = sqrt(0.5 * nu * LOG2E);
-  for (int i = 0; i < D; ++i)
+  for (int i = 0; i < D; ++i) {
+    const double us = sqrt(0.5 * nuv[coord_block(i, split)] * LOG2E);
     for (int j = 0; j <= i; ++j) T[1 + D + i * (i + 1) / 2 + j] = us * Li[i][j];
+  }
   for (int i = 1 + D + D * (D + 1) / 2; i < dts; ++i) T[i] = 0.0;
 
   // expanded coefficients in centred/scaled coordinates x' = (x - mu) / s (MFMA paths: D <= 6)
   if constexpr (D <= 6) {
   double ms[D], Wm[D];
   for (int i = 0; i < D; ++i) ms[i] = (m[i] - (double)fr->mu[i]) / fr->s[i];
-  double mWm = 0.0;
+  double mWm_b[2] = {0.0, 0.0};
   for (int a = 0; a < D; ++a) {
     double v = 0.0;
     for (int b = 0; b < D; ++b) v += W[a][b] * fr->s[a] * fr->s[b] * ms[b];
     Wm[a] = v;
-    mWm += ms[a] * v;
+    mWm_b[coord_block(a, split)] += ms[a] * v;
   }
   double c[FP];
   for (int i = 0; i < FP; ++i) c[i] = 0.0;
-  c[0] = LOG2E * (g - 0.5 * nu * mWm);
-  for (int a = 0; a < D; ++a) c[1 + a] = LOG2E * nu * Wm[a];
+  double cq = 0.0;
+  for (int b = 0; b < nb; ++b) cq += nuv[b] * mWm_b[b];
+  c[0] = LOG2E * (g - 0.5 * cq);
+  for (int a = 0; a < D; ++a) c[1 + a] = LOG2E * nuv[coord_block(a, split)] * Wm[a];
   int oo = 1 + D;
   for (int a = 0; a < D; ++a)
     for (int b = a; b < D; ++b) {
-      const double wab = W[a][b] * fr->s[a] * fr->s[b];
-      c[oo++] = (a == b ? -0.5 : -1.0) * LOG2E * nu * wab;
+      const double wab = W[a][b] * fr->s[a] * fr->s[b];  // zero across blocks
+      c[oo++] = (a == b ? -0.5 : -1.0) * LOG2E * nuv[coord_block(a, split)] * wab;
     }
   double nn = 0.0;
   const int64_t row = o.cinv ? (int64_t)o.cinv[k] : k;
@@ -373,8 +393,9 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
   }
   }
 
-  // KL(NW(q_k) || NW(p_k)) + the per-component part of KL(Dir(alpha) || Dir(alpha_p))
-  const double ap = p[0], kp = p[1], np = p[2];
+  // KL(NW(q_k) || NW(p_k)), summed over the blocks, + the per-component part of
+  // KL(Dir(alpha) || Dir(alpha_p))
+  const double ap = p[0];
   double Lp[D][D];
   load_winv<D>(p, Lp);
   double Ap[D][D];
@@ -385,20 +406,26 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     o.kl[k] = 0.0;
     return;
   }
-  double lndetWp = 0.0;
-  for (int i = 0; i < D; ++i) lndetWp -= 2.0 * log(Lp[i][i]);
-  double quad = 0.0, tr = 0.0;
+  double lndetp_b[2] = {0.0, 0.0};
+  for (int i = 0; i < D; ++i) lndetp_b[coord_block(i, split)] -= 2.0 * log(Lp[i][i]);
   double dm[D];
   for (int i = 0; i < D; ++i) dm[i] = m[i] - p[3 + i];
-  for (int a = 0; a < D; ++a)
-    for (int b = 0; b < D; ++b) {
-      quad += dm[a] * W[a][b] * dm[b];
-      tr += Ap[a][b] * W[b][a];
-    }
-  const double lnB_q = -0.5 * nu * lndetW - 0.5 * nu * D * LN2 - vb_mvlgamma(0.5 * nu, D);
-  const double lnB_p = -0.5 * np * lndetWp - 0.5 * np * D * LN2 - vb_mvlgamma(0.5 * np, D);
-  const double klnw = 0.5 * (kp * nu * quad + D * kp / kappa - D + D * log(kappa / kp)) + lnB_q - lnB_p +
-                      0.5 * (nu - np) * ElnLam - 0.5 * nu * D + 0.5 * nu * tr;
+  double klnw = 0.0;
+  for (int bb = 0; bb < nb; ++bb) {
+    double quad = 0.0, tr = 0.0;
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b)
+        if (coord_block(a, split) == bb && coord_block(b, split) == bb) {
+          quad += dm[a] * W[a][b] * dm[b];
+          tr += Ap[a][b] * W[b][a];
+        }
+    const double nu = nuv[bb], kappa = kap[bb], kp = rec_kappa(p, D, bb), np = rec_nu(p, D, bb);
+    const int Dd = Db[bb];
+    const double lnB_q = -0.5 * nu * lndet_b[bb] - 0.5 * nu * Dd * LN2 - vb_mvlgamma(0.5 * nu, Dd);
+    const double lnB_p = -0.5 * np * lndetp_b[bb] - 0.5 * np * Dd * LN2 - vb_mvlgamma(0.5 * np, Dd);
+    klnw += 0.5 * (kp * nu * quad + Dd * kp / kappa - Dd + Dd * log(kappa / kp)) + lnB_q - lnB_p +
+            0.5 * (nu - np) * ElnLam_b[bb] - 0.5 * nu * Dd + 0.5 * nu * tr;
+  }
   const double kd = -lgamma(alpha) + lgamma(ap) + (alpha - ap) * (psi_a - psi_sum);
   o.kl[k] = klnw + kd;
 }
@@ -415,7 +442,8 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
   switch (d.D) {
 #define VB_CASE(DD) \
   case DD:          \
-    hipLaunchKernelGGL(k_coeffs<DD>, grid, blk, 0, s, d.prior(), d.post(), d.K, L.Kpad, d.frame(), o, fl); break;
+    hipLaunchKernelGGL(k_coeffs<DD>, grid, blk, 0, s, d.prior(), d.post(), d.K, L.Kpad, d.frame(), o, fl, d.split); \
+    break;
     VB_CASE(1) VB_CASE(2) VB_CASE(3) VB_CASE(4) VB_CASE(5) VB_CASE(6) VB_CASE(7) VB_CASE(8)
 #undef VB_CASE
     default:
@@ -428,7 +456,7 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
 // conjugate update through natural parameters (FP64, one thread per component)
 // ---------------------------------------------------------------------------
 __global__ void k_update(double* prior, double* post, const double* __restrict__ st, int D, int64_t K,
-                         int commit) {
+                         int commit, int split) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const int F = nfeat(D);
@@ -437,23 +465,31 @@ __global__ void k_update(double* prior, double* post, const double* __restrict__
   const double Nk = S[0];
   double r[REC];
   for (int i = 0; i < REC; ++i) r[i] = 0.0;
-  const double kp = p[1];
-  const double kappa = kp + Nk;
+  // per block: kappa = kappa_p + N, nu = nu_p + N (both blocks see the same N_k)
+  double kp[2], kappa[2];
+  for (int b = 0; b < (split > 0 ? 2 : 1); ++b) {
+    kp[b] = rec_kappa(p, D, b);
+    kappa[b] = kp[b] + Nk;
+    r[b ? rec_kc(D) : 1] = kappa[b];
+    r[b ? rec_kc(D) + 1 : 2] = rec_nu(p, D, b) + Nk;
+  }
   r[0] = p[0] + Nk;
-  r[1] = kappa;
-  r[2] = p[2] + Nk;
   double m[MAXD], mp[MAXD];
   for (int i = 0; i < D; ++i) {
+    const int b = coord_block(i, split);
     mp[i] = p[3 + i];
-    m[i] = (kp * mp[i] + S[1 + i]) / kappa;
+    m[i] = (kp[b] * mp[i] + S[1 + i]) / kappa[b];
     r[3 + i] = m[i];
   }
-  // W^{-1} + kappa m m^T is additive: T3 = T3_prior + S2
+  // W^{-1} + kappa m m^T is additive within a block: T3 = T3_prior + S2; zero across blocks
   int o = 1 + D;
   for (int i = 0; i < D; ++i)
     for (int j = i; j < D; ++j) {
       const int t = tri_up(i, j, D);
-      r[3 + D + t] = p[3 + D + t] + S[o + t] + kp * mp[i] * mp[j] - kappa * m[i] * m[j];
+      const int b = coord_block(i, split);
+      r[3 + D + t] = b == coord_block(j, split)
+                         ? p[3 + D + t] + S[o + t] + kp[b] * mp[i] * mp[j] - kappa[b] * m[i] * m[j]
+                         : 0.0;
     }
   for (int i = 0; i < REC; ++i) post[k * REC + i] = r[i];
   if (commit)
@@ -462,7 +498,7 @@ __global__ void k_update(double* prior, double* post, const double* __restrict__
 
 hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s) {
   hipLaunchKernelGGL(k_update, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.prior(), d.post(),
-                     d.at<double>(d.L->stats), d.D, d.K, commit);
+                     d.at<double>(d.L->stats), d.D, d.K, commit, d.split);
   return hipGetLastError();
 }
 
@@ -502,23 +538,31 @@ hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStr
 // ---------------------------------------------------------------------------
 // parameter get / set (full symmetric W^{-1} outside, upper-packed inside)
 // ---------------------------------------------------------------------------
+// kappa and nu hold one value per block (1 or 2 per component)
 __global__ void k_get_set(double* rec, int set, int D, int64_t K, double* alpha, double* kappa, double* m,
-                          double* Winv, double* nu) {
+                          double* Winv, double* nu, int split) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
+  const int nb = split > 0 ? 2 : 1;
   double* r = rec + k * REC;
   if (set) {
     r[0] = alpha[k];
-    r[1] = kappa[k];
-    r[2] = nu[k];
+    for (int b = 0; b < nb; ++b) {
+      r[b ? rec_kc(D) : 1] = kappa[k * nb + b];
+      r[b ? rec_kc(D) + 1 : 2] = nu[k * nb + b];
+    }
     for (int i = 0; i < D; ++i) r[3 + i] = m[k * D + i];
     for (int i = 0; i < D; ++i)
       for (int j = i; j < D; ++j)
-        r[3 + D + tri_up(i, j, D)] = 0.5 * (Winv[(k * D + i) * D + j] + Winv[(k * D + j) * D + i]);
+        r[3 + D + tri_up(i, j, D)] = coord_block(i, split) == coord_block(j, split)
+                                         ? 0.5 * (Winv[(k * D + i) * D + j] + Winv[(k * D + j) * D + i])
+                                         : 0.0;
   } else {
     alpha[k] = r[0];
-    kappa[k] = r[1];
-    nu[k] = r[2];
+    for (int b = 0; b < nb; ++b) {
+      kappa[k * nb + b] = r[b ? rec_kc(D) : 1];
+      nu[k * nb + b] = r[b ? rec_kc(D) + 1 : 2];
+    }
     for (int i = 0; i < D; ++i) m[k * D + i] = r[3 + i];
     for (int i = 0; i < D; ++i)
       for (int j = i; j < D; ++j) {
@@ -533,7 +577,7 @@ hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, d
                           double* Winv, double* nu, hipStream_t s) {
   double* rec = which == 0 ? d.post() : d.prior();
   hipLaunchKernelGGL(k_get_set, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, rec, set, d.D, d.K, alpha,
-                     kappa, m, Winv, nu);
+                     kappa, m, Winv, nu, d.split);
   return hipGetLastError();
 }
 

@@ -43,12 +43,12 @@ __global__ void k_point_keys(const float* __restrict__ X, int64_t N, int64_t Npo
 // classes are octave pairs (factor 4 in lambda) below an anchor, the half-octave bin of the 90th
 // percentile of lambda over the components: class 0 holds lambda >= anchor / 4, class 3 the
 // broadest components (and degenerate ones).
-__global__ void k_lam_hist(const double* __restrict__ post, int64_t K, int D, int* __restrict__ hist) {
+__global__ void k_lam_hist(const double* __restrict__ post, int64_t K, int D, int split, int* __restrict__ hist) {
   __shared__ int h[LAM_BINS];
   for (int i = threadIdx.x; i < LAM_BINS; i += blockDim.x) h[i] = 0;
   __syncthreads();
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&h[lam_bin(comp_lambda(post + k * REC, D))], 1);
+    atomicAdd(&h[lam_bin(comp_lambda(post + k * REC, D, split))], 1);
   __syncthreads();
   for (int i = threadIdx.x; i < LAM_BINS; i += blockDim.x)
     if (h[i]) atomicAdd(&hist[i], h[i]);
@@ -69,8 +69,8 @@ __global__ void k_zero_hist(int* hist) {
   if (threadIdx.x < LAM_BINS) hist[threadIdx.x] = 0;
 }
 
-__global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t Kpow, int D, const FrameInfo* fr,
-                            unsigned long long* __restrict__ keys) {
+__global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t Kpow, int D, int split,
+                            const FrameInfo* fr, unsigned long long* __restrict__ keys) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpow) return;
   if (k >= K) {
@@ -78,7 +78,7 @@ __global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t 
     return;
   }
   const double* q = post + k * REC;
-  const int b = lam_bin(comp_lambda(q, D));
+  const int b = lam_bin(comp_lambda(q, D, split));
   const int gap = fr->lam_anchor - b;
   const uint32_t cls = b == 0 ? 3u : (gap < 4 ? 0u : (uint32_t)min(gap / 4, 3));
   const uint32_t code = (cls << 30) | morton_code(nullptr, q + 3, D, fr);
@@ -259,10 +259,10 @@ hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
   unsigned long long* keys = d.at<unsigned long long>(L.ckeys);
   int* hist = d.at<int>(L.lhist);
   hipLaunchKernelGGL(k_zero_hist, dim3(1), dim3(LAM_BINS), 0, s, hist);
-  hipLaunchKernelGGL(k_lam_hist, dim3(64), dim3(256), 0, s, d.post(), d.K, d.D, hist);
+  hipLaunchKernelGGL(k_lam_hist, dim3(64), dim3(256), 0, s, d.post(), d.K, d.D, d.split, hist);
   hipLaunchKernelGGL(k_lam_anchor, dim3(1), dim3(64), 0, s, hist, d.K, d.frame());
   hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((kpow + 255) / 256)), dim3(256), 0, s, d.post(), d.K, kpow, d.D,
-                     d.frame(), keys);
+                     d.split, d.frame(), keys);
   hipError_t e = launch_sort_keys(keys, kpow, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, keys, d.K,

@@ -39,7 +39,7 @@ struct vbgs_ctx {
   int nsplit;
   float T2;
   std::string err;
-  DevPtrs dev() const { return DevPtrs{(char*)ws, (double*)state, &L, p.D, p.K}; }
+  DevPtrs dev() const { return DevPtrs{(char*)ws, (double*)state, &L, p.D, p.K, p.modal_split}; }
 };
 
 namespace {
@@ -124,8 +124,16 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "cull must be 0 or 1";
     return VBGS_ERR_ARG;
   }
+  if (p->modal_split < 0 || p->modal_split >= p->D) {
+    if (why) *why = "modal_split must be in 0..D-1";
+    return VBGS_ERR_ARG;
+  }
+  if (p->modal_split > 0 && (rec_kc(p->D) + 2 > REC || p->proposal)) {
+    if (why) *why = "the two-factor model needs D <= 7 (record room for the colour kappa, nu) and no proposal";
+    return VBGS_ERR_UNSUPPORTED;
+  }
   for (int i = 0; i < 4; ++i)
-    if (p->reserved[i] != 0 || p->reserved1 != 0) {
+    if (p->reserved[i] != 0) {
       if (why) *why = "reserved fields must be zero";
       return VBGS_ERR_ARG;
     }
@@ -348,6 +356,12 @@ vbgs_status vbgs_init(vbgs_ctx** out, const vbgs_params* p, const double* m0, co
   if (!out || !m0 || !W0 || !state || !workspace) return VBGS_ERR_ARG;
   if (!aligned(state) || !aligned(workspace)) return VBGS_ERR_ARG;
   const int D = p->D;
+  // with two blocks the scale matrix is block diagonal: entries across the blocks are ignored
+  double W0b[MAXD * MAXD];
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j)
+      W0b[i * D + j] = coord_block(i, p->modal_split) == coord_block(j, p->modal_split) ? W0[i * D + j] : 0.0;
+  W0 = W0b;
   // W0^{-1} on the host: Cholesky of W0 (rejects non-PD), then invert
   double L[MAXD][MAXD] = {{0}};
   for (int j = 0; j < D; ++j) {
@@ -383,6 +397,7 @@ vbgs_status vbgs_init(vbgs_ctx** out, const vbgs_params* p, const double* m0, co
   in.alpha0 = p->alpha0;
   in.kappa0 = p->kappa0;
   in.nu0 = p->nu0;
+  in.split = p->modal_split;
   vbgs_ctx* c = new_ctx(p, state, workspace);
   if (!c) return VBGS_ERR_ARG;
   hipError_t e = launch_init_state(c->dev(), m0, in, S(stream));

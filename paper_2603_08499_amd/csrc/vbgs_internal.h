@@ -81,16 +81,25 @@ __device__ __forceinline__ float f_up(double v) {
   return (double)f < v ? nextafterf(f, INFINITY) : f;
 }
 
+// Coordinate blocks. With a modal split s (0 < s < D) a component is two independent
+// Normal-Wishart blocks (Sec. 2.1.2): coordinates [0, s) and [s, D), each with its own kappa, nu
+// and W (cross-block entries of W^-1 are zero). The record keeps block 0's kappa and nu at slots
+// 1 and 2 and block 1's at KC and KC + 1. With s = 0 all coordinates form one block.
+__host__ __device__ __forceinline__ int coord_block(int i, int split) { return (split > 0 && i >= split) ? 1 : 0; }
+__host__ __device__ __forceinline__ int rec_kc(int D) { return 3 + D + D * (D + 1) / 2; }
+__device__ __forceinline__ double rec_kappa(const double* q, int D, int b) { return b ? q[rec_kc(D)] : q[1]; }
+__device__ __forceinline__ double rec_nu(const double* q, int D, int b) { return b ? q[rec_kc(D) + 1] : q[2]; }
+
 // lambda_k, a lower bound on the curvature of the score (log2 units) in the first min(D, 3)
-// raw coordinates: s2 = g2 - (nu log2e / 2) d^T W d and, with d restricted to those coordinates
-// S, d^T W d >= d_S^T ((W^-1)_SS)^-1 d_S >= |d_S|^2 / tr (W^-1)_SS. Slightly reduced so that its
-// FP32 rounding stays below the bound. q: the component's record (alpha, kappa, nu, m, packed
-// upper triangle of W^-1). Returns 0 when the trace is not positive.
-__device__ __forceinline__ float comp_lambda(const double* q, int D) {
+// raw coordinates S: s2 = g2 - (log2e / 2) d^T A d with A = blockdiag(nu_b W_b) and, with d
+// restricted to S, d^T A d >= d_S^T ((A^-1)_SS)^-1 d_S >= |d_S|^2 / tr (A^-1)_SS, where
+// (A^-1)_ii = (W^-1)_ii / nu_b(i). Slightly reduced so that its FP32 rounding stays below the bound.
+// q: the component's record. Returns 0 when the trace is not positive.
+__device__ __forceinline__ float comp_lambda(const double* q, int D, int split) {
   const int ns = D < 3 ? D : 3;
   double tr = 0.0;
-  for (int i = 0; i < ns; ++i) tr += q[3 + D + i * D - i * (i - 1) / 2];
-  return tr > 0.0 ? (float)(0.5 * q[2] * LOG2E / tr * (1.0 - 1e-6)) : 0.0f;
+  for (int i = 0; i < ns; ++i) tr += q[3 + D + i * D - i * (i - 1) / 2] / rec_nu(q, D, coord_block(i, split));
+  return tr > 0.0 ? (float)(0.5 * LOG2E / tr * (1.0 - 1e-6)) : 0.0f;
 }
 
 // histogram bin of lambda in half-octaves, 0..127 (lambda <= 0 maps to bin 0)
@@ -249,6 +258,7 @@ struct DevPtrs {
   const Layout* L;
   int D;
   int64_t K;
+  int split;  // modal split (0: one block)
   template <class T>
   T* at(size_t off) const {
     return reinterpret_cast<T*>(ws + off);
@@ -261,6 +271,7 @@ struct DevPtrs {
 struct Init0 {
   double W0inv[MAXD * MAXD];
   double alpha0, kappa0, nu0;
+  int split;
 };
 
 hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& init, hipStream_t s);

@@ -29,7 +29,7 @@ def _stream(s=None):
 
 
 def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x3", exact=True,
-                screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096, cull=True):
+                screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096, cull=True, modal_split=0):
     p = _lib.Params()
     L = _lib.load()
     st = L.vbgs_default_params(ctypes.byref(p), int(D), int(K), int(n_max))
@@ -46,6 +46,7 @@ def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x
     p.C = int(C)
     p.train_batch = int(train_batch)
     p.cull = 1 if cull else 0
+    p.modal_split = int(modal_split)
     return p
 
 
@@ -131,11 +132,12 @@ class VBGS:
     def get_params(self, which="posterior"):
         w = 0 if which == "posterior" else 1
         K, D, dev = self.K, self.D, self.device
+        kn = (K, 2) if self.params.modal_split > 0 else (K,)  # one kappa and nu per block
         o = dict(alpha=torch.empty(K, dtype=torch.float64, device=dev),
-                 kappa=torch.empty(K, dtype=torch.float64, device=dev),
+                 kappa=torch.empty(kn, dtype=torch.float64, device=dev),
                  m=torch.empty((K, D), dtype=torch.float64, device=dev),
                  Winv=torch.empty((K, D, D), dtype=torch.float64, device=dev),
-                 nu=torch.empty(K, dtype=torch.float64, device=dev))
+                 nu=torch.empty(kn, dtype=torch.float64, device=dev))
         self._check(self.lib.vbgs_get_params(self.ctx, w, _ptr(o["alpha"]), _ptr(o["kappa"]), _ptr(o["m"]),
                                              _ptr(o["Winv"]), _ptr(o["nu"]), _stream()))
         return o
@@ -144,6 +146,9 @@ class VBGS:
         w = 0 if which == "posterior" else 1
         t = [torch.as_tensor(np.asarray(a, np.float64) if not torch.is_tensor(a) else a, dtype=torch.float64)
              .to(self.device).contiguous() for a in (alpha, kappa, m, Winv, nu)]
+        nb = 2 if self.params.modal_split > 0 else 1
+        if t[1].numel() != self.K * nb or t[4].numel() != self.K * nb:
+            raise ValueError("kappa and nu need %d value(s) per component" % nb)
         self._keep = t  # alive until the stream has consumed them
         self._check(self.lib.vbgs_set_params(self.ctx, w, *[_ptr(a) for a in t], _stream()))
 

@@ -58,6 +58,15 @@ def test_query_sizes_and_validation():
     # the proposal needs the exact MFMA mode; its weights and Adam moments live in the state
     with pytest.raises(P.VBGSError):
         P.query_sizes(P.make_params(6, 10, 10, score_prec="fp64", proposal=True))
+    # two-factor model: split inside 0..D-1, room in the record for the second kappa, nu, no proposal
+    P.query_sizes(P.make_params(6, 10, 10, modal_split=3))
+    P.query_sizes(P.make_params(7, 10, 10, score_prec="fp64", modal_split=3))
+    for args, status in [(dict(D=6, modal_split=6), -1), (dict(D=6, modal_split=-1), -1),
+                         (dict(D=8, score_prec="fp64", modal_split=3), -7),
+                         (dict(D=6, modal_split=3, proposal=True), -7)]:
+        with pytest.raises(P.VBGSError) as e:
+            P.query_sizes(P.make_params(K=10, n_max=10, **args))
+        assert e.value.status == status, args
     s0, w0 = P.query_sizes(P.make_params(6, 1000, 500))
     s1, w1 = P.query_sizes(P.make_params(6, 1000, 500, proposal=True))
     n_train = 128 * 6 + 128 + 128 * 128 + 128 + 1000 * 128 + 1000
