@@ -101,7 +101,13 @@ typedef struct {
                               the matching diagonal block of W0, entries of W0 across the blocks are
                               ignored). nu0 must exceed the block sizes minus 1. Needs D <= 7 and
                               proposal = 0 (else VBGS_ERR_UNSUPPORTED). */
-  int64_t reserved[4];     /* must be zero */
+  int32_t cull_dims;       /* leading coordinates the culled sweep bounds distances in, 0..3.
+                              0 (default): modal_split if it is 1..3, else 2 for D = 5 (pixel
+                              u, v, r, g, b) and min(D, 3) otherwise. Any choice gives the same
+                              results; coordinates with a much weaker precision than the others
+                              only loosen the bounds (slower). */
+  int32_t reserved0;       /* must be zero */
+  int64_t reserved[3];     /* must be zero */
 } vbgs_params;
 
 #define VBGS_H 128         /* hidden width of the proposal network (= embedding width) */

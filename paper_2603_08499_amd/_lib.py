@@ -22,7 +22,8 @@ class Params(ctypes.Structure):
                 ("alpha0", ctypes.c_double), ("score_prec", ctypes.c_int32), ("exact", ctypes.c_int32),
                 ("screen_margin", ctypes.c_double), ("n_split", ctypes.c_int32), ("proposal", ctypes.c_int32),
                 ("C", ctypes.c_int32), ("train_batch", ctypes.c_int32), ("cull", ctypes.c_int32),
-                ("modal_split", ctypes.c_int32), ("reserved", ctypes.c_int64 * 4)]
+                ("modal_split", ctypes.c_int32), ("cull_dims", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved", ctypes.c_int64 * 3)]
 
 
 _lib = None

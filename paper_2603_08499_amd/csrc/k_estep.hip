@@ -526,7 +526,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ int32_t tks[1][64];  // component indices of the tile being screened
   const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
   const int64_t j0 = xcd_block(blockIdx.x, gridDim.x) * (P1_PB * 16);  // sorted positions
-  const int ns = a.D < 3 ? a.D : 3;
+  const int ns = a.nsp;
   float* mv = mvs[w];
   const int32_t* pid = pids[w];
 
@@ -899,7 +899,7 @@ __device__ __forceinline__ void over_rows(const EArgs& a, const float* x, float 
   if (a.cull) {
     float x3[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) x3[i] = i < DT ? x[i] : 0.0f;
+    for (int i = 0; i < 3; ++i) x3[i] = i < DT && i < a.nsp ? x[i] : 0.0f;
     const int64_t ntiles = a.Kpad / CT;
     for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
       const TileInfo ti = a.tinfo[t];
@@ -1403,6 +1403,7 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.nsplit = c.nsplit;
   a.T2 = c.T2;
   a.cull = c.cull;
+  a.nsp = d.nsp;
   a.eps = screen_eps(c.prec);
   return a;
 }

@@ -275,7 +275,7 @@ __device__ void write_dead_row(const CoefOut& o, int64_t k, int dts, bool expand
 template <int D>
 __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior, const double* __restrict__ post,
                                                 int64_t K, int64_t Kpad, const FrameInfo* __restrict__ fr,
-                                                CoefOut o, int* flags, int split) {
+                                                CoefOut o, int* flags, int split, int ns) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpad) return;
   constexpr int dts = D <= 6 ? 32 : 48;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     kap[b] = rec_kappa(q, D, b < nb ? b : 0);
     nuv[b] = rec_nu(q, D, b < nb ? b : 0);
   }
-  const float lam = comp_lambda(q, D, split);
+  const float lam = comp_lambda(q, D, split, ns);
   o.lam[k] = lam;
   double m[D];
   for (int i = 0; i < D; ++i) m[i] = q[3 + i];
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     RowBound rb{};
     rb.G = f_up(T[0]);
     rb.Lam = lam;
-    for (int i = 0; i < (D < 3 ? D : 3); ++i) rb.m[i] = (float)m[i];
+    for (int i = 0; i < ns; ++i) rb.m[i] = (float)m[i];
     rb.nc = o.nc[row];
     o.rowb[row] = rb;
   }
@@ -442,7 +442,7 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
   switch (d.D) {
 #define VB_CASE(DD) \
   case DD:          \
-    hipLaunchKernelGGL(k_coeffs<DD>, grid, blk, 0, s, d.prior(), d.post(), d.K, L.Kpad, d.frame(), o, fl, d.split); \
+    hipLaunchKernelGGL(k_coeffs<DD>, grid, blk, 0, s, d.prior(), d.post(), d.K, L.Kpad, d.frame(), o, fl, d.split, d.nsp); \
     break;
     VB_CASE(1) VB_CASE(2) VB_CASE(3) VB_CASE(4) VB_CASE(5) VB_CASE(6) VB_CASE(7) VB_CASE(8)
 #undef VB_CASE

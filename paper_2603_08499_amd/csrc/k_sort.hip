@@ -15,11 +15,10 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   return v;
 }
 
-// Morton code of the first min(D, 3) coordinates, each quantised to 10 bits over the frame's
+// Morton code of the first ns (<= 3) coordinates, each quantised to 10 bits over the frame's
 // window mu +- 4 s (clamped): the same map for points and component means
-__device__ __forceinline__ uint32_t morton_code(const float* x, const double* xd, int D, const FrameInfo* fr) {
+__device__ __forceinline__ uint32_t morton_code(const float* x, const double* xd, int ns, const FrameInfo* fr) {
   uint32_t code = 0;
-  const int ns = D < 3 ? D : 3;
   for (int i = 0; i < ns; ++i) {
     const double v = x ? (double)x[i] : xd[i];
     double u = (v - (double)fr->mu[i]) / (8.0 * fr->s[i]) + 0.5;
@@ -30,11 +29,11 @@ __device__ __forceinline__ uint32_t morton_code(const float* x, const double* xd
   return code;
 }
 
-__global__ void k_point_keys(const float* __restrict__ X, int64_t N, int64_t Npow, int D, const FrameInfo* fr,
+__global__ void k_point_keys(const float* __restrict__ X, int64_t N, int64_t Npow, int D, int ns, const FrameInfo* fr,
                              unsigned long long* __restrict__ keys) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= Npow) return;
-  keys[n] = n < N ? ((unsigned long long)morton_code(X + n * D, nullptr, D, fr) << 32) | (unsigned long long)n
+  keys[n] = n < N ? ((unsigned long long)morton_code(X + n * D, nullptr, ns, fr) << 32) | (unsigned long long)n
                   : ~0ull;
 }
 
@@ -43,12 +42,13 @@ __global__ void k_point_keys(const float* __restrict__ X, int64_t N, int64_t Npo
 // classes are octave pairs (factor 4 in lambda) below an anchor, the half-octave bin of the 90th
 // percentile of lambda over the components: class 0 holds lambda >= anchor / 4, class 3 the
 // broadest components (and degenerate ones).
-__global__ void k_lam_hist(const double* __restrict__ post, int64_t K, int D, int split, int* __restrict__ hist) {
+__global__ void k_lam_hist(const double* __restrict__ post, int64_t K, int D, int split, int ns,
+                           int* __restrict__ hist) {
   __shared__ int h[LAM_BINS];
   for (int i = threadIdx.x; i < LAM_BINS; i += blockDim.x) h[i] = 0;
   __syncthreads();
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&h[lam_bin(comp_lambda(post + k * REC, D, split))], 1);
+    atomicAdd(&h[lam_bin(comp_lambda(post + k * REC, D, split, ns))], 1);
   __syncthreads();
   for (int i = threadIdx.x; i < LAM_BINS; i += blockDim.x)
     if (h[i]) atomicAdd(&hist[i], h[i]);
@@ -69,7 +69,7 @@ __global__ void k_zero_hist(int* hist) {
   if (threadIdx.x < LAM_BINS) hist[threadIdx.x] = 0;
 }
 
-__global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t Kpow, int D, int split,
+__global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t Kpow, int D, int split, int ns,
                             const FrameInfo* fr, unsigned long long* __restrict__ keys) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= Kpow) return;
@@ -78,10 +78,10 @@ __global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t 
     return;
   }
   const double* q = post + k * REC;
-  const int b = lam_bin(comp_lambda(q, D, split));
+  const int b = lam_bin(comp_lambda(q, D, split, ns));
   const int gap = fr->lam_anchor - b;
   const uint32_t cls = b == 0 ? 3u : (gap < 4 ? 0u : (uint32_t)min(gap / 4, 3));
-  const uint32_t code = (cls << 30) | morton_code(nullptr, q + 3, D, fr);
+  const uint32_t code = (cls << 30) | morton_code(nullptr, q + 3, ns, fr);
   keys[k] = ((unsigned long long)code << 32) | (unsigned long long)k;
 }
 
@@ -178,7 +178,7 @@ __global__ void k_unpack_order(const unsigned long long* __restrict__ keys, int6
 // formed from them in FP32 stays above every score of the tile. Empty (padding) tiles get G = -inf.
 __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ corder,
                                                    const uint32_t* __restrict__ ccode, int64_t K, int64_t ntiles,
-                                                   int D, const double* __restrict__ direct, int dts,
+                                                   int D, int ns, const double* __restrict__ direct, int dts,
                                                    const float* __restrict__ lam, const RowBound* __restrict__ rowb,
                                                    TileInfo* __restrict__ info, float* __restrict__ ncg) {
   // one wave per tile, lane = row
@@ -186,7 +186,6 @@ __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ c
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   const int64_t j = t * CT + lane;
-  const int ns = D < 3 ? D : 3;
   float G = -INFINITY, Lm = INFINITY, lo[3], hi[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -243,7 +242,7 @@ hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipSt
   int64_t npow = BS_LOCAL;
   while (npow < N) npow <<= 1;
   unsigned long long* keys = d.at<unsigned long long>(L.pkeys);
-  hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, s, X, N, npow, d.D, d.frame(),
+  hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, s, X, N, npow, d.D, d.nsp, d.frame(),
                      keys);
   hipError_t e = launch_sort_keys(keys, npow, s);
   if (e != hipSuccess) return e;
@@ -259,10 +258,10 @@ hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
   unsigned long long* keys = d.at<unsigned long long>(L.ckeys);
   int* hist = d.at<int>(L.lhist);
   hipLaunchKernelGGL(k_zero_hist, dim3(1), dim3(LAM_BINS), 0, s, hist);
-  hipLaunchKernelGGL(k_lam_hist, dim3(64), dim3(256), 0, s, d.post(), d.K, d.D, d.split, hist);
+  hipLaunchKernelGGL(k_lam_hist, dim3(64), dim3(256), 0, s, d.post(), d.K, d.D, d.split, d.nsp, hist);
   hipLaunchKernelGGL(k_lam_anchor, dim3(1), dim3(64), 0, s, hist, d.K, d.frame());
   hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((kpow + 255) / 256)), dim3(256), 0, s, d.post(), d.K, kpow, d.D,
-                     d.split, d.frame(), keys);
+                     d.split, d.nsp, d.frame(), keys);
   hipError_t e = launch_sort_keys(keys, kpow, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, keys, d.K,
@@ -274,7 +273,7 @@ hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s) {
   const Layout& L = *d.L;
   const int64_t ntiles = L.Kpad / CT;
   hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, d.at<int32_t>(L.corder),
-                     d.at<uint32_t>(L.ccode), d.K, ntiles, d.D, d.at<double>(L.direct), direct_stride(d.D),
+                     d.at<uint32_t>(L.ccode), d.K, ntiles, d.D, d.nsp, d.at<double>(L.direct), direct_stride(d.D),
                      d.at<float>(L.lam), d.at<RowBound>(L.rowb), d.at<TileInfo>(L.tinfo), d.at<float>(L.ncg));
   return hipGetLastError();
 }

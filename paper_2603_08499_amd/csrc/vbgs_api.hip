@@ -39,7 +39,15 @@ struct vbgs_ctx {
   int nsplit;
   float T2;
   std::string err;
-  DevPtrs dev() const { return DevPtrs{(char*)ws, (double*)state, &L, p.D, p.K, p.modal_split}; }
+  DevPtrs dev() const { return DevPtrs{(char*)ws, (double*)state, &L, p.D, p.K, p.modal_split, cull_ns()}; }
+  // leading coordinates of the culling bounds: the spatial block of the two-factor model, the pixel
+  // position of an image (D = 5), else up to three
+  int cull_ns() const {
+    if (p.cull_dims > 0) return p.cull_dims;
+    if (p.modal_split > 0 && p.modal_split <= 3) return p.modal_split;
+    if (p.D == 5) return 2;
+    return p.D < 3 ? p.D : 3;
+  }
 };
 
 namespace {
@@ -132,7 +140,15 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "the two-factor model needs D <= 7 (record room for the colour kappa, nu) and no proposal";
     return VBGS_ERR_UNSUPPORTED;
   }
-  for (int i = 0; i < 4; ++i)
+  if (p->cull_dims < 0 || p->cull_dims > 3 || p->cull_dims > p->D) {
+    if (why) *why = "cull_dims must be in 0..min(D, 3)";
+    return VBGS_ERR_ARG;
+  }
+  if (p->reserved0 != 0) {
+    if (why) *why = "reserved fields must be zero";
+    return VBGS_ERR_ARG;
+  }
+  for (int i = 0; i < 3; ++i)
     if (p->reserved[i] != 0) {
       if (why) *why = "reserved fields must be zero";
       return VBGS_ERR_ARG;

@@ -90,13 +90,12 @@ __host__ __device__ __forceinline__ int rec_kc(int D) { return 3 + D + D * (D + 
 __device__ __forceinline__ double rec_kappa(const double* q, int D, int b) { return b ? q[rec_kc(D)] : q[1]; }
 __device__ __forceinline__ double rec_nu(const double* q, int D, int b) { return b ? q[rec_kc(D) + 1] : q[2]; }
 
-// lambda_k, a lower bound on the curvature of the score (log2 units) in the first min(D, 3)
+// lambda_k, a lower bound on the curvature of the score (log2 units) in the first ns (<= 3)
 // raw coordinates S: s2 = g2 - (log2e / 2) d^T A d with A = blockdiag(nu_b W_b) and, with d
 // restricted to S, d^T A d >= d_S^T ((A^-1)_SS)^-1 d_S >= |d_S|^2 / tr (A^-1)_SS, where
 // (A^-1)_ii = (W^-1)_ii / nu_b(i). Slightly reduced so that its FP32 rounding stays below the bound.
 // q: the component's record. Returns 0 when the trace is not positive.
-__device__ __forceinline__ float comp_lambda(const double* q, int D, int split) {
-  const int ns = D < 3 ? D : 3;
+__device__ __forceinline__ float comp_lambda(const double* q, int D, int split, int ns) {
   double tr = 0.0;
   for (int i = 0; i < ns; ++i) tr += q[3 + D + i * D - i * (i - 1) / 2] / rec_nu(q, D, coord_block(i, split));
   return tr > 0.0 ? (float)(0.5 * LOG2E / tr * (1.0 - 1e-6)) : 0.0f;
@@ -259,6 +258,7 @@ struct DevPtrs {
   int D;
   int64_t K;
   int split;  // modal split (0: one block)
+  int nsp;    // leading coordinates the culling bounds use (1..3)
   template <class T>
   T* at(size_t off) const {
     return reinterpret_cast<T*>(ws + off);
@@ -335,6 +335,7 @@ struct EArgs {
   int D, dts, nsplit;
   float T2, eps;
   int cull;                   // the culled sweep ran: sorted tables and bounds are valid
+  int nsp;                    // leading coordinates of the culling bounds (1..3); the others read 0
 };
 EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out);
 // stage -1: the whole first pass; exact MFMA mode in stages 0 (clear the transpose counters),

@@ -29,7 +29,8 @@ def _stream(s=None):
 
 
 def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x3", exact=True,
-                screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096, cull=True, modal_split=0):
+                screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096, cull=True, modal_split=0,
+                cull_dims=0):
     p = _lib.Params()
     L = _lib.load()
     st = L.vbgs_default_params(ctypes.byref(p), int(D), int(K), int(n_max))
@@ -47,6 +48,7 @@ def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x
     p.train_batch = int(train_batch)
     p.cull = 1 if cull else 0
     p.modal_split = int(modal_split)
+    p.cull_dims = int(cull_dims)
     return p
 
 

@@ -171,6 +171,16 @@ def c5_prior(X: np.ndarray, K: int = 50000) -> Prior:
     return Prior(m0=distinct_rows(g, X, K), W0=r2_W0(5, K), kappa0=1.0, nu0=7.0, alpha0=1.0)
 
 
+def c5_crop(X: np.ndarray, size: int = 160, H: int = 800, W: int = 800, K_full: int = 50000):
+    """The top-left size x size pixels of a c5 frame with a prior of the full configuration's
+    shape: K scaled by the crop's share of the pixels, means drawn from the crop, W0 of K_full."""
+    Xc = np.ascontiguousarray(X.reshape(H, W, -1)[:size, :size].reshape(-1, X.shape[1]))
+    K = max(1, round(K_full * size * size / (H * W)))
+    g = rng(5, 0, 2)
+    pr = Prior(m0=distinct_rows(g, Xc, K), W0=r2_W0(5, K_full), kappa0=1.0, nu0=7.0, alpha0=1.0)
+    return Xc, pr
+
+
 # ---------------------------------------------------------------------------
 # c2 / c3: 3-D scenes of anisotropic Gaussians with a colour each
 # ---------------------------------------------------------------------------

@@ -58,6 +58,11 @@ def test_query_sizes_and_validation():
     # the proposal needs the exact MFMA mode; its weights and Adam moments live in the state
     with pytest.raises(P.VBGSError):
         P.query_sizes(P.make_params(6, 10, 10, score_prec="fp64", proposal=True))
+    # culling coordinates: 0 (automatic) or 1..min(D, 3)
+    P.query_sizes(P.make_params(5, 10, 10, cull_dims=2))
+    for args in (dict(D=6, cull_dims=4), dict(D=2, cull_dims=3), dict(D=6, cull_dims=-1)):
+        with pytest.raises(P.VBGSError):
+            P.query_sizes(P.make_params(K=10, n_max=10, **args))
     # two-factor model: split inside 0..D-1, room in the record for the second kappa, nu, no proposal
     P.query_sizes(P.make_params(6, 10, 10, modal_split=3))
     P.query_sizes(P.make_params(7, 10, 10, score_prec="fp64", modal_split=3))
@@ -78,7 +83,23 @@ def test_params_struct_layout_matches_header():
     P = L.Params
     assert ctypes.sizeof(P) == 120
     assert P.screen_margin.offset == 56 and P.n_split.offset == 64 and P.proposal.offset == 68
-    assert P.C.offset == 72 and P.train_batch.offset == 76 and P.cull.offset == 80 and P.reserved.offset == 88
+    assert P.C.offset == 72 and P.train_batch.offset == 76 and P.cull.offset == 80
+    assert P.modal_split.offset == 84 and P.cull_dims.offset == 88 and P.reserved.offset == 96
+    # the same offsets as the C compiler gives the header's struct
+    import os
+    import subprocess
+    import tempfile
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    names = [n for n, _ in P._fields_]
+    src = "#include <stdio.h>\n#include \"vbgs.h\"\nint main(void) {\n printf(\"%zu\\n\", sizeof(vbgs_params));\n"
+    src += "".join(' printf("%%zu\\n", offsetof(vbgs_params, %s));\n' % n for n in names) + " return 0;\n}\n"
+    with tempfile.TemporaryDirectory() as d:
+        with open(os.path.join(d, "o.c"), "w") as f:
+            f.write(src)
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(root, "include"), "-o", os.path.join(d, "o"),
+                               os.path.join(d, "o.c")])
+        got = [int(v) for v in subprocess.check_output([os.path.join(d, "o")]).split()]
+    assert got == [ctypes.sizeof(P)] + [getattr(P, n).offset for n in names]
 
 
 def test_null_context_calls_fail_cleanly():
