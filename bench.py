@@ -9,7 +9,7 @@ frame's prior after every update. Frames are generated on the host, copied to HB
 the timed region and cycled. A step is one whole fit step over one frame.
 
 Prints one JSON line. Options: --gpus N (only 1: the path runs on one GPU),
---steps K, --warmup W, --prec, --exact, --cull, --modal-split S, --workload {c3,c2,c4,search},
+--steps K, --warmup W, --prec, --exact, --cull, --modal-split S, --workload {c3,c2,c4,c5,search},
 --reassign-n, --no-cpu, --no-fp64.
 """
 import argparse
@@ -121,6 +121,83 @@ def run_c4(args):
     print(json.dumps(out))
 
 
+def run_c5(args):
+    """800x800 image (c5: D=5, N=640000, K=50000): coordinate-ascent steps on the one frame (E-step,
+    ELBO, update; the first `warmup` steps untimed), then the image rendered at every pixel from the
+    fitted posterior and its PSNR against the observed colours (Sec. 5.1). The oracle renders a
+    sample of pixels at the prior on the host."""
+    import torch
+    import paper_2603_08499_amd as P
+    from synth import scenes
+    dev = torch.device("cuda:0")
+    X = scenes.c5_frame()
+    pr = scenes.c5_prior(X)
+    N, D, K = X.shape[0], pr.D, pr.K
+    prec = args.c5_prec
+    m = P.VBGS(D, K, N, pr.m0, pr.W0, device=dev, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
+               score_prec=prec, exact=True, cull=bool(args.cull))
+    Xg = torch.from_numpy(X).to(dev)
+    Xq = Xg[:, :2].contiguous()
+    obs = Xg[:, 2:].contiguous()
+    pos = m.renderer(N, score_prec=prec)
+    col0, _ = m.render(pos, Xq)
+    psnr0 = P.psnr(col0, obs).cpu().numpy()[1]
+
+    def step():
+        m.estep_stats(Xg, lse=False)
+        F = m.elbo()
+        m.update(commit=False)
+        return F
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    m.timing(True)
+    m.timing_read()
+    t0 = time.perf_counter()
+    Fs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    phases = m.timing_read()
+    m.timing(False)
+    print("bench c5: %.3f ms/step" % ms, file=sys.stderr, flush=True)
+    m.render(pos, Xq)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        col, _ = m.render(pos, Xq)
+    e1.record()
+    torch.cuda.synchronize()
+    rms = e0.elapsed_time(e1) / 5
+    out_psnr = P.psnr(col, obs).cpu().numpy()
+    cpu = None
+    if not args.no_cpu:
+        from oracle import render_ref as RR
+        from oracle import vbgs_ref as R
+        idx = np.linspace(0, N - 1, args.c5_cpu_pixels).astype(np.int64)
+        qs, mc, B = RR.marginal(R.NW.from_prior(pr), 2)
+        c0 = time.perf_counter()
+        RR.render_points(X[idx, :2], qs, mc, B, chunk=64)
+        tc = time.perf_counter() - c0
+        cpu = {"value": len(idx) / tc, "unit": "pixels/s", "cores": int(R.lib().oracle_threads()), "kind": "oracle",
+               "sample": "%d evenly strided pixels of the 800x800 image rendered at the prior against all "
+                         "K=%d components (FP64) in %.1f s" % (len(idx), K, tc)}
+    avg = {k: round(v[0] / v[1], 4) for k, v in phases.items() if v[1]}
+    out = {"metric": "c5 fit step pairs/s and render pixels/s", "value": N * K / (ms * 1e-3), "unit": "pairs/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": prec + "+f64", "data": "synthetic",
+           "config": {"workload": "c5: 800x800 image of 20000 seeded blobs over one background colour, D=5, "
+                                  "N=640000, K=50000, coordinate-ascent steps on the one frame, then the "
+                                  "render of every pixel", "N": N, "K": K, "D": D, "score_prec": prec},
+           "phase_ms": avg, "elbo_last": Fs[-1].item(),
+           "render": {"ms": rms, "pixels_per_s": N / (rms * 1e-3), "psnr_db": float(out_psnr[1]),
+                      "psnr_prior_db": float(psnr0), "mse": float(out_psnr[0]),
+                      "steps_fitted": args.warmup + args.steps},
+           "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
 def sweep_traffic(args):
     """HBM bytes per launch of the screening sweep from the committed counter summary, or None when
     the summary was taken on another workload or precision or the kernel source has changed since."""
@@ -191,6 +268,8 @@ def main():
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="copy this many MiB device to device once before the timed loop (a kernel of known "
                          "traffic for scaling the HBM byte counters of a profiled run)")
+    ap.add_argument("--c5-prec", default="fp32", help="screen precision of --workload c5")
+    ap.add_argument("--c5-cpu-pixels", type=int, default=2048)
     ap.add_argument("--c4-exact", type=int, default=10)
     ap.add_argument("--c4-train-steps", type=int, default=1500)
     ap.add_argument("--c4-C", type=int, default=32)
@@ -204,6 +283,8 @@ def main():
         return run_c4(args)
     if args.workload == "search":
         return run_search(args)
+    if args.workload == "c5":
+        return run_c5(args)
     import torch
     import paper_2603_08499_amd as P
 

@@ -183,6 +183,28 @@ vbgs_status vbgs_set_params(vbgs_ctx* ctx, int32_t which, const double* alpha, c
 vbgs_status vbgs_reassign(vbgs_ctx* ctx, const float* X, int64_t N, const double* lse, const double* gumbel,
                           int64_t n, int32_t* out_points, int32_t* out_comps, void* stream);
 
+/* Rendering of the fitted mixture at query positions (the colour that Sec. 5.1's PSNR is taken on).
+ * The first s coordinates are the position, the other Dc = D - s the colour. For each query position
+ * x the colour is sum_k r_k(x) E[c | x, k]: r_k(x) are the responsibilities of the position marginal
+ * of the posterior (the Normal-Wishart (m_s, kappa, ((W^-1)_ss)^-1, nu - Dc); in the two-factor model
+ * the position factor itself), scored exactly as vbgs_estep_stats scores points; E[c | x, k] =
+ * m_c + (W^-1)_cs ((W^-1)_ss)^-1 (x - m_s) (two-factor model: m_c).
+ * model: the fitted context (its posterior is read, nothing in it changes). position: a context the
+ * caller created with D = s (= the model's modal_split when that is set), the model's K,
+ * modal_split = 0, no proposal, score_prec FP64 or an MFMA precision with exact = 1, n_max >= Nq;
+ * its prior and posterior are overwritten with the marginal and its E-step workspace is used (its
+ * statistics become invalid for vbgs_update). Xq: device Nq x s FP32 positions. regress: device
+ * K x Dc x (1 + s) FP64, caller-owned, receives [m_c, B] per component. colour_out: device Nq x Dc
+ * FP32. lse_out: device Nq FP64 (nats, the position marginal's log normaliser) or NULL.
+ * A non-positive-definite (W^-1)_ss sets the position context's VBGS_ERR_NOT_PD flag. */
+vbgs_status vbgs_render(vbgs_ctx* model, vbgs_ctx* position, const float* Xq, int64_t Nq, double* regress,
+                        float* colour_out, double* lse_out, void* stream);
+
+/* PSNR of Sec. 5.1 between two images given as n FP32 values in [0, 1] (values outside are clamped):
+ * MSE over all n values of the 0..255-scaled differences, PSNR = 10 log10(255^2 / MSE) (+inf when
+ * equal). out: device 2 FP64, [MSE, PSNR]. Deterministic (fixed summation order). */
+vbgs_status vbgs_psnr(const float* a, const float* b, int64_t n, double* out, void* stream);
+
 /* Synchronise `stream` and return the sticky device flags (VBGS_ERR_NOT_PD,
  * VBGS_ERR_NONFINITE) or VBGS_OK. Clears nothing; vbgs_clear_flags does. */
 vbgs_status vbgs_sync_status(vbgs_ctx* ctx, void* stream);

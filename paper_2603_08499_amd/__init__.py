@@ -3,4 +3,4 @@
 The computation runs in the HIP library ``libvbgs.so`` (C ABI in include/vbgs.h);
 this package only marshals arguments to it.
 """
-from .vbgs import VBGS, VBGSError, make_params, query_sizes  # noqa: F401
+from .vbgs import VBGS, VBGSError, make_params, psnr, query_sizes  # noqa: F401

@@ -56,6 +56,8 @@ def load():
         "vbgs_clear_flags": (i32, [vp, vp]),
         "vbgs_counters": (i32, [vp, ctypes.POINTER(i64), vp]),
         "vbgs_reassign": (i32, [vp, vp, i64, vp, vp, i64, vp, vp, vp]),
+        "vbgs_render": (i32, [vp, vp, vp, i64, vp, vp, vp, vp]),
+        "vbgs_psnr": (i32, [vp, vp, i64, vp, vp]),
         "vbgs_proposal_set": (i32, [vp] + [vp] * 8 + [vp]),
         "vbgs_proposal_get": (i32, [vp] + [vp] * 6 + [vp]),
         "vbgs_estep_stats_pruned": (i32, [vp, vp, i64, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]),

@@ -947,6 +947,94 @@ __global__ __launch_bounds__(256) void k_over_lse(const EArgs a) {
   }
 }
 
+// ---- rendering: colour expected at each query position ------------------------------------------
+// sum_k r_k(x) (m_c,k + B_k (x - m_s,k)) with r_k(x) = exp2(s2_k(x) - LSE2(x)) the responsibilities of
+// the position marginal; reg[k] = [m_c (Dc), B (Dc x DT)]. One thread per point over its kept
+// candidates (exact MFMA mode) or over every component (FP64 mode); overflowed points are left to
+// k_render_over.
+constexpr int RMAX = MAXD;
+
+template <int DT>
+__device__ __forceinline__ void render_add(double* acc, int Dc, const double* __restrict__ g, const double* d,
+                                           double r) {
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c)
+    if (c < Dc) {
+      double v = g[c];
+#pragma unroll
+      for (int j = 0; j < DT; ++j) v = fma(g[Dc + c * DT + j], d[j], v);
+      acc[c] = fma(r, v, acc[c]);
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_render_points(const EArgs a, const double* __restrict__ reg, int Dc,
+                                                       int dense, float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= a.N) return;
+  if (!dense && a.cand_n[p * 4] < 0) return;
+  const int rs = Dc * (1 + DT);
+  const double L2 = a.lse2[p];
+  const float* x = a.X + p * DT;
+  double acc[RMAX];
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) acc[c] = 0.0;
+  double d[DT];
+  if (dense) {
+    for (int64_t k = 0; k < a.K; ++k) {
+      const double s2 = direct_score2_dt<DT>(a.direct + k * a.dts, x, d);
+      render_add<DT>(acc, Dc, reg + k * rs, d, exp2(s2 - L2));
+    }
+  } else {
+    for (int g = 0; g < 4; ++g) {
+      const int cnt = a.cand_n[p * 4 + g];
+      for (int j = 0; j < cnt; ++j) {
+        const int32_t k = a.cand_k[(p * 4 + g) * CS + j];
+        if (k < 0) continue;
+        const double s2 = direct_score2_dt<DT>(a.direct + (int64_t)k * a.dts, x, d);
+        render_add<DT>(acc, Dc, reg + (int64_t)k * rs, d, exp2(s2 - L2));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c)
+    if (c < Dc) out[p * Dc + c] = (float)acc[c];
+}
+
+// overflowed points: one workgroup per point over the rows its bound reaches (or every component)
+template <int DT>
+__global__ __launch_bounds__(256) void k_render_over(const EArgs a, const double* __restrict__ reg, int Dc,
+                                                     float* __restrict__ out) {
+  __shared__ double red[RMAX][256];
+  const int n_over = a.frame->n_over;
+  const int rs = Dc * (1 + DT);
+  for (int i = blockIdx.x; i < n_over; i += gridDim.x) {
+    const int64_t p = a.over_list[i];
+    const double L2 = a.lse2[p];
+    const float* x = a.X + p * DT;
+    double acc[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) acc[c] = 0.0;
+    over_rows<DT>(a, x, (float)L2 - a.T2 - 1.0f, [&](int64_t k) {
+      double d[DT];
+      const double s2 = direct_score2_dt<DT>(a.direct + k * a.dts, x, d);
+      render_add<DT>(acc, Dc, reg + k * rs, d, exp2(s2 - L2));
+    });
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if ((int)threadIdx.x < Dc) out[p * Dc + threadIdx.x] = (float)red[threadIdx.x][0];
+    __syncthreads();
+  }
+}
+
 // ---- overflowed points: statistics of every pair within the margin (fixed-point atomics) --------
 template <int DT>
 __global__ __launch_bounds__(256) void k_over_stats(const EArgs a) {
@@ -1406,6 +1494,26 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.nsp = d.nsp;
   a.eps = screen_eps(c.prec);
   return a;
+}
+
+hipError_t launch_render(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, const double* reg, int Dc,
+                         float* out, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  const EArgs a = make_eargs(d, c, X, N, nullptr);
+  const int dense = c.prec == VBGS_FP64 ? 1 : 0;
+  const dim3 gp((unsigned)((N + 255) / 256));
+  switch (d.D) {
+#define VB_RD(DD)                                                                              \
+  case DD:                                                                                     \
+    if (!dense) hipLaunchKernelGGL(k_render_over<DD>, dim3(256), dim3(256), 0, s, a, reg, Dc, out); \
+    hipLaunchKernelGGL(k_render_points<DD>, gp, dim3(256), 0, s, a, reg, Dc, dense, out);     \
+    break;
+    VB_RD(1) VB_RD(2) VB_RD(3) VB_RD(4) VB_RD(5) VB_RD(6)
+#undef VB_RD
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,

@@ -581,6 +581,103 @@ hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, d
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// rendering: spatial marginal and colour regression of every component
+// ---------------------------------------------------------------------------
+// Coordinates [0, s) are the position, [s, D) the colour. With Sigma ~ W^-1(Psi = W^-1, nu) the
+// marginal of the position block is Sigma_ss ~ W^-1(Psi_ss, nu - Dc) and mu_s | Sigma ~ N(m_s, Sigma_ss
+// / kappa): a Normal-Wishart (m_s, kappa, W_s = Psi_ss^-1, nu - Dc) over s coordinates. The colour
+// expected given the position and the component is m_c + B (x - m_s), B = Psi_cs Psi_ss^-1 (the mean
+// of Sigma_cs Sigma_ss^-1 under the inverse Wishart). In the two-factor model the position factor is
+// its own Normal-Wishart and B = 0. Writes the marginal as the record of an s-dimensional state
+// (prior and posterior) and reg[k] = [m_c (Dc), B (Dc x s, row-major)].
+__global__ void k_render_marginal(const double* __restrict__ post, int64_t K, int D, int split, int s,
+                                  double* __restrict__ sp_prior, double* __restrict__ sp_post,
+                                  double* __restrict__ reg, int* flags) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double* q = post + k * REC;
+  const int Dc = D - s;
+  double r[REC];
+  for (int i = 0; i < REC; ++i) r[i] = 0.0;
+  r[0] = q[0];
+  r[1] = rec_kappa(q, D, 0);
+  r[2] = split > 0 ? rec_nu(q, D, 0) : q[2] - Dc;
+  for (int i = 0; i < s; ++i) r[3 + i] = q[3 + i];
+  for (int i = 0; i < s; ++i)
+    for (int j = i; j < s; ++j) r[3 + s + tri_up(i, j, s)] = q[3 + D + tri_up(i, j, D)];
+  // Cholesky of Psi_ss (lower, row-major s x s)
+  double Lc[MAXD * MAXD];
+  bool pd = true;
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = q[3 + D + tri_up(j, i, D)];
+      for (int t = 0; t < j; ++t) v -= Lc[i * MAXD + t] * Lc[j * MAXD + t];
+      if (i == j) {
+        pd = pd && v > 0.0;
+        Lc[i * MAXD + i] = v > 0.0 ? sqrt(v) : 1.0;
+      } else {
+        Lc[i * MAXD + j] = v / Lc[j * MAXD + j];
+      }
+    }
+  if (!pd) atomicOr(flags, FLAG_NOT_PD);
+  double* o = reg + k * (int64_t)(Dc * (1 + s));
+  for (int c = 0; c < Dc; ++c) {
+    o[c] = q[3 + s + c];
+    // row c of B: Psi_ss b = Psi_s,c (forward then back substitution)
+    double y[MAXD];
+    for (int i = 0; i < s; ++i) {
+      double v = split > 0 ? 0.0 : q[3 + D + tri_up(i, s + c, D)];
+      for (int t = 0; t < i; ++t) v -= Lc[i * MAXD + t] * y[t];
+      y[i] = v / Lc[i * MAXD + i];
+    }
+    for (int i = s - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int t = i + 1; t < s; ++t) v -= Lc[t * MAXD + i] * y[t];
+      y[i] = v / Lc[i * MAXD + i];
+    }
+    for (int j = 0; j < s; ++j) o[Dc + c * s + j] = pd ? y[j] : 0.0;
+  }
+  for (int i = 0; i < REC; ++i) {
+    sp_prior[k * REC + i] = r[i];
+    sp_post[k * REC + i] = r[i];
+  }
+}
+
+hipError_t launch_render_marginal(const DevPtrs& model, const DevPtrs& sp, double* reg, hipStream_t s) {
+  hipLaunchKernelGGL(k_render_marginal, dim3((unsigned)((model.K + 127) / 128)), dim3(128), 0, s, model.post(),
+                     model.K, model.D, model.split, sp.D, sp.prior(), sp.post(), reg, &sp.frame()->flags);
+  return hipGetLastError();
+}
+
+// mean squared error of two images in [0, 1] on the 0..255 scale (values clamped to [0, 1]) and
+// the PSNR 10 log10(255^2 / MSE) of Sec. 5.1; one workgroup, fixed summation order
+__global__ __launch_bounds__(1024) void k_psnr(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
+                                               double* __restrict__ out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double d = 255.0 * ((double)fminf(fmaxf(a[i], 0.0f), 1.0f) - (double)fminf(fmaxf(b[i], 0.0f), 1.0f));
+    acc = fma(d, d, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mse = n > 0 ? red[0] / (double)n : 0.0;
+    out[0] = mse;
+    out[1] = mse > 0.0 ? 10.0 * log10(255.0 * 255.0 / mse) : INFINITY;
+  }
+}
+
+hipError_t launch_psnr(const float* a, const float* b, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_psnr, dim3(1), dim3(1024), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
 __global__ void k_clear_flags(FrameInfo* fr) {
   fr->flags = 0;
   fr->refined1 = 0;

@@ -570,6 +570,40 @@ vbgs_status vbgs_reassign(vbgs_ctx* c, const float* X, int64_t N, const double* 
   return VBGS_OK;
 }
 
+vbgs_status vbgs_render(vbgs_ctx* model, vbgs_ctx* sp, const float* Xq, int64_t Nq, double* regress,
+                        float* colour_out, double* lse_out, void* stream) {
+  if (!model || !sp) return VBGS_ERR_ARG;
+  const int D = model->p.D, s = sp->p.D;
+  if (s < 1 || s >= D || s > 6) return fail(sp, VBGS_ERR_SHAPE, "the position context needs 1 <= D_s < D, D_s <= 6");
+  if (model->p.modal_split > 0 && model->p.modal_split != s)
+    return fail(sp, VBGS_ERR_SHAPE, "the position context's D must equal the model's modal_split");
+  if (sp->p.K != model->p.K || sp->p.modal_split != 0 || sp->p.proposal != 0)
+    return fail(sp, VBGS_ERR_SHAPE, "the position context needs the model's K, modal_split = 0, no proposal");
+  if (sp->p.score_prec != VBGS_FP64 && sp->p.exact != 1)
+    return fail(sp, VBGS_ERR_UNSUPPORTED, "rendering needs the FP64 path or the exact MFMA mode");
+  if (Nq < 0 || Nq > sp->p.n_max) return fail(sp, VBGS_ERR_SHAPE, "Nq outside 0..n_max of the position context");
+  if (!regress || (Nq > 0 && (!Xq || !colour_out))) return fail(sp, VBGS_ERR_ARG, "null buffer");
+  hipError_t e = launch_render_marginal(model->dev(), sp->dev(), regress, S(stream));
+  if (e != hipSuccess) return hipfail(sp, e, "render marginal");
+  sp->post_version++;
+  sp->have_stats = false;
+  if (Nq == 0) return VBGS_OK;
+  vbgs_status st = run_pass1(sp, Xq, Nq, lse_out, stream);
+  if (st != VBGS_OK) return st;
+  EstepCfg cfg{sp->p.score_prec, sp->p.exact, sp->T2, sp->nsplit};
+  cfg.cull = use_cull(sp) ? 1 : 0;
+  e = launch_render(sp->dev(), cfg, Xq, Nq, regress, D - s, colour_out, S(stream));
+  if (e != hipSuccess) return hipfail(sp, e, "render");
+  sp->last_N = Nq;
+  sp->lse_version = sp->post_version;
+  return VBGS_OK;
+}
+
+vbgs_status vbgs_psnr(const float* a, const float* b, int64_t n, double* out, void* stream) {
+  if (n < 0 || !out || (n > 0 && (!a || !b))) return VBGS_ERR_ARG;
+  return launch_psnr(a, b, n, out, S(stream)) == hipSuccess ? VBGS_OK : VBGS_ERR_HIP;
+}
+
 vbgs_status vbgs_sync_status(vbgs_ctx* c, void* stream) {
   if (!c) return VBGS_ERR_ARG;
   int32_t flags = 0;

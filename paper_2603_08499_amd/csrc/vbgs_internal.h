@@ -57,7 +57,7 @@ struct FrameInfo {
 struct TileInfo {
   float G;          // max over the tile of the score constant g2 (log2 units)
   float Lam;        // min over the tile of lambda_k: s2 <= g2 - lambda_k |x_S - m_k,S|^2
-  float lo[3], hi[3];  // box of the means in the first min(D, 3) raw coordinates
+  float lo[3], hi[3];  // box of the means in the culling coordinates (the others read 0)
   uint32_t code;    // Morton code of the tile's first row
   uint32_t pad;
 };
@@ -282,6 +282,10 @@ hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStr
 hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, double* kappa, double* m,
                           double* Winv, double* nu, hipStream_t s);
 hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s);
+// rendering: the position marginal of the model's posterior written into the s-dimensional state
+// of sp, and reg[k] = [m_c, B]; the colour at query positions from sp's first pass
+hipError_t launch_render_marginal(const DevPtrs& model, const DevPtrs& sp, double* reg, hipStream_t s);
+hipError_t launch_psnr(const float* a, const float* b, int64_t n, double* out, hipStream_t s);
 hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
 hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s);
 hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s);
@@ -348,5 +352,7 @@ hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, h
 hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull = 0);
 hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s);
 hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s);
+hipError_t launch_render(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, const double* reg, int Dc,
+                         float* out, hipStream_t s);
 
 }  // namespace vbgs

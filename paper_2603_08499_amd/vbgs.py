@@ -61,6 +61,20 @@ def query_sizes(p):
     return sb.value, wb.value
 
 
+def psnr(a, b):
+    """PSNR of Sec. 5.1 between two float32 device images in [0, 1] (any shape, same numel):
+    returns a device tensor [MSE, PSNR] (FP64)."""
+    L = _lib.load()
+    if a.dtype != torch.float32 or b.dtype != torch.float32 or a.numel() != b.numel():
+        raise ValueError("a and b must be float32 tensors of the same size")
+    a, b = a.contiguous(), b.contiguous()
+    out = torch.empty(2, dtype=torch.float64, device=a.device)
+    st = L.vbgs_psnr(_ptr(a), _ptr(b), a.numel(), _ptr(out), _stream())
+    if st:
+        raise VBGSError(st)
+    return out
+
+
 class VBGS:
     """One mixture of K Normal-Wishart components over D-dimensional points.
 
@@ -181,6 +195,31 @@ class VBGS:
         self._check(self.lib.vbgs_reassign(self.ctx, _ptr(X), N, _ptr(lse), _ptr(gumbel), int(n),
                                            _ptr(pts) if n > 0 else None, _ptr(comps) if n > 0 else None, _stream()))
         return pts, comps
+
+    # ---- rendering ------------------------------------------------------------------------
+    def renderer(self, n_max, score_prec="bf16x3", exact=True, **kw):
+        """The position context vbgs_render needs: D_s = modal_split (or 2 for D = 5 images, else 3),
+        the model's K, n_max query positions. Its parameters are overwritten by every render."""
+        s = self.params.modal_split or (2 if self.D == 5 else 3)
+        return VBGS(s, self.K, n_max, np.zeros((self.K, s)), np.eye(s), device=self.device,
+                    score_prec=score_prec, exact=exact, **kw)
+
+    def render(self, position, Xq, lse=False, regress=None):
+        """Colour expected at the query positions Xq (Nq x D_s FP32): the responsibilities of the
+        position marginal times each component's colour given the position. Returns (colour Nq x Dc
+        FP32, lse Nq FP64 or None)."""
+        Xq = position._points(Xq)
+        Nq, s = Xq.shape[0], position.D
+        Dc = self.D - s
+        if regress is None:
+            regress = torch.empty((self.K, Dc * (1 + s)), dtype=torch.float64, device=self.device)
+        colour = torch.empty((Nq, Dc), dtype=torch.float32, device=self.device)
+        lse_out = torch.empty(Nq, dtype=torch.float64, device=self.device) if lse else None
+        st = self.lib.vbgs_render(self.ctx, position.ctx, _ptr(Xq), Nq, _ptr(regress), _ptr(colour),
+                                  _ptr(lse_out), _stream())
+        if st:
+            raise VBGSError(st, self.lib.vbgs_last_error(position.ctx).decode())
+        return colour, lse_out
 
     # ---- learned candidate proposal -----------------------------------------------------
     def _f32(self, a):

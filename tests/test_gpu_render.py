@@ -1,0 +1,167 @@
+"""GPU parity of the rendering (colour expected at query positions) and of the PSNR of Sec. 5.1.
+
+Both sides render from their own posterior (set from the same seeded values, or fitted each on its
+own); the oracle never reads a GPU result. Tolerances: colours are returned in FP32, so they are
+compared to 1e-6 absolute (the FP64 sums agree to ~1e-13 before that rounding); the position
+marginal's LSE to 2e-6 nats.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import factorised_ref as FR
+from oracle import render_ref as RR
+from oracle import vbgs_ref as R
+from synth import scenes
+
+gpu = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_08499_amd  # noqa: F401  (fails loudly if libvbgs.so is missing)
+    return torch.device("cuda:0")
+
+
+def _model(dev, pr, n_max, split=0, prec="bf16x3"):
+    import paper_2603_08499_amd as P
+    return P.VBGS(pr.D, pr.K, n_max, pr.m0, pr.W0, device=dev, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
+                  score_prec=prec, exact=True, modal_split=split)
+
+
+def _perturbed_joint(p: R.NW, seed):
+    g = np.random.default_rng(seed)
+    K, D = p.m.shape
+    A = g.normal(0, 0.3, (K, D, D))
+    Winv = p.Winv * g.uniform(0.5, 2.0, (K, 1, 1)) + np.einsum("kij,klj->kil", A, A) * p.Winv[:, :1, :1]
+    return R.NW(alpha=p.alpha * g.uniform(0.5, 5.0, K), kappa=p.kappa * g.uniform(0.5, 4.0, K),
+                m=p.m + g.normal(0, 0.01, p.m.shape), Winv=Winv, nu=p.nu + g.uniform(0.0, 6.0, K))
+
+
+def _perturbed_split(p: FR.NW2, seed):
+    g = np.random.default_rng(seed)
+    K, D = p.m.shape
+    Winv = np.zeros_like(p.Winv)
+    for b in (0, 1):
+        i = p.idx(b)
+        A = g.normal(0, 0.3, (K, len(i), len(i)))
+        base = p.Winv[:, i][:, :, i]
+        Winv[:, i[:, None], i[None, :]] = (base * g.uniform(0.5, 2.0, (K, 1, 1))
+                                           + np.einsum("kij,klj->kil", A, A) * base[:, :1, :1])
+    return FR.NW2(alpha=p.alpha * g.uniform(0.5, 5.0, K), kappa=p.kappa * g.uniform(0.5, 4.0, (K, 2)),
+                  m=p.m + g.normal(0, 0.01, p.m.shape), Winv=Winv, nu=p.nu + g.uniform(0.0, 6.0, (K, 2)),
+                  split=p.split)
+
+
+@gpu
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("D,s,split,K", [(5, 2, 0, 120), (6, 3, 0, 300), (6, 3, 3, 250), (5, 2, 2, 90)])
+def test_render_parity(dev, prec, D, s, split, K):
+    print("render case", prec, D, s, split, K, flush=True)
+    N = 2500
+    X, pr = scenes.random_problem(N, K, D, seed=40 + D + K)
+    g = np.random.default_rng(1)
+    Xq = np.concatenate([X[:, :s], g.uniform(0, 1, (500, s)).astype(np.float32)])   # data and free positions
+    m = _model(dev, pr, N, split)
+    if split:
+        q = _perturbed_split(FR.NW2.from_prior(pr, split), 3)
+        qs, mc, B = RR.marginal_factorised(q)
+    else:
+        q = _perturbed_joint(R.NW.from_prior(pr), 3)
+        qs, mc, B = RR.marginal(q, s)
+    m.set_params("posterior", q.alpha, q.kappa, q.m, q.Winv, q.nu)
+    pos = m.renderer(len(Xq), score_prec=prec)
+    col, lse = m.render(pos, torch.from_numpy(np.ascontiguousarray(Xq)).to(dev), lse=True)
+    torch.cuda.synchronize()
+    assert pos.sync_status() == 0
+    ref, lref = RR.render_points(Xq, qs, mc, B)
+    dc = np.abs(col.cpu().numpy() - ref).max()
+    dl = np.abs(lse.cpu().numpy() - lref).max()
+    print("  max|d colour| %.2e max|d LSE| %.2e" % (dc, dl), pos.counters())
+    assert dc < 1e-6 and dl < 2e-6
+
+
+@gpu
+def test_render_c1_after_fitting(dev):
+    """c1 fitted for ten steps on each side; the image rendered at every pixel and its PSNR against
+    the observed colours."""
+    import paper_2603_08499_amd as P
+    X = scenes.c1_frame()
+    pr = scenes.c1_prior(X)
+    q = R.cavi(X, pr, 10)[-1].q_next
+    qs, mc, B = RR.marginal(q, 2)
+    ref, _ = RR.render(X[:, :2], qs, mc, B)
+    mse_r, psnr_r = RR.psnr(ref, X[:, 2:])
+    m = _model(dev, pr, X.shape[0])
+    Xg = torch.from_numpy(X).to(dev)
+    for _ in range(10):
+        m.estep_stats(Xg, lse=False)
+        m.update(commit=False)
+    pos = m.renderer(X.shape[0])
+    col, _ = m.render(pos, Xg[:, :2].contiguous())
+    out = P.psnr(col, Xg[:, 2:].contiguous()).cpu().numpy()
+    dc = np.abs(col.cpu().numpy() - ref).max()
+    print("c1: max|d colour| %.2e PSNR gpu %.4f oracle %.4f dB" % (dc, out[1], psnr_r))
+    assert dc < 1e-5
+    assert abs(out[1] - psnr_r) < 1e-3 and psnr_r > 20.0
+
+
+@gpu
+def test_render_c5_full_image(dev):
+    """The 800x800 image at the prior (the posterior both sides know): every pixel rendered on the
+    GPU, 2048 sampled pixels by the oracle; then ten fitted steps and the PSNR of the render."""
+    import paper_2603_08499_amd as P
+    X = scenes.c5_frame()
+    pr = scenes.c5_prior(X)
+    N = X.shape[0]
+    m = _model(dev, pr, N, prec="fp32")
+    Xg = torch.from_numpy(X).to(dev)
+    pos = m.renderer(N, score_prec="fp32")
+    col0, lse0 = m.render(pos, Xg[:, :2].contiguous(), lse=True)
+    idx = scenes.rng(5, 0, 4).choice(N, 2048, replace=False)
+    qs, mc, B = RR.marginal(R.NW.from_prior(pr), 2)
+    ref, lref = RR.render_points(X[idx, :2], qs, mc, B, chunk=64)
+    dc = np.abs(col0.cpu().numpy()[idx] - ref).max()
+    dl = np.abs(lse0.cpu().numpy()[idx] - lref).max()
+    p0 = P.psnr(col0, Xg[:, 2:].contiguous()).cpu().numpy()
+    for _ in range(10):
+        m.estep_stats(Xg, lse=False)
+        m.update(commit=False)
+    col, _ = m.render(pos, Xg[:, :2].contiguous())
+    p1 = P.psnr(col, Xg[:, 2:].contiguous()).cpu().numpy()
+    torch.cuda.synchronize()
+    print("c5: prior sampled max|d colour| %.2e max|d LSE| %.2e; PSNR prior %.3f dB, after 10 steps %.3f dB"
+          % (dc, dl, p0[1], p1[1]), pos.counters())
+    assert dc < 1e-6 and dl < 2e-6
+    assert p1[1] > p0[1]
+
+
+@gpu
+def test_psnr_kernel(dev):
+    import paper_2603_08499_amd as P
+    g = np.random.default_rng(8)
+    a = g.uniform(-0.1, 1.1, 300001).astype(np.float32)
+    b = g.uniform(0, 1, 300001).astype(np.float32)
+    out = P.psnr(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)).cpu().numpy()
+    mse, p = RR.psnr(a, b)
+    assert abs(out[0] - mse) <= 1e-12 * mse and abs(out[1] - p) < 1e-10
+    same = P.psnr(torch.from_numpy(b).to(dev), torch.from_numpy(b).to(dev)).cpu().numpy()
+    assert same[0] == 0.0 and np.isinf(same[1])
+
+
+@gpu
+def test_render_argument_checks(dev):
+    import paper_2603_08499_amd as P
+    X, pr = scenes.random_problem(200, 20, 6, seed=2)
+    m = _model(dev, pr, 200, split=3)
+    bad = P.VBGS(2, 20, 200, np.zeros((20, 2)), np.eye(2), device=dev)        # D_s must equal modal_split
+    with pytest.raises(P.VBGSError):
+        m.render(bad, torch.zeros((10, 2), dtype=torch.float32, device=dev))
+    pos = m.renderer(100)
+    with pytest.raises(P.VBGSError):                                          # Nq above n_max
+        m.render(pos, torch.zeros((101, 3), dtype=torch.float32, device=dev))
+    plain = P.VBGS(3, 20, 100, np.zeros((20, 3)), np.eye(3), device=dev, exact=False)
+    with pytest.raises(P.VBGSError):                                          # plain GEMM tier
+        m.render(plain, torch.zeros((10, 3), dtype=torch.float32, device=dev))
