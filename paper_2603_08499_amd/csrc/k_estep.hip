@@ -524,8 +524,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ int32_t seeds[1][24];
   __shared__ uint8_t bms[1][64];  // per tile of the current chunk: the 16-point blocks it reaches
   __shared__ int32_t tks[1][64];  // component indices of the tile being screened
+  const uint64_t t_start = wall_clock64();
   const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
-  const int64_t j0 = xcd_block(blockIdx.x, gridDim.x) * (P1_PB * 16);  // sorted positions
+  const int64_t jb = a.border[xcd_block(blockIdx.x, gridDim.x)];
+  const int64_t j0 = jb * (P1_PB * 16);  // sorted positions
   const int ns = a.nsp;
   float* mv = mvs[w];
   const int32_t* pid = pids[w];
@@ -676,6 +678,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
   }
   count_refined(&a.frame->refined1, S.nref);
+  if (lane == 0) {
+    a.bcost[jb] = (float)(wall_clock64() - t_start);
+    a.bcode[jb] = a.pcode[j0];
+  }
   if (lane == 0 && S.nblk) {
     atomicAdd(&a.frame->blocks, (unsigned long long)S.nblk);
     atomicAdd(&a.frame->blocks_cum, (unsigned long long)S.nblk);
@@ -813,6 +819,69 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n, const int32_t* gate
   if (gate && gate[0] == 0) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0ull;
+}
+
+// ---- dispatch order of the culled sweep ------------------------------------------------------------
+// Workgroups go to the eight XCDs in turn and each XCD takes one contiguous range of the point
+// blocks (xcd_block). Within its range, an XCD starts the blocks whose last sweep took longest
+// first (longest processing time first), so that the long blocks do not form the tail. The costs
+// are those the previous launch on the same context measured; they predict this launch when the
+// blocks hold the same points (coordinate-ascent steps on one frame), checked through the Morton
+// code of each block's first point: a range where fewer than 7/8 of the blocks match, one longer
+// than BO_MAX, or a reset keeps the Morton order (which keeps neighbouring blocks, and the
+// component tiles they share, together in time). Any order gives the same results.
+constexpr int BO_MAX = 4096;
+
+__global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost, const uint32_t* __restrict__ bcode,
+                                                      const uint32_t* __restrict__ pcode, int64_t nb, int64_t cap,
+                                                      int32_t* __restrict__ border, int reset) {
+  __shared__ unsigned long long key[BO_MAX];
+  const int tid = threadIdx.x, x = blockIdx.x;
+  const int64_t per = nb / 8, rem = nb % 8;
+  const int64_t start = x * per + (x < rem ? x : rem), len = per + (x < rem ? 1 : 0);
+  if (reset) {
+    for (int64_t i = (int64_t)x * 1024 + tid; i < cap; i += 8 * 1024) bcost[i] = 0.0f;
+  }
+  __shared__ int same;
+  if (tid == 0) same = 0;
+  __syncthreads();
+  if (!reset && len <= BO_MAX) {
+    int m = 0;
+    for (int64_t i = tid; i < len; i += 1024) m += bcode[start + i] == pcode[(start + i) * 64] ? 1 : 0;
+    if (m) atomicAdd(&same, m);
+  }
+  __syncthreads();
+  if (reset || len > BO_MAX || 8 * (int64_t)same < 7 * len) {
+    for (int64_t i = tid; i < len; i += 1024) border[start + i] = (int32_t)(start + i);
+    return;
+  }
+  int n2 = 1;
+  while (n2 < len) n2 <<= 1;
+  for (int i = tid; i < n2; i += 1024) {
+    if (i < len) {
+      float v = bcost[start + i];
+      v = v > 0.0f ? v : 0.0f;  // also maps NaN to 0
+      key[i] = ((unsigned long long)(0xFFFFFFFFu - __float_as_uint(v)) << 32) | (unsigned)i;
+    } else {
+      key[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < n2; i += 1024) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const unsigned long long u = key[i], v = key[ixj];
+          if ((u > v) == ((i & k) == 0)) {
+            key[i] = v;
+            key[ixj] = u;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = tid; i < len; i += 1024) border[start + i] = (int32_t)(start + (int64_t)(key[i] & 0xFFFFFFFFull));
 }
 
 // ---- exact LSE of the recorded candidates, one thread per point ---------------------------------
@@ -1364,6 +1433,8 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
     if (cull) {
       const dim3 gw((unsigned)((N + 63) / 64));  // one 64-point wave per workgroup
+      hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, (int64_t)gw.x,
+                         a.nb_cap, a.border, a.order_reset);
       if (prec == VBGS_FP32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), gw, dim3(64), 0, s, a);
       else if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), gw, dim3(64), 0, s, a);
       else hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), gw, dim3(64), 0, s, a);
@@ -1492,6 +1563,11 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.T2 = c.T2;
   a.cull = c.cull;
   a.nsp = d.nsp;
+  a.bcost = d.at<float>(L.bcost);
+  a.bcode = d.at<uint32_t>(L.bcode);
+  a.border = d.at<int32_t>(L.border);
+  a.nb_cap = (L.bcode - L.bcost) / 4;
+  a.order_reset = c.order_reset;
   a.eps = screen_eps(c.prec);
   return a;
 }

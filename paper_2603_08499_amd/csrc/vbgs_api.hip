@@ -36,6 +36,7 @@ struct vbgs_ctx {
   uint64_t post_version;
   uint64_t lse_version;
   bool have_stats;
+  bool order_reset;  // the sweep's block costs are not measured yet
   int nsplit;
   float T2;
   std::string err;
@@ -269,6 +270,9 @@ Layout make_layout(const vbgs_params& p) {
   L.ncg = take(sparse ? (size_t)L.Kpad / 4 * sizeof(float) : 0);
   L.lhist = take(sparse ? (size_t)LAM_BINS * 4 : 0);
   L.scan_part = take(sparse ? (size_t)((L.Kpad + 1023) / 1024 + 1) * 4 : 0);
+  L.bcost = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
+  L.bcode = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
+  L.border = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   // learned proposal
   const bool pr = p.proposal == 1;
   const int C = p.C > 0 ? p.C : 32;
@@ -353,6 +357,7 @@ static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   c->post_version = 0;
   c->lse_version = ~(uint64_t)0;
   c->have_stats = false;
+  c->order_reset = true;
   c->timing = false;
   c->timers_made = false;
   c->prop_ready = false;
@@ -457,6 +462,7 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
   cfg.cull = use_cull(c) ? 1 : 0;
+  cfg.order_reset = c->order_reset ? 1 : 0;
   hipError_t e;
   {
     Phase ph(c, 0, S(stream));
@@ -475,6 +481,7 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   if (e == hipSuccess) {
     Phase ph(c, 2, S(stream));
     e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 1);
+    if (cfg.cull && N > 0) c->order_reset = false;
   }
   if (e == hipSuccess) {
     Phase ph(c, 9, S(stream));
@@ -757,6 +764,8 @@ vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* c, const float* X, int64_t N, cons
   }
   const bool cull = use_cull(c);
   cfg.cull = cull ? 1 : 0;
+  cfg.order_reset = c->order_reset ? 1 : 0;
+  if (cull && N > 0) c->order_reset = false;
   if (e == hipSuccess) {
     Phase ph(c, 1, s);
     e = prepare_components(c, s);

@@ -117,6 +117,8 @@ struct Layout {
   int nsplit_max;
   // spatial ordering (culled exact sweep)
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
+  size_t bcost, bcode, border;  // per 64-point block: measured sweep time, its first point's Morton
+                                // code at that time, dispatch order
   // learned proposal (workspace)
   size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
       p_tdh2, p_tdp1, p_th2b, p_th2T, p_tloss, p_grads;
@@ -299,6 +301,7 @@ struct EstepCfg {
   int nsplit;    // pass-2 point splits
   const int32_t* gate = nullptr;  // device flag gating the exact dense kernels (proposal fallback)
   int cull = 0;                   // culled sweep over spatially sorted points and components
+  int order_reset = 0;            // forget the measured block costs (first sweep of a context)
 };
 
 struct EArgs {
@@ -335,6 +338,11 @@ struct EArgs {
   const f32x4* ncg;           // per tile and lane group g: for each 16-row block cb, the largest
                               // coefficient norm of rows 16 cb + 4 g .. 16 cb + 4 g + 3
   int32_t* scan_part;         // block sums of the pair-count scan
+  float* bcost;               // culled sweep: per 64-point block, the duration of its last sweep
+  uint32_t* bcode;            // and the Morton code of its first point then
+  int32_t* border;            // culled sweep: dispatch position -> block (costliest first per XCD)
+  int64_t nb_cap;             // capacity of bcost / border
+  int order_reset;
   int64_t N, K, Kpad;
   int D, dts, nsplit;
   float T2, eps;
