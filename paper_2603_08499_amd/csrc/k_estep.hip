@@ -424,6 +424,69 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
   return x * per + (x < rem ? x : rem) + q;
 }
 
+// One tile's operands staged in LDS by asynchronous global -> LDS copies (lane L's 16 bytes at
+// 16 L of each piece), so that the copy of the next tile overlaps the work on the current one.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int P>
+struct TileStage {
+  u32x4 a[CT / 16][2][64];  // coefficient rows: [16-row block][hi / lo (FP32: first / second half)][lane]
+  u32x4 rb[2][64];          // RowBound of row `lane`, two 16-byte halves
+  int32_t krow[64];         // component of row `lane`
+};
+
+__device__ __forceinline__ void dma16(const void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void*)dst, 16, 0, 0);
+}
+
+// start copying tile t into st (after the reads of its previous contents have completed)
+template <int P>
+__device__ __forceinline__ void stage_tile(const EArgs& a, int64_t t, int lane, TileStage<P>& st) {
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t r0 = t * CT;
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+  for (int cb = 0; cb < CT / 16; ++cb) {
+    const int64_t r = r0 + cb * 16 + c;
+    if constexpr (P == VBGS_FP32) {
+      dma16(a.c32 + r * FP + 8 * g, &st.a[cb][0][0]);
+      dma16(a.c32 + r * FP + 8 * g + 4, &st.a[cb][1][0]);
+    } else {
+      dma16(a.ch + r * FP + 8 * g, &st.a[cb][0][0]);
+      if constexpr (P == VBGS_BF16X3) dma16(a.cl + r * FP + 8 * g, &st.a[cb][1][0]);
+    }
+  }
+  const char* rbp = reinterpret_cast<const char*>(a.rowb + r0 + lane);
+  dma16(rbp, &st.rb[0][0]);
+  dma16(rbp + 16, &st.rb[1][0]);
+  __builtin_amdgcn_global_load_lds(a.corder + r0 + lane, (lds_void*)&st.krow[0], 4, 0, 0);
+}
+
+// wait for the copies of the staged tile and read this lane's pieces
+template <int P>
+__device__ __forceinline__ void read_stage(const TileStage<P>& st, int lane, Opnd<P>* A, RowBound& rb,
+                                           int32_t& krow) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+  for (int cb = 0; cb < CT / 16; ++cb) {
+    if constexpr (P == VBGS_FP32) {
+      A[cb].a = __builtin_bit_cast(f32x4, st.a[cb][0][lane]);
+      A[cb].b = __builtin_bit_cast(f32x4, st.a[cb][1][lane]);
+    } else {
+      A[cb].h = __builtin_bit_cast(bf16x8, st.a[cb][0][lane]);
+      if constexpr (P == VBGS_BF16X3) A[cb].l = __builtin_bit_cast(bf16x8, st.a[cb][1][lane]);
+    }
+  }
+  const u32x4 h0 = st.rb[0][lane], h1 = st.rb[1][lane];  // RowBound {G, Lam, m[3], nc, pad[2]}
+  rb.G = __uint_as_float(h0.x);
+  rb.Lam = __uint_as_float(h0.y);
+  rb.m[0] = __uint_as_float(h0.z);
+  rb.m[1] = __uint_as_float(h0.w);
+  rb.m[2] = __uint_as_float(h1.x);
+  rb.nc = __uint_as_float(h1.y);
+  krow = st.krow[lane];
+}
+
 template <int P>
 struct SweepWave {
   Opnd<P> B[P1_PB];
@@ -435,23 +498,25 @@ struct SweepWave {
   float mw;  // the wave's smallest M when last taken (seeds: -inf)
 };
 
-// screen tile t for the wave's points (see above); rec: record candidates
-template <int P>
+// screen tile t for the wave's points (see above); rec: record candidates. st holds tile t when
+// staged is set (else it is copied here); t_next >= 0 starts the copy of the next tile.
 // tk: the wave's LDS slot for the tile's component indices (lane = row)
-__device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int64_t t, bool rec, int lane,
-                                            unsigned bm, float* __restrict__ mv, const int32_t* __restrict__ pid,
-                                            int32_t* __restrict__ tk) {
+template <int P>
+__device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int64_t t, int64_t t_next, bool staged,
+                                            bool rec, int lane, unsigned bm, float* __restrict__ mv,
+                                            const int32_t* __restrict__ pid, int32_t* __restrict__ tk,
+                                            TileStage<P>& st) {
   const int g = lane >> 4, c = lane & 15;
   const int64_t r0 = t * CT;
-  const RowBound rb = a.rowb[r0 + lane];
-  const int32_t krow = a.corder[r0 + lane];  // rows past K hold no component (never recorded)
-  const f32x4 ncq = a.ncg[t * 4 + g];        // largest norm of this lane's four rows, per block
+  if (!staged) stage_tile<P>(a, t, lane, st);
   Opnd<P> A[CT / 16];
-#pragma unroll
-  for (int cb = 0; cb < CT / 16; ++cb) {
-    const int64_t r = r0 + cb * 16 + c;
-    A[cb] = load_op<P>(a.c32 + r * FP, a.ch + r * FP, a.cl + r * FP, g);
-  }
+  RowBound rb;
+  int32_t krow;  // rows past K hold no component (never recorded)
+  read_stage<P>(st, lane, A, rb, krow);
+  if (t_next >= 0) stage_tile<P>(a, t_next, lane, st);
+  // largest coefficient norm of this lane's four rows 16 cb + 4 g + i (i < 4), per block cb
+  float nc4 = fmaxf(rb.nc, __shfl_xor(rb.nc, 1));
+  nc4 = fmaxf(nc4, __shfl_xor(nc4, 2));
   const float mw = S.mw;  // stale lower bound on the wave's smallest M (M only grows)
   const float margin = a.T2 + 1.0f;
   float d2 = 0.0f;
@@ -463,16 +528,13 @@ __device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int
     d2 = fmaf(gap, gap, d2);
   }
   const unsigned long long rmask = __ballot(rb.G - rb.Lam * d2 >= mw - margin);
-  // the four blocks' rows were requested together with the bounds: one wait for all of them
-#pragma unroll
-  for (int cb = 0; cb < CT / 16; ++cb) operands_ready<P>(A[cb]);
   tk[lane] = krow;
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int cb = 0; cb < CT / 16; ++cb) {
     if (((rmask >> (16 * cb)) & 0xFFFFull) == 0ull) continue;  // wave-uniform
     ++S.nblk;
-    const float ncm = ncq[cb];  // rows 16 cb + 4 g + i, i < 4
+    const float ncm = __shfl(nc4, 16 * cb + 4 * g);  // rows 16 cb + 4 g + i, i < 4
     // the four point blocks' products first (independent MFMA chains), then their screens
     f32x4 svb[P1_PB];
 #pragma unroll
@@ -524,6 +586,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ int32_t seeds[1][24];
   __shared__ uint8_t bms[1][64];  // per tile of the current chunk: the 16-point blocks it reaches
   __shared__ int32_t tks[1][64];  // component indices of the tile being screened
+  __shared__ TileStage<P> stg;    // operands of the tile being screened or the next one
   const uint64_t t_start = wall_clock64();
   const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
   const int64_t jb = a.border[xcd_block(blockIdx.x, gridDim.x)];
@@ -607,7 +670,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __builtin_amdgcn_wave_barrier();
     for (int i = 0; i < 2 * nseed; ++i) {
       const int64_t t = __builtin_amdgcn_readfirstlane(seeds[w][i % nseed]);
-      screen_tile<P>(a, S, t, i >= nseed, lane, 0xFu, mv, pid, tks[w]);
+      const int64_t tn = i + 1 < 2 * nseed ? (int64_t)__builtin_amdgcn_readfirstlane(seeds[w][(i + 1) % nseed]) : -1;
+      screen_tile<P>(a, S, t, tn, i > 0, i >= nseed, lane, 0xFu, mv, pid, tks[w], stg);
       share_m<P>(S, lane, mv);
     }
     const float margin = a.T2 + 1.0f;
@@ -655,10 +719,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         }
       }
       __builtin_amdgcn_wave_barrier();
+      bool staged = false;
       while (m) {
         const int i = __ffsll((long long)m) - 1;
         m &= m - 1ull;
-        screen_tile<P>(a, S, base + i, true, lane, __builtin_amdgcn_readfirstlane(bms[w][i]), mv, pid, tks[w]);
+        const int64_t tn = m ? base + (__ffsll((long long)m) - 1) : -1;
+        screen_tile<P>(a, S, base + i, tn, staged, true, lane, __builtin_amdgcn_readfirstlane(bms[w][i]), mv, pid,
+                       tks[w], stg);
+        staged = tn >= 0;
       }
     }
     share_m<P>(S, lane, mv);
