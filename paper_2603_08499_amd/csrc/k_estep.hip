@@ -969,12 +969,24 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
       double m = -INFINITY, l = 0.0;
       for (int g = 0; g < 4; ++g) {
         const int cnt = a.cand_n[p * 4 + g];
-        for (int j = 0; j < cnt; ++j) {
-          const int64_t e = (p * 4 + g) * CS + j;
-          double d[DT];
-          const double s2 = direct_score2_dt<DT>(a.direct + (int64_t)a.cand_k[e] * a.dts, x, d);
-          online_add(m, l, s2);
-          a.cand_s[e] = (float)s2;
+        const int64_t e0 = (p * 4 + g) * CS;
+        // four candidates at a time, so that their rows are fetched together
+        for (int j = 0; j < cnt; j += 4) {
+          int32_t kk[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) kk[u] = j + u < cnt ? a.cand_k[e0 + j + u] : -1;
+          double sc[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            double d[DT];
+            sc[u] = kk[u] >= 0 ? direct_score2_dt<DT>(a.direct + (int64_t)kk[u] * a.dts, x, d) : -INFINITY;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (kk[u] >= 0) {
+              online_add(m, l, sc[u]);
+              a.cand_s[e0 + j + u] = (float)sc[u];
+            }
         }
       }
       L2 = m + log2(l);
