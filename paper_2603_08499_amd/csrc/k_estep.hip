@@ -1275,6 +1275,16 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ 
   }
 }
 
+// exclusive scan of n counts: off[i] = sum_{j < i} cnt[j], off[n] = total; part: ceil(n / SCAN_B) + 1
+hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t* part, hipStream_t s) {
+  const int64_t nsb = (n + SCAN_B - 1) / SCAN_B;
+  if (nsb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part);
+  hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(256), 0, s, part, nsb, off, n);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part, off);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= a.N || a.cand_n[p * 4] < 0) return;

@@ -236,15 +236,100 @@ __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ c
   }
 }
 
+// ---- stable LSD radix sort of 64-bit keys on their upper 32 bits (four 8-bit digits) -------------
+// The lower 32 bits (the element index) ride along; the input is in index order, so equal codes
+// keep index order, as the full 64-bit order would. Per pass: digit histograms per workgroup of
+// RX_B keys (digit-major), their exclusive scan, and a stable scatter that ranks keys of equal digit
+// within each wave by ballots on the digit's bits.
+__global__ __launch_bounds__(256) void k_radix_hist(const unsigned long long* __restrict__ keys, int64_t n, int shift,
+                                                    int32_t* __restrict__ hist, int64_t nb) {
+  __shared__ int32_t h[256];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RX_B;
+#pragma unroll
+  for (int i = 0; i < RX_B / 256; ++i) {
+    const int64_t j = base + i * 256 + t;
+    if (j < n) atomicAdd(&h[(int)((keys[j] >> shift) & 255ull)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)t * nb + blockIdx.x] = h[t];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const unsigned long long* __restrict__ in,
+                                                       unsigned long long* __restrict__ out, int64_t n, int shift,
+                                                       const int32_t* __restrict__ off, int64_t nb) {
+  __shared__ int32_t run[256];    // next output position per digit
+  __shared__ int32_t wc[4][256];  // per wave: keys of each digit in the current chunk, then their base
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  run[t] = off[(int64_t)t * nb + blockIdx.x];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int64_t base = (int64_t)blockIdx.x * RX_B;
+  for (int ch = 0; ch < RX_B / 256; ++ch) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wc[q][t] = 0;
+    __syncthreads();
+    const int64_t j = base + ch * 256 + t;
+    const bool valid = j < n;
+    const unsigned long long key = valid ? in[j] : 0ull;
+    const int dg = (int)((key >> shift) & 255ull);
+    unsigned long long eq = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long bal = __ballot(valid && ((dg >> b) & 1));
+      eq &= ((dg >> b) & 1) ? bal : ~bal;
+    }
+    const int rank = __popcll(eq & below);
+    if (valid && rank == 0) wc[w][dg] = __popcll(eq);
+    __syncthreads();
+    {  // thread t: digit t, bases of the four waves
+      int acc = run[t];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int v = wc[q][t];
+        wc[q][t] = acc;
+        acc += v;
+      }
+      run[t] = acc;
+    }
+    __syncthreads();
+    if (valid) out[wc[w][dg] + rank] = key;
+    __syncthreads();
+  }
+}
+
+// sorts keys[0, n) (tmp: n keys of scratch); four passes, so the result is back in keys
+static hipError_t radix_sort32(const DevPtrs& d, unsigned long long* keys, int64_t n, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  const Layout& L = *d.L;
+  unsigned long long* tmp = d.at<unsigned long long>(L.rx_tmp);
+  int32_t* hist = d.at<int32_t>(L.rx_hist);
+  int32_t* off = d.at<int32_t>(L.rx_off);
+  int32_t* part = d.at<int32_t>(L.rx_part);
+  const int64_t nb = (n + RX_B - 1) / RX_B;
+  unsigned long long* src = keys;
+  unsigned long long* dst = tmp;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 32 + 8 * pass;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(256), 0, s, src, n, shift, hist, nb);
+    hipError_t e = launch_excl_scan(hist, 256 * nb, off, part, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(256), 0, s, src, dst, n, shift, off, nb);
+    unsigned long long* x = src;
+    src = dst;
+    dst = x;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s) {
   const Layout& L = *d.L;
   if (N <= 0) return hipSuccess;
-  int64_t npow = BS_LOCAL;
-  while (npow < N) npow <<= 1;
   unsigned long long* keys = d.at<unsigned long long>(L.pkeys);
-  hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, s, X, N, npow, d.D, d.nsp, d.frame(),
-                     keys);
-  hipError_t e = launch_sort_keys(keys, npow, s);
+  hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, N, N, d.D, d.nsp,
+                     d.frame(), keys);
+  hipError_t e = radix_sort32(d, keys, N, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, keys, N,
                      d.at<int32_t>(L.porder), (int32_t*)nullptr, d.at<uint32_t>(L.pcode));
@@ -253,16 +338,14 @@ hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipSt
 
 hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
   const Layout& L = *d.L;
-  int64_t kpow = BS_LOCAL;
-  while (kpow < d.K) kpow <<= 1;
   unsigned long long* keys = d.at<unsigned long long>(L.ckeys);
   int* hist = d.at<int>(L.lhist);
   hipLaunchKernelGGL(k_zero_hist, dim3(1), dim3(LAM_BINS), 0, s, hist);
   hipLaunchKernelGGL(k_lam_hist, dim3(64), dim3(256), 0, s, d.post(), d.K, d.D, d.split, d.nsp, hist);
   hipLaunchKernelGGL(k_lam_anchor, dim3(1), dim3(64), 0, s, hist, d.K, d.frame());
-  hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((kpow + 255) / 256)), dim3(256), 0, s, d.post(), d.K, kpow, d.D,
+  hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.post(), d.K, d.K, d.D,
                      d.split, d.nsp, d.frame(), keys);
-  hipError_t e = launch_sort_keys(keys, kpow, s);
+  hipError_t e = radix_sort32(d, keys, d.K, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, keys, d.K,
                      d.at<int32_t>(L.corder), d.at<int32_t>(L.cinv), d.at<uint32_t>(L.ccode));

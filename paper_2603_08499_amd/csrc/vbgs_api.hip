@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -261,6 +262,13 @@ Layout make_layout(const vbgs_params& p) {
   L.porder = take(sparse ? (size_t)n * 4 : 0);
   L.pcode = take(sparse ? (size_t)n * 4 : 0);
   L.ckeys = take((size_t)kpow * 8);
+  {
+    const int64_t nk = std::max<int64_t>(n, K), nbx = (nk + RX_B - 1) / RX_B, ne = 256 * nbx;
+    L.rx_tmp = take(sparse ? (size_t)nk * 8 : 0);
+    L.rx_hist = take(sparse ? (size_t)ne * 4 : 0);
+    L.rx_off = take(sparse ? (size_t)(ne + 1) * 4 : 0);
+    L.rx_part = take(sparse ? (size_t)((ne + 1023) / 1024 + 2) * 4 : 0);
+  }
   L.corder = take(sparse ? (size_t)L.Kpad * 4 : 0);
   L.cinv = take(sparse ? (size_t)L.Kpad * 4 : 0);
   L.ccode = take(sparse ? (size_t)L.Kpad * 4 : 0);

@@ -117,7 +117,8 @@ struct Layout {
   int nsplit_max;
   // spatial ordering (culled exact sweep)
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
-  size_t bcost, bcode, border;  // per 64-point block: measured sweep time, its first point's Morton
+  size_t bcost, bcode, border;
+  size_t rx_tmp, rx_hist, rx_off, rx_part;  // radix sort: ping-pong keys, digit histograms, scan  // per 64-point block: measured sweep time, its first point's Morton
                                 // code at that time, dispatch order
   // learned proposal (workspace)
   size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
@@ -289,6 +290,8 @@ hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s);
 hipError_t launch_render_marginal(const DevPtrs& model, const DevPtrs& sp, double* reg, hipStream_t s);
 hipError_t launch_psnr(const float* a, const float* b, int64_t n, double* out, hipStream_t s);
 hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
+hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t* part, hipStream_t s);
+constexpr int RX_B = 2048;  // keys per workgroup of the radix sort
 hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s);
 hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s);
 hipError_t launch_reassign(const DevPtrs& d, const float* X, int64_t N, const double* lse, const double* gumbel,
