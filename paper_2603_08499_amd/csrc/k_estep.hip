@@ -1467,38 +1467,46 @@ __global__ __launch_bounds__(256) void k_pass2_direct(const EArgs a) {
 // ---------------------------------------------------------------------------
 // fold: fixed-order sum over splits, un-centre to raw coordinates
 // ---------------------------------------------------------------------------
-__global__ void k_fold(const double* __restrict__ spart, int nsplit, int64_t Kpad, int64_t K, int D,
+template <int D>
+__global__ void k_fold(const double* __restrict__ spart, int nsplit, int64_t Kpad, int64_t K,
                        const FrameInfo* __restrict__ fr, const double* __restrict__ direct, int dts, int mode,
                        double* __restrict__ stats, double* __restrict__ stats_out) {
   // mode 0: partials are raw; 1: centred/scaled frame coordinates x' = (x - mu) / s;
   // 2: raw coordinates centred at the component's own mean m_k
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  const int F = nfeat(D), SS = stat_stride(D);
-  double v[48];
+  constexpr int F = 1 + D + D * (D + 1) / 2, SS = D <= 6 ? 32 : 48;
+  double v[F];
+#pragma unroll
   for (int i = 0; i < F; ++i) {
     double s = 0.0;
     for (int q = 0; q < nsplit; ++q) s += spart[((int64_t)q * Kpad + k) * SS + i];
     v[i] = s;
   }
-  double o[48];
+  double o[F];
   if (mode == 0) {
+#pragma unroll
     for (int i = 0; i < F; ++i) o[i] = v[i];
   } else {
     // x = mu + s x':  S1 = mu N + s S1',  S2_ij = mu_i mu_j N + mu_i s_j S1'_j + s_i mu_j S1'_i + s_i s_j S2'_ij
-    double mu[MAXD], sc[MAXD];
+    double mu[D], sc[D];
+#pragma unroll
     for (int i = 0; i < D; ++i) {
       mu[i] = mode == 1 ? (double)fr->mu[i] : direct[k * dts + 1 + i];
       sc[i] = mode == 1 ? fr->s[i] : 1.0;
     }
     const double Nk = v[0];
     o[0] = Nk;
+#pragma unroll
     for (int i = 0; i < D; ++i) o[1 + i] = mu[i] * Nk + sc[i] * v[1 + i];
     int t = 1 + D;
+#pragma unroll
     for (int i = 0; i < D; ++i)
+#pragma unroll
       for (int j = i; j < D; ++j, ++t)
         o[t] = mu[i] * mu[j] * Nk + mu[i] * sc[j] * v[1 + j] + sc[i] * mu[j] * v[1 + i] + sc[i] * sc[j] * v[t];
   }
+#pragma unroll
   for (int i = 0; i < F; ++i) {
     stats[k * F + i] = o[i];
     if (stats_out) stats_out[k * F + i] = o[i];
@@ -1747,9 +1755,19 @@ hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int
 hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, hipStream_t s) {
   const int mode = c.prec == VBGS_FP64 ? 0 : (c.exact ? 2 : 1);
   const int nsplit = mode == 2 ? 1 : c.nsplit;
-  hipLaunchKernelGGL(k_fold, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.at<double>(d.L->spart),
-                     nsplit, d.L->Kpad, d.K, d.D, d.frame(), d.at<double>(d.L->direct), direct_stride(d.D), mode,
-                     d.at<double>(d.L->stats), stats_out);
+  const dim3 grid((unsigned)((d.K + 255) / 256));
+  switch (d.D) {
+#define VB_FD(DD)                                                                                           \
+  case DD:                                                                                                  \
+    hipLaunchKernelGGL(k_fold<DD>, grid, dim3(256), 0, s, d.at<double>(d.L->spart), nsplit, d.L->Kpad, d.K,  \
+                       d.frame(), d.at<double>(d.L->direct), direct_stride(d.D), mode, d.at<double>(d.L->stats), \
+                       stats_out);                                                                          \
+    break;
+    VB_FD(1) VB_FD(2) VB_FD(3) VB_FD(4) VB_FD(5) VB_FD(6) VB_FD(7) VB_FD(8)
+#undef VB_FD
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -455,26 +455,31 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
 // ---------------------------------------------------------------------------
 // conjugate update through natural parameters (FP64, one thread per component)
 // ---------------------------------------------------------------------------
-__global__ void k_update(double* prior, double* post, const double* __restrict__ st, int D, int64_t K,
-                         int commit, int split) {
+template <int D>
+__global__ void k_update(double* prior, double* post, const double* __restrict__ st, int64_t K, int commit,
+                         int split) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  const int F = nfeat(D);
+  constexpr int F = 1 + D + D * (D + 1) / 2;
   const double* p = prior + k * REC;
   const double* S = st + k * F;
   const double Nk = S[0];
   double r[REC];
+#pragma unroll
   for (int i = 0; i < REC; ++i) r[i] = 0.0;
   // per block: kappa = kappa_p + N, nu = nu_p + N (both blocks see the same N_k)
-  double kp[2], kappa[2];
-  for (int b = 0; b < (split > 0 ? 2 : 1); ++b) {
+  double kp[2] = {1.0, 1.0}, kappa[2] = {1.0, 1.0};
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    if (b == 1 && split == 0) break;
     kp[b] = rec_kappa(p, D, b);
     kappa[b] = kp[b] + Nk;
     r[b ? rec_kc(D) : 1] = kappa[b];
     r[b ? rec_kc(D) + 1 : 2] = rec_nu(p, D, b) + Nk;
   }
   r[0] = p[0] + Nk;
-  double m[MAXD], mp[MAXD];
+  double m[D], mp[D];
+#pragma unroll
   for (int i = 0; i < D; ++i) {
     const int b = coord_block(i, split);
     mp[i] = p[3 + i];
@@ -482,8 +487,10 @@ __global__ void k_update(double* prior, double* post, const double* __restrict__
     r[3 + i] = m[i];
   }
   // W^{-1} + kappa m m^T is additive within a block: T3 = T3_prior + S2; zero across blocks
-  int o = 1 + D;
+  constexpr int o = 1 + D;
+#pragma unroll
   for (int i = 0; i < D; ++i)
+#pragma unroll
     for (int j = i; j < D; ++j) {
       const int t = tri_up(i, j, D);
       const int b = coord_block(i, split);
@@ -491,32 +498,72 @@ __global__ void k_update(double* prior, double* post, const double* __restrict__
                          ? p[3 + D + t] + S[o + t] + kp[b] * mp[i] * mp[j] - kappa[b] * m[i] * m[j]
                          : 0.0;
     }
+#pragma unroll
   for (int i = 0; i < REC; ++i) post[k * REC + i] = r[i];
-  if (commit)
+  if (commit) {
+#pragma unroll
     for (int i = 0; i < REC; ++i) prior[k * REC + i] = r[i];
+  }
 }
 
 hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.prior(), d.post(),
-                     d.at<double>(d.L->stats), d.D, d.K, commit, d.split);
+  const dim3 grid((unsigned)((d.K + 255) / 256));
+  switch (d.D) {
+#define VB_UP(DD)                                                                                          \
+  case DD:                                                                                                 \
+    hipLaunchKernelGGL(k_update<DD>, grid, dim3(256), 0, s, d.prior(), d.post(), d.at<double>(d.L->stats), d.K, \
+                       commit, d.split);                                                                   \
+    break;
+    VB_UP(1) VB_UP(2) VB_UP(3) VB_UP(4) VB_UP(5) VB_UP(6) VB_UP(7) VB_UP(8)
+#undef VB_UP
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // ELBO: F = ln2 * sum LSE2 - [lnGamma(sum alpha) - lnGamma(sum alpha_p)] - sum_k kl_k
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_elbo(const double* __restrict__ lse_part, int64_t np,
-                                               const double* __restrict__ kl, int64_t K,
-                                               const FrameInfo* __restrict__ fr, double* out) {
-  __shared__ double a[1024], b[1024];
+// Two stages in a fixed order (so the value does not depend on scheduling): ELBO_BLOCKS workgroups
+// each sum one contiguous range of the LSE partials and of the KL terms, then one workgroup sums
+// their partials.
+constexpr int ELBO_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_elbo_part(const double* __restrict__ lse_part, int64_t np,
+                                                   const double* __restrict__ kl, int64_t K,
+                                                   double* __restrict__ part) {
+  __shared__ double a[256], b[256];
   const int t = threadIdx.x;
+  const int64_t pp = (np + ELBO_BLOCKS - 1) / ELBO_BLOCKS, pk = (K + ELBO_BLOCKS - 1) / ELBO_BLOCKS;
+  const int64_t p0 = blockIdx.x * pp, p1 = min(p0 + pp, np), k0 = blockIdx.x * pk, k1 = min(k0 + pk, K);
   double s = 0.0, u = 0.0;
-  for (int64_t i = t; i < np; i += 1024) s += lse_part[i];
-  for (int64_t i = t; i < K; i += 1024) u += kl[i];
+  for (int64_t i = p0 + t; i < p1; i += 256) s += lse_part[i];
+  for (int64_t i = k0 + t; i < k1; i += 256) u += kl[i];
   a[t] = s;
   b[t] = u;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      a[t] += a[t + w];
+      b[t] += b[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[blockIdx.x] = a[0];
+    part[ELBO_BLOCKS + blockIdx.x] = b[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_elbo(const double* __restrict__ part, const FrameInfo* __restrict__ fr,
+                                              double* out) {
+  __shared__ double a[256], b[256];
+  const int t = threadIdx.x;
+  a[t] = part[t];
+  b[t] = part[ELBO_BLOCKS + t];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
     if (t < w) {
       a[t] += a[t + w];
       b[t] += b[t + w];
@@ -530,8 +577,10 @@ __global__ __launch_bounds__(1024) void k_elbo(const double* __restrict__ lse_pa
 }
 
 hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_elbo, dim3(1), dim3(1024), 0, s, d.at<double>(d.L->lse_part), n_lse_part,
-                     d.at<double>(d.L->kl), d.K, d.frame(), out);
+  double* part = d.at<double>(d.L->elbo_part);
+  hipLaunchKernelGGL(k_elbo_part, dim3(ELBO_BLOCKS), dim3(256), 0, s, d.at<double>(d.L->lse_part), n_lse_part,
+                     d.at<double>(d.L->kl), d.K, part);
+  hipLaunchKernelGGL(k_elbo, dim3(1), dim3(256), 0, s, part, d.frame(), out);
   return hipGetLastError();
 }
 

@@ -278,6 +278,7 @@ Layout make_layout(const vbgs_params& p) {
   L.ncg = take(sparse ? (size_t)L.Kpad / 4 * sizeof(float) : 0);
   L.lhist = take(sparse ? (size_t)LAM_BINS * 4 : 0);
   L.scan_part = take(sparse ? (size_t)((L.Kpad + 1023) / 1024 + 1) * 4 : 0);
+  L.elbo_part = take(512 * 8);
   L.bcost = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.bcode = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.border = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);

@@ -118,6 +118,7 @@ struct Layout {
   // spatial ordering (culled exact sweep)
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
   size_t bcost, bcode, border;
+  size_t elbo_part;  // 2 x 256 partial sums of the ELBO reduction
   size_t rx_tmp, rx_hist, rx_off, rx_part;  // radix sort: ping-pong keys, digit histograms, scan  // per 64-point block: measured sweep time, its first point's Morton
                                 // code at that time, dispatch order
   // learned proposal (workspace)
