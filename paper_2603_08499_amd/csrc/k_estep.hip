@@ -1317,41 +1317,34 @@ __device__ __forceinline__ void fx_acc(Fx128& a, double v) {
   a.hi += (long long)hi_d + (a.lo < lo ? 1 : 0);
 }
 
+// A component with more than HEAVY kept pairs is summed by a whole wave (k_comp_stats_heavy), so
+// that no thread here walks a long list; 128-bit integer sums do not depend on how the pairs are
+// split among lanes.
+constexpr int HEAVY = 64;
+
 template <int DT>
-__global__ __launch_bounds__(128) void k_comp_stats(const EArgs a) {
-  constexpr int F = 1 + DT + DT * (DT + 1) / 2;
-  const int64_t k = (int64_t)blockIdx.x * 128 + threadIdx.x;
-  if (k >= a.K) return;
-  double is[DT];
+__device__ __forceinline__ void comp_pair_acc(const EArgs& a, const double* row, int64_t n, const double* is,
+                                              Fx128* acc) {
+  double d[DT];
+  const double s2 = direct_score2_dt<DT>(row, a.X + n * DT, d);
+  const double r = exp2(s2 - a.lse2[n]);
+  fx_acc(acc[0], r);
+  double u[DT];
 #pragma unroll
-  for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
-  Fx128 acc[F];
-#pragma unroll
-  for (int f = 0; f < F; ++f) {  // contributions of overflowed points (global fixed-point atomics)
-    acc[f].lo = a.fx[(k * FP + f) * 2];
-    acc[f].hi = (long long)a.fx[(k * FP + f) * 2 + 1];
+  for (int i = 0; i < DT; ++i) {
+    u[i] = d[i] * is[i];
+    fx_acc(acc[1 + i], r * u[i]);
   }
-  const double* row = a.direct + k * a.dts;
-  const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
-  for (int32_t e = e0; e < e1; ++e) {
-    const int64_t n = a.ent_n[e];
-    double d[DT];
-    const double s2 = direct_score2_dt<DT>(row, a.X + n * DT, d);
-    const double r = exp2(s2 - a.lse2[n]);
-    fx_acc(acc[0], r);
-    double u[DT];
+  int o = 1 + DT;
 #pragma unroll
-    for (int i = 0; i < DT; ++i) {
-      u[i] = d[i] * is[i];
-      fx_acc(acc[1 + i], r * u[i]);
-    }
-    int o = 1 + DT;
+  for (int i = 0; i < DT; ++i)
 #pragma unroll
-    for (int i = 0; i < DT; ++i)
-#pragma unroll
-      for (int j = i; j < DT; ++j, ++o) fx_acc(acc[o], r * u[i] * u[j]);
-  }
-  // fixed point -> FP64, undo the power-of-two scaling; raw coordinates centred at m_k
+    for (int j = i; j < DT; ++j, ++o) fx_acc(acc[o], r * u[i] * u[j]);
+}
+
+// fixed point -> FP64, undo the power-of-two scaling; raw coordinates centred at m_k
+template <int DT>
+__device__ __forceinline__ void comp_stats_out(const EArgs& a, int64_t k, const Fx128* acc) {
   double* out = a.spart + k * FP;
   out[0] = (double)acc[0].hi + (double)acc[0].lo * 5.42101086242752217e-20;
 #pragma unroll
@@ -1363,6 +1356,82 @@ __global__ __launch_bounds__(128) void k_comp_stats(const EArgs a) {
 #pragma unroll
     for (int j = i; j < DT; ++j, ++o)
       out[o] = ((double)acc[o].hi + (double)acc[o].lo * 5.42101086242752217e-20) * a.frame->s[i] * a.frame->s[j];
+}
+
+// one wave per 64 components; each of them with more than HEAVY pairs is summed by the whole wave
+// (lanes take every 64th pair, then a 128-bit wave sum)
+template <int DT>
+__global__ __launch_bounds__(64) void k_comp_stats_heavy(const EArgs a) {
+  constexpr int F = 1 + DT + DT * (DT + 1) / 2;
+  const int lane = threadIdx.x;
+  const int64_t kl = (int64_t)blockIdx.x * 64 + lane;
+  const bool heavy = kl < a.K && a.coffset[kl + 1] - a.coffset[kl] > HEAVY;
+  unsigned long long hm = __ballot(heavy);
+  if (hm == 0ull) return;
+  double is[DT];
+#pragma unroll
+  for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
+  while (hm) {
+    const int q = __ffsll((long long)hm) - 1;
+    hm &= hm - 1ull;
+    const int64_t k = (int64_t)blockIdx.x * 64 + q;
+    const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
+    Fx128 acc[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {  // lane 0 starts from the overflowed points' contributions
+      acc[f].lo = lane == 0 ? a.fx[(k * FP + f) * 2] : 0ull;
+      acc[f].hi = lane == 0 ? (long long)a.fx[(k * FP + f) * 2 + 1] : 0ll;
+    }
+    const double* row = a.direct + k * a.dts;
+    for (int32_t e = e0 + lane; e < e1; e += 64) comp_pair_acc<DT>(a, row, a.ent_n[e], is, acc);
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long lo2 = __shfl_xor(acc[f].lo, off);
+        const long long hi2 = __shfl_xor(acc[f].hi, off);
+        const unsigned long long lo = acc[f].lo + lo2;
+        acc[f].hi += hi2 + (lo < lo2 ? 1 : 0);
+        acc[f].lo = lo;
+      }
+    if (lane == 0) comp_stats_out<DT>(a, k, acc);
+  }
+}
+
+// CG lanes per component (the others: k_comp_stats_heavy): lane j takes pairs j, j + CG, ..., then
+// the lanes' 128-bit sums are added (the shorter chains hide the gathers' latency)
+constexpr int CG = 4;
+
+template <int DT>
+__global__ __launch_bounds__(128) void k_comp_stats(const EArgs a) {
+  constexpr int F = 1 + DT + DT * (DT + 1) / 2;
+  const int64_t k = ((int64_t)blockIdx.x * 128 + threadIdx.x) / CG;
+  const int j = threadIdx.x % CG;
+  const bool val = k < a.K && a.coffset[k + 1] - a.coffset[k] <= HEAVY;
+  double is[DT];
+#pragma unroll
+  for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
+  Fx128 acc[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {  // lane 0 of the group starts from the overflowed points' contributions
+    acc[f].lo = val && j == 0 ? a.fx[(k * FP + f) * 2] : 0ull;
+    acc[f].hi = val && j == 0 ? (long long)a.fx[(k * FP + f) * 2 + 1] : 0ll;
+  }
+  if (val) {
+    const double* row = a.direct + k * a.dts;
+    const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
+    for (int32_t e = e0 + j; e < e1; e += CG) comp_pair_acc<DT>(a, row, a.ent_n[e], is, acc);
+  }
+#pragma unroll
+  for (int f = 0; f < F; ++f)
+#pragma unroll
+    for (int off = CG / 2; off > 0; off >>= 1) {
+      const unsigned long long lo2 = __shfl_xor(acc[f].lo, off);
+      const long long hi2 = __shfl_xor(acc[f].hi, off);
+      const unsigned long long lo = acc[f].lo + lo2;
+      acc[f].hi += hi2 + (lo < lo2 ? 1 : 0);
+      acc[f].lo = lo;
+    }
+  if (val && j == 0) comp_stats_out<DT>(a, k, acc);
 }
 
 __global__ void k_zero_i32(int32_t* p, int64_t n, const int32_t* gate) {
@@ -1592,7 +1661,6 @@ hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s) {
 hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) {
   if (N > 0) {
     const dim3 gp((unsigned)((N + 255) / 256));
-    const dim3 gk((unsigned)((a.K + 127) / 128));
     const int64_t nsb = (a.K + SCAN_B - 1) / SCAN_B;
     switch (D) {
 #define VB_ST(DD)                                                                         \
@@ -1603,7 +1671,8 @@ hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) 
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part,   \
                        a.coffset);                                                                       \
     hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                          \
-    hipLaunchKernelGGL(k_comp_stats<DD>, gk, dim3(128), 0, s, a);                         \
+    hipLaunchKernelGGL(k_comp_stats<DD>, dim3((unsigned)((a.K * CG + 127) / 128)), dim3(128), 0, s, a); \
+    hipLaunchKernelGGL(k_comp_stats_heavy<DD>, dim3((unsigned)((a.K + 63) / 64)), dim3(64), 0, s, a); \
     break;
       VB_ST(1) VB_ST(2) VB_ST(3) VB_ST(4) VB_ST(5) VB_ST(6)
 #undef VB_ST
