@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="copy this many MiB device to device once before the timed loop (a kernel of known "
                          "traffic for scaling the HBM byte counters of a profiled run)")
-    ap.add_argument("--c5-prec", default="fp32", help="screen precision of --workload c5")
+    ap.add_argument("--c5-prec", default="auto", help="screen precision of --workload c5")
     ap.add_argument("--c5-cpu-pixels", type=int, default=2048)
     ap.add_argument("--c4-exact", type=int, default=10)
     ap.add_argument("--c4-train-steps", type=int, default=1500)

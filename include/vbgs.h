@@ -70,7 +70,11 @@ typedef enum {
   VBGS_FP64 = 0,    /* direct form (x-m)^T W (x-m) in FP64 on the vector ALUs */
   VBGS_FP32 = 1,    /* v_mfma_f32_16x16x4_f32, FP32 accumulation */
   VBGS_BF16 = 2,    /* v_mfma_f32_16x16x32_bf16, FP32 accumulation */
-  VBGS_BF16X3 = 3   /* split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+  VBGS_BF16X3 = 3,  /* split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+  VBGS_AUTO = 4     /* exact = 1 only: per E-step, the split-BF16 screen unless its error bound
+                       (2^-12 |c| |phi| for the mean coefficient-row and feature norms) exceeds
+                       32 log2 units, else the FP32 screen; the choice is made on the device and
+                       reported by vbgs_counters (the results are exact either way) */
 } vbgs_prec;
 
 typedef struct {
@@ -113,7 +117,8 @@ typedef struct {
 #define VBGS_H 128         /* hidden width of the proposal network (= embedding width) */
 
 /* Fill *p with defaults for (D, K, n_max): kappa0 = 1, nu0 = D + 2, alpha0 = 1,
- * score_prec = VBGS_BF16X3, exact = 1, screen_margin = 0 (automatic). */
+ * score_prec = VBGS_AUTO (D <= 6; else VBGS_FP64), exact = 1, screen_margin = 0 (automatic). Set
+ * an explicit MFMA precision with exact = 0 or with the proposal. */
 vbgs_status vbgs_default_params(vbgs_params* p, int32_t D, int64_t K, int64_t n_max);
 
 /* Bytes of caller-owned device memory: `state` persists across calls and frames
@@ -216,8 +221,10 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
  * out[4] = blocks of 64 points x 16 components the sweep screened on MFMA, out[5] = the
  * number of such blocks without culling (4 per 256-point workgroup and 16 components), out[6] =
  * the blocks screened by all E-steps since vbgs_init or the last vbgs_clear_flags, out[7] = the
- * points whose candidate lists overflowed (their LSE and statistics come from a full rescan). */
-vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[8], void* stream);
+ * points whose candidate lists overflowed (their LSE and statistics come from a full rescan),
+ * out[8] = the screen precision the sweep used (vbgs_prec), out[9] = the split-BF16 screen's
+ * error bound for the mean coefficient-row and feature norms, in 1/1000 log2 units. */
+vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[10], void* stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each call.
  * Phases: 0 frame moments + features, 1 expectations + coefficient rows (with culling also the

@@ -952,6 +952,67 @@ __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost,
   for (int i = tid; i < len; i += 1024) border[start + i] = (int32_t)(start + (int64_t)(key[i] & 0xFFFFFFFFull));
 }
 
+// ---- screen precision of the exact mode -------------------------------------------------------------
+// The screen's error bound for a pair is eps |c_k| |phi_n| (log2 units). For the mean row and
+// feature norms the split-BF16 bound (eps = 2^-12) is recorded in the frame; with VBGS_AUTO the FP32
+// screen (eps = 2^-16) is taken when that bound exceeds AUTO_BUDGET (a loose screen records so
+// many candidates that points overflow their lists). Two fixed-order stages (deterministic).
+constexpr float AUTO_BUDGET = 32.0f;
+constexpr int SCR_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void k_screen_part(const float* __restrict__ nc, int64_t nrow,
+                                                     const float* __restrict__ nphi, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double a[256], b[256];
+  const int t = threadIdx.x;
+  const int64_t pr = (nrow + SCR_BLOCKS - 1) / SCR_BLOCKS, pn = (n + SCR_BLOCKS - 1) / SCR_BLOCKS;
+  const int64_t r0 = blockIdx.x * pr, r1 = min(r0 + pr, nrow), n0 = blockIdx.x * pn, n1 = min(n0 + pn, n);
+  double s = 0.0, u = 0.0;
+  for (int64_t i = r0 + t; i < r1; i += 256) s += nc[i];
+  for (int64_t i = n0 + t; i < n1; i += 256) u += nphi[i];
+  a[t] = s;
+  b[t] = u;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      a[t] += a[t + w];
+      b[t] += b[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[blockIdx.x] = a[0];
+    part[SCR_BLOCKS + blockIdx.x] = b[0];
+  }
+}
+
+// force: the configured precision, or VBGS_AUTO to choose; gate[0] / gate[1]: run the split-BF16 /
+// the FP32 screen
+__global__ __launch_bounds__(256) void k_screen_pick(const double* __restrict__ part, int64_t K, int64_t n,
+                                                     int force, FrameInfo* __restrict__ fr,
+                                                     int32_t* __restrict__ gate) {
+  __shared__ double a[256], b[256];
+  const int t = threadIdx.x;
+  a[t] = part[t];
+  b[t] = part[SCR_BLOCKS + t];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      a[t] += a[t + w];
+      b[t] += b[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const float slack = (float)((double)screen_eps(VBGS_BF16X3) * (a[0] / (double)K) * (b[0] / (double)n));
+    const int prec = force != VBGS_AUTO ? force : (slack > AUTO_BUDGET ? VBGS_FP32 : VBGS_BF16X3);
+    fr->screen_slack = slack;
+    fr->screen_prec = prec;
+    gate[0] = prec == VBGS_BF16X3 ? 1 : 0;
+    gate[1] = prec == VBGS_FP32 ? 1 : 0;
+  }
+}
+
 // ---- exact LSE of the recorded candidates, one thread per point ---------------------------------
 template <int DT>
 __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
@@ -1598,19 +1659,28 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, a.gate);
   } else if (stage == 1) {
     const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
+    hipLaunchKernelGGL(k_screen_part, dim3(SCR_BLOCKS), dim3(256), 0, s, a.nc, a.Kpad, a.nphi, N, a.scr_part);
+    hipLaunchKernelGGL(k_screen_pick, dim3(1), dim3(256), 0, s, a.scr_part, a.K, N, prec, a.frame, a.scr_gate);
+    // VBGS_AUTO: both screens are enqueued, each gated by the choice (the other exits at once)
+    EArgs ab = a, af = a;
+    if (prec == VBGS_AUTO) {
+      ab.gate = a.scr_gate;
+      ab.eps = screen_eps(VBGS_BF16X3);
+      af.gate = a.scr_gate + 1;
+      af.eps = screen_eps(VBGS_FP32);
+    }
+    const bool run_bf3 = prec == VBGS_BF16X3 || prec == VBGS_AUTO, run_f32 = prec == VBGS_FP32 || prec == VBGS_AUTO;
     if (cull) {
       const dim3 gw((unsigned)((N + 63) / 64));  // one 64-point wave per workgroup
       hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, (int64_t)gw.x,
                          a.nb_cap, a.border, a.order_reset);
-      if (prec == VBGS_FP32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), gw, dim3(64), 0, s, a);
-      else if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), gw, dim3(64), 0, s, a);
-      else hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), gw, dim3(64), 0, s, a);
-    } else if (prec == VBGS_FP32) {
-      hipLaunchKernelGGL((k_pass1<VBGS_FP32, true>), grid, dim3(256), 0, s, a);
-    } else if (prec == VBGS_BF16) {
-      hipLaunchKernelGGL((k_pass1<VBGS_BF16, true>), grid, dim3(256), 0, s, a);
+      if (run_f32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), gw, dim3(64), 0, s, af);
+      if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), gw, dim3(64), 0, s, a);
+      if (run_bf3) hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), gw, dim3(64), 0, s, ab);
     } else {
-      hipLaunchKernelGGL((k_pass1<VBGS_BF16X3, true>), grid, dim3(256), 0, s, a);
+      if (run_f32) hipLaunchKernelGGL((k_pass1<VBGS_FP32, true>), grid, dim3(256), 0, s, af);
+      if (prec == VBGS_BF16) hipLaunchKernelGGL((k_pass1<VBGS_BF16, true>), grid, dim3(256), 0, s, a);
+      if (run_bf3) hipLaunchKernelGGL((k_pass1<VBGS_BF16X3, true>), grid, dim3(256), 0, s, ab);
     }
   } else {
     const dim3 gp((unsigned)((N + 255) / 256));
@@ -1734,6 +1804,8 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.bcode = d.at<uint32_t>(L.bcode);
   a.border = d.at<int32_t>(L.border);
   a.nb_cap = (L.bcode - L.bcost) / 4;
+  a.scr_part = d.at<double>(L.scr_part);
+  a.scr_gate = d.at<int32_t>(L.scr_gate);
   a.order_reset = c.order_reset;
   a.eps = screen_eps(c.prec);
   return a;

@@ -94,7 +94,7 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "prior scalars need kappa0 > 0, alpha0 > 0, nu0 > D - 1";
     return VBGS_ERR_ARG;
   }
-  if (p->score_prec < VBGS_FP64 || p->score_prec > VBGS_BF16X3) {
+  if (p->score_prec < VBGS_FP64 || p->score_prec > VBGS_AUTO) {
     if (why) *why = "unknown score_prec";
     return VBGS_ERR_ARG;
   }
@@ -109,6 +109,10 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
   if (p->exact != 0 && p->exact != 1) {
     if (why) *why = "exact must be 0 or 1";
     return VBGS_ERR_ARG;
+  }
+  if (p->score_prec == VBGS_AUTO && (p->exact != 1 || p->proposal)) {
+    if (why) *why = "VBGS_AUTO chooses the screen of the exact mode: it needs exact = 1 and no proposal";
+    return VBGS_ERR_UNSUPPORTED;
   }
   if (!isfinite(p->screen_margin)) {
     if (why) *why = "screen_margin must be finite";
@@ -279,6 +283,8 @@ Layout make_layout(const vbgs_params& p) {
   L.lhist = take(sparse ? (size_t)LAM_BINS * 4 : 0);
   L.scan_part = take(sparse ? (size_t)((L.Kpad + 1023) / 1024 + 1) * 4 : 0);
   L.elbo_part = take(512 * 8);
+  L.scr_part = take(512 * 8);
+  L.scr_gate = take(2 * 4);
   L.bcost = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.bcode = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.border = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
@@ -336,7 +342,7 @@ vbgs_status vbgs_default_params(vbgs_params* p, int32_t D, int64_t K, int64_t n_
   p->kappa0 = 1.0;
   p->nu0 = D + 2.0;
   p->alpha0 = 1.0;
-  p->score_prec = D <= 6 ? VBGS_BF16X3 : VBGS_FP64;
+  p->score_prec = D <= 6 ? VBGS_AUTO : VBGS_FP64;
   p->exact = 1;
   p->screen_margin = 0.0;
   p->C = 32;
@@ -638,7 +644,7 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* c, void* stream) {
   return hipfail(c, launch_clear_flags(c->dev(), S(stream)), "clear_flags");
 }
 
-vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[8], void* stream) {
+vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[10], void* stream) {
   if (!c || !out) return VBGS_ERR_ARG;
   FrameInfo f;
   hipError_t e = hipStreamSynchronize(S(stream));
@@ -652,6 +658,8 @@ vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[8], void* stream) {
   out[5] = c->last_N > 0 ? (c->last_N + P1_PTS - 1) / P1_PTS * (P1_PTS / 64) * (c->L.Kpad / 16) : 0;
   out[6] = (int64_t)f.blocks_cum;
   out[7] = f.n_over;
+  out[8] = f.screen_prec;
+  out[9] = (int64_t)llround((double)f.screen_slack * 1000.0);
   return VBGS_OK;
 }
 

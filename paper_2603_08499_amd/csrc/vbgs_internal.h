@@ -50,7 +50,8 @@ struct FrameInfo {
   int32_t lam_anchor;    // curvature class anchor of the component sort (bin of lambda, see lam_bin)
   unsigned long long blocks;      // 64-point x 64-component blocks screened by the exact sweep
   unsigned long long blocks_cum;  // the same, summed since the last clear of the flags
-  double pad1[1];
+  float screen_slack;    // split-BF16 screen bound for the mean |c| and |phi| (log2 units)
+  int32_t screen_prec;   // screen precision the last sweep used
 };
 
 // Bound of a 64-row tile of the spatially sorted component table (culled exact sweep).
@@ -119,6 +120,7 @@ struct Layout {
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
   size_t bcost, bcode, border;
   size_t elbo_part;  // 2 x 256 partial sums of the ELBO reduction
+  size_t scr_part, scr_gate;  // screen choice: 2 x 256 partial norm sums, two gate flags
   size_t rx_tmp, rx_hist, rx_off, rx_part;  // radix sort: ping-pong keys, digit histograms, scan  // per 64-point block: measured sweep time, its first point's Morton
                                 // code at that time, dispatch order
   // learned proposal (workspace)
@@ -346,6 +348,8 @@ struct EArgs {
   uint32_t* bcode;            // and the Morton code of its first point then
   int32_t* border;            // culled sweep: dispatch position -> block (costliest first per XCD)
   int64_t nb_cap;             // capacity of bcost / border
+  double* scr_part;           // screen choice: partial sums of the row and feature norms
+  int32_t* scr_gate;          // screen choice: [run split BF16, run FP32]
   int order_reset;
   int64_t N, K, Kpad;
   int D, dts, nsplit;

@@ -28,7 +28,7 @@ def _stream(s=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x3", exact=True,
+def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec=None, exact=True,
                 screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096, cull=True, modal_split=0,
                 cull_dims=0):
     p = _lib.Params()
@@ -39,6 +39,8 @@ def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec="bf16x
     p.kappa0 = float(kappa0)
     p.nu0 = float(D + 2 if nu0 is None else nu0)
     p.alpha0 = float(alpha0)
+    if score_prec is None:  # the automatic screen where it applies (exact mode, no proposal), else split BF16
+        score_prec = "auto" if exact and not proposal and D <= 6 else ("bf16x3" if D <= 6 else "fp64")
     p.score_prec = _lib.PREC[score_prec] if isinstance(score_prec, str) else int(score_prec)
     p.exact = 1 if exact else 0
     p.screen_margin = float(screen_margin)
@@ -175,10 +177,12 @@ class VBGS:
         self._check(self.lib.vbgs_clear_flags(self.ctx, _stream()))
 
     def counters(self):
-        out = (ctypes.c_int64 * 8)()
+        out = (ctypes.c_int64 * 10)()
         self._check(self.lib.vbgs_counters(self.ctx, out, _stream()))
+        names = {v: k for k, v in _lib.PREC.items()}
         return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3], blocks=out[4],
-                    blocks_dense=out[5], blocks_cum=out[6], n_over=out[7])
+                    blocks_dense=out[5], blocks_cum=out[6], n_over=out[7], screen=names.get(out[8], out[8]),
+                    screen_bound_bf16x3=out[9] / 1000.0)
 
     def reassign(self, X, lse, gumbel, n):
         """Move the means of the n least-used components onto n points drawn with probabilities
@@ -197,7 +201,7 @@ class VBGS:
         return pts, comps
 
     # ---- rendering ------------------------------------------------------------------------
-    def renderer(self, n_max, score_prec="bf16x3", exact=True, **kw):
+    def renderer(self, n_max, score_prec=None, exact=True, **kw):
         """The position context vbgs_render needs: D_s = modal_split (or 2 for D = 5 images, else 3),
         the model's K, n_max query positions. Its parameters are overwritten by every render."""
         s = self.params.modal_split or (2 if self.D == 5 else 3)

@@ -58,6 +58,12 @@ def test_query_sizes_and_validation():
     # the proposal needs the exact MFMA mode; its weights and Adam moments live in the state
     with pytest.raises(P.VBGSError):
         P.query_sizes(P.make_params(6, 10, 10, score_prec="fp64", proposal=True))
+    # the automatic screen precision belongs to the exact mode without the proposal
+    P.query_sizes(P.make_params(6, 10, 10, score_prec="auto"))
+    for args in (dict(exact=False), dict(proposal=True)):
+        with pytest.raises(P.VBGSError) as e:
+            P.query_sizes(P.make_params(6, 10, 10, score_prec="auto", **args))
+        assert e.value.status == -7
     # culling coordinates: 0 (automatic) or 1..min(D, 3)
     P.query_sizes(P.make_params(5, 10, 10, cull_dims=2))
     for args in (dict(D=6, cull_dims=4), dict(D=2, cull_dims=3), dict(D=6, cull_dims=-1)):

@@ -16,7 +16,7 @@ from synth import scenes
 
 gpu = pytest.mark.gpu
 
-EXACT_TIERS = [("fp64", True), ("fp32", True), ("bf16", True), ("bf16x3", True)]
+EXACT_TIERS = [("fp64", True), ("fp32", True), ("bf16", True), ("bf16x3", True), ("auto", True)]
 
 
 @pytest.fixture(scope="module")
@@ -309,3 +309,33 @@ def test_cull_matches_unculled(dev, case):
     print("  culled vs unculled: max|dLSE| %.2e stats relerr %.2e dF %.2e" % (dl, es, abs(F0 - F1)),
           "counters unculled", c0, "culled", c1)
     assert dl < 1e-9 and es < 1e-9 and abs(F0 - F1) <= 1e-11 * abs(F0)
+
+
+@gpu
+def test_auto_screen_choice(dev):
+    """VBGS_AUTO keeps the split-BF16 screen where its bound is small (c3 slice) and takes the FP32
+    screen where it is not (the 800x800 image, 50000 components in the unit square); both match the
+    oracle."""
+    scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
+    X0 = scenes.c3_frame(0, scene=scene)
+    pr3 = scenes.c3_prior(X0)
+    X5 = scenes.c5_frame()
+    pr5 = scenes.c5_prior(X5)
+    for name, X, pr, want in (("c3", np.ascontiguousarray(X0[150000:154096]), pr3, "bf16x3"),
+                              ("c5", np.ascontiguousarray(X5.reshape(800, 800, 5)[:64, :64].reshape(-1, 5)), pr5,
+                               "fp32")):
+        m = _model(dev, pr, X.shape[0], "auto", True)
+        lse, st = m.estep_stats(torch.from_numpy(X).to(dev))
+        torch.cuda.synchronize()
+        cnt = m.counters()
+        p = R.NW.from_prior(pr)
+        e = R.expectations(p)
+        ls = R.lse(X, p, e)
+        ref = R.stats(X, p, ls, e, scatter=False).packed()
+        dl = np.abs(lse.cpu().numpy() - ls).max()
+        es = _stat_err(ref, st.cpu().numpy(), pr.D)
+        print(name, "screen", cnt["screen"], "bf16x3 bound %.1f log2" % cnt["screen_bound_bf16x3"],
+              "max|dLSE| %.2e stats relerr %.2e" % (dl, es))
+        assert cnt["screen"] == want
+        assert dl < 2e-6 and es < 1e-5
+        m.close()
