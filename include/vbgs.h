@@ -81,7 +81,7 @@ typedef struct {
   int32_t abi_version;     /* must be VBGS_ABI_VERSION */
   int32_t D;               /* feature dimension, 1..8 (MFMA precisions: 1..6) */
   int64_t K;               /* number of components, >= 1 */
-  int64_t n_max;           /* largest N any call will pass (workspace sizing) */
+  int64_t n_max;           /* largest N any call will pass (workspace sizing); exact MFMA mode: <= 2^23 */
   double kappa0, nu0, alpha0;  /* shared prior scalars: kappa0 > 0, nu0 > D-1, alpha0 > 0 */
   int32_t score_prec;      /* vbgs_prec */
   int32_t exact;           /* MFMA precisions only. 1: the GEMM is a bounded screen and every

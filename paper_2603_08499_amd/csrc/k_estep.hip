@@ -589,6 +589,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ TileStage<P> stg;    // operands of the tile being screened or the next one
   const uint64_t t_start = wall_clock64();
   const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
+  if (blockIdx.x == 0 && lane == 0) a.bprev[0] = gridDim.x;  // read by the next launch's k_block_order
   const int64_t jb = a.border[xcd_block(blockIdx.x, gridDim.x)];
   const int64_t j0 = jb * (P1_PB * 16);  // sorted positions
   const int ns = a.nsp;
@@ -891,17 +892,18 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n, const int32_t* gate
 
 // ---- dispatch order of the culled sweep ------------------------------------------------------------
 // Workgroups go to the eight XCDs in turn and each XCD takes one contiguous range of the point
-// blocks (xcd_block). Within its range, an XCD starts the blocks whose last sweep took longest
-// first (longest processing time first), so that the long blocks do not form the tail. The costs
-// are those the previous launch on the same context measured; they predict this launch when the
-// blocks hold the same points (coordinate-ascent steps on one frame), checked through the Morton
-// code of each block's first point: a range where fewer than 7/8 of the blocks match, one longer
-// than BO_MAX, or a reset keeps the Morton order (which keeps neighbouring blocks, and the
-// component tiles they share, together in time). Any order gives the same results.
+// blocks (xcd_block). Within its range, an XCD starts the blocks predicted to take longest first
+// (longest processing time first), so that the long blocks do not form the tail. A block's
+// predicted cost is the time the previous launch on the same context measured for the block
+// that covered the same place: the previous blocks are in Morton order, so the one whose first
+// point's code is the largest not above this block's first code (the same block when the points
+// are the same, as in coordinate-ascent steps on one frame; a neighbour in space on a new frame).
+// A range longer than BO_MAX, or a reset, keeps the Morton order. Any order gives the same results.
 constexpr int BO_MAX = 4096;
 
 __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost, const uint32_t* __restrict__ bcode,
                                                       const uint32_t* __restrict__ pcode, int64_t nb, int64_t cap,
+                                                      const int64_t* __restrict__ bprev,
                                                       int32_t* __restrict__ border, int reset) {
   __shared__ unsigned long long key[BO_MAX];
   const int tid = threadIdx.x, x = blockIdx.x;
@@ -910,16 +912,8 @@ __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost,
   if (reset) {
     for (int64_t i = (int64_t)x * 1024 + tid; i < cap; i += 8 * 1024) bcost[i] = 0.0f;
   }
-  __shared__ int same;
-  if (tid == 0) same = 0;
-  __syncthreads();
-  if (!reset && len <= BO_MAX) {
-    int m = 0;
-    for (int64_t i = tid; i < len; i += 1024) m += bcode[start + i] == pcode[(start + i) * 64] ? 1 : 0;
-    if (m) atomicAdd(&same, m);
-  }
-  __syncthreads();
-  if (reset || len > BO_MAX || 8 * (int64_t)same < 7 * len) {
+  const int64_t np = reset ? 0 : bprev[0];
+  if (reset || len > BO_MAX || np < 1 || np > cap) {
     for (int64_t i = tid; i < len; i += 1024) border[start + i] = (int32_t)(start + i);
     return;
   }
@@ -927,7 +921,15 @@ __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost,
   while (n2 < len) n2 <<= 1;
   for (int i = tid; i < n2; i += 1024) {
     if (i < len) {
-      float v = bcost[start + i];
+      // the previous block covering this block's first point: last code <= this one (else the first)
+      const uint32_t code = pcode[(start + i) * 64];
+      int64_t lo = 0, hi = np - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (bcode[mid] <= code) lo = mid;
+        else hi = mid - 1;
+      }
+      float v = bcost[lo];
       v = v > 0.0f ? v : 0.0f;  // also maps NaN to 0
       key[i] = ((unsigned long long)(0xFFFFFFFFu - __float_as_uint(v)) << 32) | (unsigned)i;
     } else {
@@ -1673,7 +1675,7 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     if (cull) {
       const dim3 gw((unsigned)((N + 63) / 64));  // one 64-point wave per workgroup
       hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, (int64_t)gw.x,
-                         a.nb_cap, a.border, a.order_reset);
+                         a.nb_cap, a.bprev, a.border, a.order_reset);
       if (run_f32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), gw, dim3(64), 0, s, af);
       if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), gw, dim3(64), 0, s, a);
       if (run_bf3) hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), gw, dim3(64), 0, s, ab);
@@ -1803,6 +1805,7 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.bcost = d.at<float>(L.bcost);
   a.bcode = d.at<uint32_t>(L.bcode);
   a.border = d.at<int32_t>(L.border);
+  a.bprev = d.at<int64_t>(L.bprev);
   a.nb_cap = (L.bcode - L.bcost) / 4;
   a.scr_part = d.at<double>(L.scr_part);
   a.scr_gate = d.at<int32_t>(L.scr_gate);

@@ -102,8 +102,8 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "MFMA precisions support D <= 6 (32 feature slots); use VBGS_FP64";
     return VBGS_ERR_UNSUPPORTED;
   }
-  if (p->score_prec != VBGS_FP64 && p->exact == 1 && p->n_max > ((int64_t)1 << 25)) {
-    if (why) *why = "exact MFMA mode supports n_max <= 2^25 (candidate lists are indexed in int32)";
+  if (p->score_prec != VBGS_FP64 && p->exact == 1 && p->n_max > ((int64_t)1 << 23)) {
+    if (why) *why = "exact MFMA mode supports n_max <= 2^23 (the 128 candidate slots per point are indexed in int32)";
     return VBGS_ERR_SHAPE;
   }
   if (p->exact != 0 && p->exact != 1) {
@@ -288,6 +288,7 @@ Layout make_layout(const vbgs_params& p) {
   L.bcost = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.bcode = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.border = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
+  L.bprev = take(8);
   // learned proposal
   const bool pr = p.proposal == 1;
   const int C = p.C > 0 ? p.C : 32;

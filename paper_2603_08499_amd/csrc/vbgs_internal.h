@@ -24,7 +24,7 @@ constexpr int PT = 64;        // points per LDS tile (pass 2)
 constexpr int P1_PB = 4;      // 16-point blocks per wave in pass 1
 constexpr int P1_PTS = 4 * P1_PB * 16;  // points per pass-1 workgroup (4 waves)
 constexpr int MOM_BLOCKS = 256;
-constexpr int CS = 16;        // candidate slots per (point, lane group) in the exact sweep
+constexpr int CS = 32;        // candidate slots per (point, lane group) in the exact sweep
 constexpr float DEAD_C0 = -1.0e30f;     // constant slot of padding components
 
 // device flag bits
@@ -118,11 +118,12 @@ struct Layout {
   int nsplit_max;
   // spatial ordering (culled exact sweep)
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
-  size_t bcost, bcode, border;
+  size_t bcost, bcode, border;  // per 64-point block of the culled sweep: measured time, Morton code
+                                // of its first point, dispatch order
+  size_t bprev;                 // number of blocks of the last sweep (int64)
   size_t elbo_part;  // 2 x 256 partial sums of the ELBO reduction
   size_t scr_part, scr_gate;  // screen choice: 2 x 256 partial norm sums, two gate flags
-  size_t rx_tmp, rx_hist, rx_off, rx_part;  // radix sort: ping-pong keys, digit histograms, scan  // per 64-point block: measured sweep time, its first point's Morton
-                                // code at that time, dispatch order
+  size_t rx_tmp, rx_hist, rx_off, rx_part;  // radix sort: ping-pong keys, digit histograms, scan
   // learned proposal (workspace)
   size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
       p_tdh2, p_tdp1, p_th2b, p_th2T, p_tloss, p_grads;
@@ -347,6 +348,7 @@ struct EArgs {
   float* bcost;               // culled sweep: per 64-point block, the duration of its last sweep
   uint32_t* bcode;            // and the Morton code of its first point then
   int32_t* border;            // culled sweep: dispatch position -> block (costliest first per XCD)
+  int64_t* bprev;             // culled sweep: blocks of the last launch (their bcost / bcode entries)
   int64_t nb_cap;             // capacity of bcost / border
   double* scr_part;           // screen choice: partial sums of the row and feature norms
   int32_t* scr_gate;          // screen choice: [run split BF16, run FP32]
