@@ -133,6 +133,22 @@ def test_invariants_c1():
     assert np.allclose(Rr.sum(1), 1.0, atol=1e-12)
 
 
+def test_materialised_statistics_equal_the_fused_contraction():
+    """Alg. 2 (materialise R, then reduce) and Alg. 3 / Eq. (fused_contr) (Delta S = R^T S_u with the
+    per-point statistics S_u = [1, x, x x^T]) give the same N, S1, S2: here the N x K responsibilities
+    from the explicit-inverse scores times the per-point statistics, against the oracle's sums."""
+    X, pr, p = _prob(120, 7, 4, 17)
+    q = _perturbed_posterior(p, 4)
+    Xd = X.astype(np.float64)
+    Rr, _ = brute.responsibilities(Xd, q)                 # materialised N x K
+    D = Xd.shape[1]
+    iu = np.triu_indices(D)
+    Su = np.concatenate([np.ones((len(Xd), 1)), Xd, (Xd[:, :, None] * Xd[:, None, :])[:, iu[0], iu[1]]], 1)
+    fused = Rr.T @ Su                                      # K x (1 + D + D(D+1)/2)
+    got = R.stats(Xd, q, R.lse(Xd, q)).packed()
+    assert np.allclose(got, fused, rtol=1e-10, atol=1e-12)
+
+
 def test_elbo_monotone_c1():
     X = scenes.c1_frame()
     pr = scenes.c1_prior(X)
