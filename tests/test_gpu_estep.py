@@ -339,3 +339,29 @@ def test_auto_screen_choice(dev):
         assert cnt["screen"] == want
         assert dl < 2e-6 and es < 1e-5
         m.close()
+
+
+@gpu
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_plain_tier_error_white_noise_vs_scene(dev, prec):
+    """The precision search's input (white noise of c3's shapes) against scene points: the plain
+    tier's statistics error, each against the oracle, on 2048 points of each with all K = 100000
+    components of the c3 prior."""
+    scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
+    X0 = scenes.c3_frame(0, scene=scene)
+    pr = scenes.c3_prior(X0)
+    p = R.NW.from_prior(pr)
+    errs = {}
+    for name, X in (("scene", np.ascontiguousarray(X0[150000:152048])),
+                    ("white", np.ascontiguousarray(scenes.white_frame(0)[:2048]))):
+        m = _model(dev, pr, X.shape[0], prec, exact=False)
+        _, st = m.estep_stats(torch.from_numpy(X).to(dev))
+        torch.cuda.synchronize()
+        e = R.expectations(p)
+        ls = R.lse(X, p, e)
+        errs[name] = _stat_err(R.stats(X, p, ls, e, scatter=False).packed(), st.cpu().numpy(), 6)
+        m.close()
+    print(prec, "plain-tier statistics relerr: scene %.3e white %.3e" % (errs["scene"], errs["white"]))
+    # measured: white noise understates the scene error (about 4x for both tiers), so a tolerance met
+    # on white noise does not carry over to scenes; white noise never shows the larger error here
+    assert 0.0 < errs["white"] <= errs["scene"]
