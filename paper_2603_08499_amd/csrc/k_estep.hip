@@ -1105,22 +1105,42 @@ __device__ __forceinline__ float point_row_d2(const RowBound& r, const float* x3
   return d2;
 }
 
-// call f(k) for every component whose bound with x reaches thr (culled) or for every component
+// call f(k) for every component whose bound with x reaches thr (culled) or for every component.
+// Culled: each wave tests 64 tiles at a time (lane = tile), then the rows of the tiles that pass,
+// two tiles at a time (lane = row), so that the row-bound loads of a tile are issued together.
+// Needs a workgroup of whole waves.
 template <int DT, typename F>
 __device__ __forceinline__ void over_rows(const EArgs& a, const float* x, float thr, F&& f) {
+  static_assert(CT == 64, "a tile's rows are one wave's lanes");
   if (a.cull) {
     float x3[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) x3[i] = i < DT && i < a.nsp ? x[i] : 0.0f;
     const int64_t ntiles = a.Kpad / CT;
-    for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
-      const TileInfo ti = a.tinfo[t];
-      if (ti.G - ti.Lam * point_tile_d2(ti, x3) < thr) continue;
-      for (int r = 0; r < CT; ++r) {
-        const int64_t row = t * CT + r;
-        if (row >= a.K) break;
-        const RowBound rb = a.rowb[row];
-        if (rb.G - rb.Lam * point_row_d2(rb, x3) >= thr) f((int64_t)a.corder[row]);
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    auto row_test = [&](int64_t row, const RowBound& rb) {
+      if (row < a.K && rb.G - rb.Lam * point_row_d2(rb, x3) >= thr) f((int64_t)a.corder[row]);
+    };
+    for (int64_t base = (int64_t)(threadIdx.x >> 6) * 64; base < ntiles; base += (int64_t)nw * 64) {
+      const int64_t t = base + lane;
+      bool pass = false;
+      if (t < ntiles) {
+        const TileInfo ti = a.tinfo[t];
+        pass = ti.G - ti.Lam * point_tile_d2(ti, x3) >= thr;
+      }
+      unsigned long long pm = __ballot(pass);
+      while (pm) {
+        const int i1 = __ffsll((long long)pm) - 1;
+        pm &= pm - 1ull;
+        const int i2 = pm ? __ffsll((long long)pm) - 1 : -1;
+        if (pm) pm &= pm - 1ull;
+        const int64_t r1 = (base + i1) * CT + lane;
+        const int64_t r2 = i2 >= 0 ? (base + i2) * CT + lane : -1;
+        RowBound b1{}, b2{};
+        if (r1 < a.K) b1 = a.rowb[r1];
+        if (r2 >= 0 && r2 < a.K) b2 = a.rowb[r2];
+        row_test(r1, b1);
+        if (r2 >= 0) row_test(r2, b2);
       }
     }
   } else {
@@ -1460,41 +1480,76 @@ __global__ __launch_bounds__(64) void k_comp_stats_heavy(const EArgs a) {
   }
 }
 
-// CG lanes per component (the others: k_comp_stats_heavy): lane j takes pairs j, j + CG, ..., then
-// the lanes' 128-bit sums are added (the shorter chains hide the gathers' latency)
-constexpr int CG = 4;
+// One group of SG lanes per component with at most HEAVY pairs (the others: k_comp_stats_heavy).
+// The pairs are taken SG at a time: each lane scores one pair (its responsibility r and scaled
+// offset u) into LDS, then lane f < F adds feature f (r, r u_i or r u_i u_j) of every pair of the
+// chunk into its own 128-bit sum, so no lane holds more than one sum.
+constexpr int SG = 32;
 
 template <int DT>
-__global__ __launch_bounds__(128) void k_comp_stats(const EArgs a) {
+__global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
   constexpr int F = 1 + DT + DT * (DT + 1) / 2;
-  const int64_t k = ((int64_t)blockIdx.x * 128 + threadIdx.x) / CG;
-  const int j = threadIdx.x % CG;
-  const bool val = k < a.K && a.coffset[k + 1] - a.coffset[k] <= HEAVY;
-  double is[DT];
+  constexpr int R = 1 + DT;  // per pair: r, u[DT]
+  __shared__ double buf[256 / SG][SG * R];
+  const int grp = threadIdx.x / SG, l = threadIdx.x % SG;
+  const int64_t k = (int64_t)blockIdx.x * (256 / SG) + grp;
+  const bool val = k < a.K && a.coffset[k + 1] - a.coffset[k] <= HEAVY;  // uniform over the group
+  // the feature this lane sums: r (l = 0), r u_i (l = 1 + i), r u_i u_j (i <= j, row-major)
+  int fi = l >= 1 && l <= DT ? l - 1 : -1, fj = -1;
+  {
+    int o = 1 + DT;
 #pragma unroll
-  for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
-  Fx128 acc[F];
+    for (int i = 0; i < DT; ++i)
 #pragma unroll
-  for (int f = 0; f < F; ++f) {  // lane 0 of the group starts from the overflowed points' contributions
-    acc[f].lo = val && j == 0 ? a.fx[(k * FP + f) * 2] : 0ull;
-    acc[f].hi = val && j == 0 ? (long long)a.fx[(k * FP + f) * 2 + 1] : 0ll;
+      for (int j = i; j < DT; ++j, ++o)
+        if (o == l) {
+          fi = i;
+          fj = j;
+        }
   }
+  const bool mine = val && l < F;
+  Fx128 acc;  // starts from the overflowed points' contributions
+  acc.lo = mine ? a.fx[(k * FP + l) * 2] : 0ull;
+  acc.hi = mine ? (long long)a.fx[(k * FP + l) * 2 + 1] : 0ll;
   if (val) {
+    double is[DT];
+#pragma unroll
+    for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
     const double* row = a.direct + k * a.dts;
+    double* rec = buf[grp];
     const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
-    for (int32_t e = e0 + j; e < e1; e += CG) comp_pair_acc<DT>(a, row, a.ent_n[e], is, acc);
-  }
+    for (int32_t c0 = e0; c0 < e1; c0 += SG) {
+      const int m = min(SG, e1 - c0);
+      if (l < m) {
+        const int64_t n = a.ent_n[c0 + l];
+        double d[DT];
+        const double s2 = direct_score2_dt<DT>(row, a.X + n * DT, d);
+        rec[l * R] = exp2(s2 - a.lse2[n]);
 #pragma unroll
-  for (int f = 0; f < F; ++f)
-#pragma unroll
-    for (int off = CG / 2; off > 0; off >>= 1) {
-      const unsigned long long lo2 = __shfl_xor(acc[f].lo, off);
-      const long long hi2 = __shfl_xor(acc[f].hi, off);
-      const unsigned long long lo = acc[f].lo + lo2;
-      acc[f].hi += hi2 + (lo < lo2 ? 1 : 0);
-      acc[f].lo = lo;
+        for (int i = 0; i < DT; ++i) rec[l * R + 1 + i] = d[i] * is[i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (l < F)
+        for (int q = 0; q < m; ++q) {
+          const double* rq = rec + q * R;
+          double v = rq[0];
+          if (fi >= 0) v = v * rq[1 + fi];
+          if (fj >= 0) v = v * rq[1 + fj];
+          fx_acc(acc, v);
+        }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-  if (val && j == 0) comp_stats_out<DT>(a, k, acc);
+  }
+  if (mine) {  // fixed point -> FP64, undo the scaling; raw coordinates centred at m_k
+    double v = (double)acc.hi + (double)acc.lo * 5.42101086242752217e-20;
+    if (fi >= 0) v = v * a.frame->s[fi];
+    if (fj >= 0) v = v * a.frame->s[fj];
+    a.spart[k * FP + l] = v;
+  }
 }
 
 __global__ void k_zero_i32(int32_t* p, int64_t n, const int32_t* gate) {
@@ -1743,7 +1798,7 @@ hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) 
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part,   \
                        a.coffset);                                                                       \
     hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                          \
-    hipLaunchKernelGGL(k_comp_stats<DD>, dim3((unsigned)((a.K * CG + 127) / 128)), dim3(128), 0, s, a); \
+    hipLaunchKernelGGL(k_comp_stats<DD>, dim3((unsigned)((a.K + 256 / SG - 1) / (256 / SG))), dim3(256), 0, s, a); \
     hipLaunchKernelGGL(k_comp_stats_heavy<DD>, dim3((unsigned)((a.K + 63) / 64)), dim3(64), 0, s, a); \
     break;
       VB_ST(1) VB_ST(2) VB_ST(3) VB_ST(4) VB_ST(5) VB_ST(6)
