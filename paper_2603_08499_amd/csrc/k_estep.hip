@@ -1400,83 +1400,95 @@ __device__ __forceinline__ void fx_acc(Fx128& a, double v) {
   a.hi += (long long)hi_d + (a.lo < lo ? 1 : 0);
 }
 
-// A component with more than HEAVY kept pairs is summed by a whole wave (k_comp_stats_heavy), so
-// that no thread here walks a long list; 128-bit integer sums do not depend on how the pairs are
+// A component with more than HEAVY kept pairs is summed by a whole workgroup (k_comp_stats_heavy),
+// so that no lane group walks a long list; 128-bit integer sums do not depend on how the pairs are
 // split among lanes.
-constexpr int HEAVY = 64;
+constexpr int HEAVY = 4096;
+constexpr int SG = 32;  // lanes per component group in the statistics kernels
 
+// Components with more than HEAVY pairs, one workgroup of 256 lanes per component (the workgroup
+// of components [64 b, 64 b + 64) takes its heavy ones in turn). Each chunk of 256 pairs is scored
+// one pair per lane into LDS; then group j of SG lanes takes pairs [SG j, SG j + SG) of the chunk,
+// lane f adding feature f into its 128-bit sum; the groups' sums of each feature are added last.
 template <int DT>
-__device__ __forceinline__ void comp_pair_acc(const EArgs& a, const double* row, int64_t n, const double* is,
-                                              Fx128* acc) {
-  double d[DT];
-  const double s2 = direct_score2_dt<DT>(row, a.X + n * DT, d);
-  const double r = exp2(s2 - a.lse2[n]);
-  fx_acc(acc[0], r);
-  double u[DT];
-#pragma unroll
-  for (int i = 0; i < DT; ++i) {
-    u[i] = d[i] * is[i];
-    fx_acc(acc[1 + i], r * u[i]);
-  }
-  int o = 1 + DT;
-#pragma unroll
-  for (int i = 0; i < DT; ++i)
-#pragma unroll
-    for (int j = i; j < DT; ++j, ++o) fx_acc(acc[o], r * u[i] * u[j]);
-}
-
-// fixed point -> FP64, undo the power-of-two scaling; raw coordinates centred at m_k
-template <int DT>
-__device__ __forceinline__ void comp_stats_out(const EArgs& a, int64_t k, const Fx128* acc) {
-  double* out = a.spart + k * FP;
-  out[0] = (double)acc[0].hi + (double)acc[0].lo * 5.42101086242752217e-20;
-#pragma unroll
-  for (int i = 0; i < DT; ++i)
-    out[1 + i] = ((double)acc[1 + i].hi + (double)acc[1 + i].lo * 5.42101086242752217e-20) * a.frame->s[i];
-  int o = 1 + DT;
-#pragma unroll
-  for (int i = 0; i < DT; ++i)
-#pragma unroll
-    for (int j = i; j < DT; ++j, ++o)
-      out[o] = ((double)acc[o].hi + (double)acc[o].lo * 5.42101086242752217e-20) * a.frame->s[i] * a.frame->s[j];
-}
-
-// one wave per 64 components; each of them with more than HEAVY pairs is summed by the whole wave
-// (lanes take every 64th pair, then a 128-bit wave sum)
-template <int DT>
-__global__ __launch_bounds__(64) void k_comp_stats_heavy(const EArgs a) {
+__global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
   constexpr int F = 1 + DT + DT * (DT + 1) / 2;
-  const int lane = threadIdx.x;
-  const int64_t kl = (int64_t)blockIdx.x * 64 + lane;
-  const bool heavy = kl < a.K && a.coffset[kl + 1] - a.coffset[kl] > HEAVY;
-  unsigned long long hm = __ballot(heavy);
-  if (hm == 0ull) return;
+  constexpr int R = 1 + DT, NG = 256 / SG;
+  __shared__ double buf[256 * R];
+  __shared__ Fx128 part[NG][SG];
+  __shared__ int32_t heavy[64];
+  __shared__ int nheavy;
+  const int tid = threadIdx.x, grp = tid / SG, l = tid % SG;
+  if (tid == 0) nheavy = 0;
+  __syncthreads();
+  if (tid < 64) {
+    const int64_t k = (int64_t)blockIdx.x * 64 + tid;
+    if (k < a.K && a.coffset[k + 1] - a.coffset[k] > HEAVY) heavy[atomicAdd(&nheavy, 1)] = (int32_t)k;
+  }
+  __syncthreads();
+  const int nh = nheavy;
+  if (nh == 0) return;
+  int fi = l >= 1 && l <= DT ? l - 1 : -1, fj = -1;
+  {
+    int o = 1 + DT;
+#pragma unroll
+    for (int i = 0; i < DT; ++i)
+#pragma unroll
+      for (int j = i; j < DT; ++j, ++o)
+        if (o == l) {
+          fi = i;
+          fj = j;
+        }
+  }
   double is[DT];
 #pragma unroll
   for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
-  while (hm) {
-    const int q = __ffsll((long long)hm) - 1;
-    hm &= hm - 1ull;
-    const int64_t k = (int64_t)blockIdx.x * 64 + q;
-    const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
-    Fx128 acc[F];
-#pragma unroll
-    for (int f = 0; f < F; ++f) {  // lane 0 starts from the overflowed points' contributions
-      acc[f].lo = lane == 0 ? a.fx[(k * FP + f) * 2] : 0ull;
-      acc[f].hi = lane == 0 ? (long long)a.fx[(k * FP + f) * 2 + 1] : 0ll;
-    }
+  for (int h = 0; h < nh; ++h) {
+    const int64_t k = heavy[h];
+    Fx128 acc;  // group 0 starts from the overflowed points' contributions
+    acc.lo = grp == 0 && l < F ? a.fx[(k * FP + l) * 2] : 0ull;
+    acc.hi = grp == 0 && l < F ? (long long)a.fx[(k * FP + l) * 2 + 1] : 0ll;
     const double* row = a.direct + k * a.dts;
-    for (int32_t e = e0 + lane; e < e1; e += 64) comp_pair_acc<DT>(a, row, a.ent_n[e], is, acc);
+    const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
+    for (int32_t c0 = e0; c0 < e1; c0 += 256) {
+      const int m = min(256, e1 - c0);
+      if (tid < m) {
+        const int64_t n = a.ent_n[c0 + tid];
+        double d[DT];
+        const double s2 = direct_score2_dt<DT>(row, a.X + n * DT, d);
+        buf[tid * R] = exp2(s2 - a.lse2[n]);
 #pragma unroll
-    for (int f = 0; f < F; ++f)
-      for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long lo2 = __shfl_xor(acc[f].lo, off);
-        const long long hi2 = __shfl_xor(acc[f].hi, off);
-        const unsigned long long lo = acc[f].lo + lo2;
-        acc[f].hi += hi2 + (lo < lo2 ? 1 : 0);
-        acc[f].lo = lo;
+        for (int i = 0; i < DT; ++i) buf[tid * R + 1 + i] = d[i] * is[i];
       }
-    if (lane == 0) comp_stats_out<DT>(a, k, acc);
+      __syncthreads();
+      if (l < F) {
+        const int q1 = min(m, grp * SG + SG);
+        for (int q = grp * SG; q < q1; ++q) {
+          const double* rq = buf + q * R;
+          double v = rq[0];
+          if (fi >= 0) v = v * rq[1 + fi];
+          if (fj >= 0) v = v * rq[1 + fj];
+          fx_acc(acc, v);
+        }
+      }
+      __syncthreads();
+    }
+    part[grp][l] = acc;
+    __syncthreads();
+    if (grp == 0 && l < F) {
+#pragma unroll
+      for (int j = 1; j < NG; ++j) {
+        const Fx128 o = part[j][l];
+        const unsigned long long lo = acc.lo + o.lo;
+        acc.hi += o.hi + (lo < o.lo ? 1 : 0);
+        acc.lo = lo;
+      }
+      double v = (double)acc.hi + (double)acc.lo * 5.42101086242752217e-20;
+      if (fi >= 0) v = v * a.frame->s[fi];
+      if (fj >= 0) v = v * a.frame->s[fj];
+      a.spart[k * FP + l] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -1484,8 +1496,6 @@ __global__ __launch_bounds__(64) void k_comp_stats_heavy(const EArgs a) {
 // The pairs are taken SG at a time: each lane scores one pair (its responsibility r and scaled
 // offset u) into LDS, then lane f < F adds feature f (r, r u_i or r u_i u_j) of every pair of the
 // chunk into its own 128-bit sum, so no lane holds more than one sum.
-constexpr int SG = 32;
-
 template <int DT>
 __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
   constexpr int F = 1 + DT + DT * (DT + 1) / 2;
@@ -1799,7 +1809,7 @@ hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) 
                        a.coffset);                                                                       \
     hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                          \
     hipLaunchKernelGGL(k_comp_stats<DD>, dim3((unsigned)((a.K + 256 / SG - 1) / (256 / SG))), dim3(256), 0, s, a); \
-    hipLaunchKernelGGL(k_comp_stats_heavy<DD>, dim3((unsigned)((a.K + 63) / 64)), dim3(64), 0, s, a); \
+    hipLaunchKernelGGL(k_comp_stats_heavy<DD>, dim3((unsigned)((a.K + 63) / 64)), dim3(256), 0, s, a); \
     break;
       VB_ST(1) VB_ST(2) VB_ST(3) VB_ST(4) VB_ST(5) VB_ST(6)
 #undef VB_ST

@@ -56,7 +56,8 @@ def _set(m, which, nw):
 
 @gpu
 @pytest.mark.parametrize("prec,exact", EXACT_TIERS)
-@pytest.mark.parametrize("N,K,D", [(3001, 301, 6), (777, 90, 5), (1000, 1, 6), (1500, 120, 2)])
+# (9000, 2, 6): components with more than 4096 kept pairs, summed by a whole workgroup each
+@pytest.mark.parametrize("N,K,D", [(3001, 301, 6), (777, 90, 5), (1000, 1, 6), (1500, 120, 2), (9000, 2, 6)])
 def test_estep_parity_exact(dev, prec, exact, N, K, D):
     print("case", prec, N, K, D, flush=True)
     X, pr = scenes.random_problem(N, K, D, seed=N + K)
