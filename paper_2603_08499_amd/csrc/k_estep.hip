@@ -1371,11 +1371,19 @@ hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t
 __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= a.N || a.cand_n[p * 4] < 0) return;
+  // eight pairs at a time, so that their cursor atomics are in flight together
   for (int g = 0; g < 4; ++g) {
     const int cnt = a.cand_n[p * 4 + g];
-    for (int j = 0; j < cnt; ++j) {
-      const int32_t k = a.cand_k[(p * 4 + g) * CS + j];
-      if (k >= 0) a.ent_n[a.coffset[k] + atomicAdd(&a.ccursor[k], 1)] = (int32_t)p;
+    const int32_t* ck = a.cand_k + (p * 4 + g) * CS;
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
+      int32_t k[8], pos[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) k[u] = j0 + u < cnt ? ck[j0 + u] : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pos[u] = k[u] >= 0 ? a.coffset[k[u]] + atomicAdd(&a.ccursor[k[u]], 1) : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k[u] >= 0) a.ent_n[pos[u]] = (int32_t)p;
     }
   }
 }
