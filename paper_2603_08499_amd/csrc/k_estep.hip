@@ -657,22 +657,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       for (int q = 0; q < 8; ++q) r |= q < upto && t >= cq[q] - 1 && t <= cq[q] + 1;
       return r;
     };
+    // the distinct centres first, then their neighbours c_q +- 1 (all distinct, inside the table)
     int nseed = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      bool dup = false;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) dup |= r < q && cq[r] == cq[q];
+      if (!dup) {
+        if (lane == 0) seeds[w][nseed] = cq[q];
+        ++nseed;
+      }
+    }
+    const int ncen = nseed;
 #pragma unroll
     for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int d = -1; d <= 1; ++d) {
+      for (int d = -1; d <= 1; d += 2) {
         const int64_t t = (int64_t)cq[q] + d;
-        if (t >= 0 && t < ntiles && !near_centre(t, q)) {
+        bool centre = false;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) centre |= t == cq[r];
+        if (t >= 0 && t < ntiles && !centre && !near_centre(t, q)) {
           if (lane == 0) seeds[w][nseed] = (int32_t)t;
           ++nseed;
         }
       }
     __builtin_amdgcn_wave_barrier();
-    for (int i = 0; i < 2 * nseed; ++i) {
-      const int64_t t = __builtin_amdgcn_readfirstlane(seeds[w][i % nseed]);
-      const int64_t tn = i + 1 < 2 * nseed ? (int64_t)__builtin_amdgcn_readfirstlane(seeds[w][(i + 1) % nseed]) : -1;
-      screen_tile<P>(a, S, t, tn, i > 0, i >= nseed, lane, 0xFu, mv, pid, tks[w], stg);
+    // a pilot over the centres raises M without recording; then every seed is screened, recording
+    const int npil = ncen, nst = npil + nseed;
+    auto seed_at = [&](int i) { return (int64_t)__builtin_amdgcn_readfirstlane(seeds[w][i < npil ? i : i - npil]); };
+    for (int i = 0; i < nst; ++i) {
+      const int64_t tn = i + 1 < nst ? seed_at(i + 1) : -1;
+      screen_tile<P>(a, S, seed_at(i), tn, i > 0, i >= npil, lane, 0xFu, mv, pid, tks[w], stg);
       share_m<P>(S, lane, mv);
     }
     const float margin = a.T2 + 1.0f;
