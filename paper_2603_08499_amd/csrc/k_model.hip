@@ -700,15 +700,39 @@ hipError_t launch_render_marginal(const DevPtrs& model, const DevPtrs& sp, doubl
 }
 
 // mean squared error of two images in [0, 1] on the 0..255 scale (values clamped to [0, 1]) and
-// the PSNR 10 log10(255^2 / MSE) of Sec. 5.1; one workgroup, fixed summation order
+// the PSNR 10 log10(255^2 / MSE) of Sec. 5.1; one workgroup: each thread sums a fixed set of
+// values in a fixed order, then a fixed tree (deterministic)
 __global__ __launch_bounds__(1024) void k_psnr(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
                                                double* __restrict__ out) {
   __shared__ double red[1024];
+  auto sq = [](float x, float y) {
+    const double d = 255.0 * ((double)fminf(fmaxf(x, 0.0f), 1.0f) - (double)fminf(fmaxf(y, 0.0f), 1.0f));
+    return d * d;
+  };
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
-    const double d = 255.0 * ((double)fminf(fmaxf(a[i], 0.0f), 1.0f) - (double)fminf(fmaxf(b[i], 0.0f), 1.0f));
-    acc = fma(d, d, acc);
+  int64_t i0 = 0;  // values before i0 are taken four at a time (16-byte loads, eight in flight)
+  if ((((uintptr_t)a | (uintptr_t)b) & 15) == 0) {
+    const float4* a4 = reinterpret_cast<const float4*>(a);
+    const float4* b4 = reinterpret_cast<const float4*>(b);
+    const int64_t n4 = n / 4;
+    int64_t j = threadIdx.x;
+    for (; j + 3 * 1024 < n4; j += 4 * 1024) {
+      float4 x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = a4[j + u * 1024];
+        y[u] = b4[j + u * 1024];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += sq(x[u].x, y[u].x) + sq(x[u].y, y[u].y) + sq(x[u].z, y[u].z) + sq(x[u].w, y[u].w);
+    }
+    for (; j < n4; j += 1024) {
+      const float4 x = a4[j], y = b4[j];
+      acc += sq(x.x, y.x) + sq(x.y, y.y) + sq(x.z, y.z) + sq(x.w, y.w);
+    }
+    i0 = 4 * n4;
   }
+  for (int64_t i = i0 + threadIdx.x; i < n; i += 1024) acc += sq(a[i], b[i]);
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {

@@ -149,6 +149,11 @@ def test_psnr_kernel(dev):
     assert abs(out[0] - mse) <= 1e-12 * mse and abs(out[1] - p) < 1e-10
     same = P.psnr(torch.from_numpy(b).to(dev), torch.from_numpy(b).to(dev)).cpu().numpy()
     assert same[0] == 0.0 and np.isinf(same[1])
+    # inputs not 16-byte aligned take the one-value-at-a-time path
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    off = P.psnr(ta[1:], tb[1:]).cpu().numpy()
+    mse1, p1 = RR.psnr(a[1:], b[1:])
+    assert abs(off[0] - mse1) <= 1e-12 * mse1 and abs(off[1] - p1) < 1e-10
 
 
 @gpu
