@@ -71,10 +71,16 @@ typedef enum {
   VBGS_FP32 = 1,    /* v_mfma_f32_16x16x4_f32, FP32 accumulation */
   VBGS_BF16 = 2,    /* v_mfma_f32_16x16x32_bf16, FP32 accumulation */
   VBGS_BF16X3 = 3,  /* split BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation */
-  VBGS_AUTO = 4     /* exact = 1 only: per E-step, the split-BF16 screen unless its error bound
+  VBGS_AUTO = 4,    /* exact = 1 only: per E-step, the split-BF16 screen unless its error bound
                        (2^-12 |c| |phi| for the mean coefficient-row and feature norms) exceeds
                        32 log2 units, else the FP32 screen; the choice is made on the device and
                        reported by vbgs_counters (the results are exact either way) */
+  VBGS_FP8 = 5      /* exact = 0 only (a plain tier whose error is reported): every feature and
+                       coefficient row scaled by a power of two so that its largest magnitude lies
+                       in [224, 448], rounded to OCP e4m3 (nearest even), v_mfma_f32_16x16x32_fp8_fp8
+                       with FP32 accumulation, the two scales undone on the FP32 scores. As a screen
+                       its error bound (~2^-3 |c| |phi|) would admit nearly every pair, so the exact
+                       mode does not take it (VBGS_ERR_UNSUPPORTED) */
 } vbgs_prec;
 
 typedef struct {

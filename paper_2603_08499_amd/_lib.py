@@ -13,7 +13,7 @@ STATUS = {0: "VBGS_OK", -1: "VBGS_ERR_ARG", -2: "VBGS_ERR_SHAPE", -3: "VBGS_ERR_
 NPHASE = 10
 PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "proposal", "sort", "lse"]
 H = 128
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4, "fp8": 5}
 
 
 class Params(ctypes.Structure):

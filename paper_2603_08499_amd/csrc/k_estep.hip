@@ -52,6 +52,17 @@ template <>
 struct Opnd<VBGS_BF16X3> {
   bf16x8 h, l;
 };
+template <>
+struct Opnd<VBGS_FP8> {
+  long q;  // eight e4m3 bytes, slots 8 g .. 8 g + 7
+};
+
+// FP8 tier: this lane's eight e4m3 slots of a row
+__device__ __forceinline__ Opnd<VBGS_FP8> load_op8(const uint8_t* row, int g) {
+  Opnd<VBGS_FP8> o;
+  o.q = *reinterpret_cast<const long*>(row + 8 * g);
+  return o;
+}
 
 template <int P>
 __device__ __forceinline__ Opnd<P> load_op(const float* f32row, const uint16_t* hrow, const uint16_t* lrow,
@@ -75,6 +86,8 @@ __device__ __forceinline__ Opnd<P> zero_op() {
   if constexpr (P == VBGS_FP32) {
     o.a = f32x4{0.f, 0.f, 0.f, 0.f};
     o.b = o.a;
+  } else if constexpr (P == VBGS_FP8) {
+    o.q = 0;
   } else {
     for (int i = 0; i < 8; ++i) o.h[i] = (__bf16)0.0f;
     if constexpr (P == VBGS_BF16X3) o.l = o.h;
@@ -111,6 +124,8 @@ __device__ __forceinline__ f32x4 mfma_scores(const Opnd<P>& A, const Opnd<P>& B)
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.b[3], B.b[3], acc, 0, 0, 0);
   } else if constexpr (P == VBGS_BF16) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.h, B.h, acc, 0, 0, 0);
+  } else if constexpr (P == VBGS_FP8) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(A.q, B.q, acc, 0, 0, 0);
   } else {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.h, B.l, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.l, B.h, acc, 0, 0, 0);
@@ -169,8 +184,10 @@ __device__ __noinline__ int evict_candidates(int32_t* __restrict__ ck, float* __
 template <int P>
 struct __attribute__((aligned(16))) CTile {
   float c32[P == VBGS_FP32 ? CT : 1][FP];
-  uint16_t h[P == VBGS_FP32 ? 1 : CT][FP];
+  uint16_t h[P == VBGS_FP32 || P == VBGS_FP8 ? 1 : CT][FP];
   uint16_t l[P == VBGS_BF16X3 ? CT : 1][FP];
+  uint8_t q8[P == VBGS_FP8 ? CT : 1][FP];
+  float cs8[P == VBGS_FP8 ? CT : 4];
   float nc[CT];
 };
 
@@ -179,7 +196,7 @@ struct __attribute__((aligned(16))) CTile {
 template <int P>
 struct TileRegs {
   uint4 v[P == VBGS_FP32 ? 2 : (P == VBGS_BF16X3 ? 2 : 1)];
-  uint4 nc;
+  uint4 nc, s8;
 };
 
 template <int P>
@@ -189,6 +206,9 @@ __device__ __forceinline__ void tile_fetch(TileRegs<P>& R, const EArgs& a, int64
     const uint4* src = reinterpret_cast<const uint4*>(a.c32 + k0 * FP);
     R.v[0] = src[t];
     R.v[1] = src[t + 256];
+  } else if constexpr (P == VBGS_FP8) {  // 64 rows x 32 B = 128 x 16 B, scales 16 x 16 B
+    if (t < CT * FP / 16) R.v[0] = reinterpret_cast<const uint4*>(a.c8 + k0 * FP)[t];
+    if (t < CT / 4) R.s8 = reinterpret_cast<const uint4*>(a.cs8 + k0)[t];
   } else {
     R.v[0] = reinterpret_cast<const uint4*>(a.ch + k0 * FP)[t];
     if constexpr (P == VBGS_BF16X3) R.v[1] = reinterpret_cast<const uint4*>(a.cl + k0 * FP)[t];
@@ -202,6 +222,9 @@ __device__ __forceinline__ void tile_store(CTile<P>& T, const TileRegs<P>& R) {
   if constexpr (P == VBGS_FP32) {
     reinterpret_cast<uint4*>(&T.c32[0][0])[t] = R.v[0];
     reinterpret_cast<uint4*>(&T.c32[0][0])[t + 256] = R.v[1];
+  } else if constexpr (P == VBGS_FP8) {
+    if (t < CT * FP / 16) reinterpret_cast<uint4*>(&T.q8[0][0])[t] = R.v[0];
+    if (t < CT / 4) reinterpret_cast<uint4*>(T.cs8)[t] = R.s8;
   } else {
     reinterpret_cast<uint4*>(&T.h[0][0])[t] = R.v[0];
     if constexpr (P == VBGS_BF16X3) reinterpret_cast<uint4*>(&T.l[0][0])[t] = R.v[1];
@@ -236,14 +259,21 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
 
   Opnd<P> B[P1_PB];
   float nphE[P1_PB], M[P1_PB], ls[P1_PB];
+  float psc[P1_PB];  // FP8 tier: factor undoing the point row's scaling
   int cn[P1_PB];
   bool val[P1_PB], ovf[P1_PB];
 #pragma unroll
   for (int b = 0; b < P1_PB; ++b) {
     const int64_t p = p0 + 16 * b + c;
     val[b] = p < a.N;
+    psc[b] = 1.0f;
     if (val[b]) {
-      B[b] = load_op<P>(a.phi32 + p * FP, a.phih + p * FP, a.phil + p * FP, g);
+      if constexpr (P == VBGS_FP8) {
+        B[b] = load_op8(a.phi8 + p * FP, g);
+        psc[b] = a.phis[p];
+      } else {
+        B[b] = load_op<P>(a.phi32 + p * FP, a.phih + p * FP, a.phil + p * FP, g);
+      }
       nphE[b] = a.eps * a.nphi[p];
     } else {
       B[b] = zero_op<P>();
@@ -268,13 +298,24 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
 #pragma unroll
     for (int cb = 0; cb < CT / 16; ++cb) {
       const int r = cb * 16 + c;
-      const Opnd<P> A = load_op<P>(&Tc.c32[P == VBGS_FP32 ? r : 0][0], &Tc.h[P == VBGS_FP32 ? 0 : r][0],
-                                   &Tc.l[P == VBGS_BF16X3 ? r : 0][0], g);
+      Opnd<P> A;
+      f32x4 csc = {1.f, 1.f, 1.f, 1.f};  // FP8 tier: factors undoing rows cb * 16 + 4 g + i
+      if constexpr (P == VBGS_FP8) {
+        A = load_op8(&Tc.q8[r][0], g);
+        csc = *reinterpret_cast<const f32x4*>(&Tc.cs8[cb * 16 + 4 * g]);
+      } else {
+        A = load_op<P>(&Tc.c32[P == VBGS_FP32 ? r : 0][0], &Tc.h[P == VBGS_FP32 ? 0 : r][0],
+                       &Tc.l[P == VBGS_BF16X3 ? r : 0][0], g);
+      }
       const f32x4 nc4 = *reinterpret_cast<const f32x4*>(&Tc.nc[cb * 16 + 4 * g]);
       const float ncm = fmaxf(fmaxf(nc4[0], nc4[1]), fmaxf(nc4[2], nc4[3]));
 #pragma unroll
       for (int b = 0; b < P1_PB; ++b) {
-        const f32x4 s = mfma_scores<P>(A, B[b]);
+        f32x4 s = mfma_scores<P>(A, B[b]);
+        if constexpr (P == VBGS_FP8) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s[i] = s[i] * csc[i] * psc[b];
+        }
         const float mx = fmaxf(fmaxf(s[0], s[1]), fmaxf(s[2], s[3]));
         if constexpr (EXACT) {
           // one bound for the lane's four pairs: |s~ - s| <= e = eps ||phi|| max_i ||c_i||;
@@ -780,8 +821,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 template <int P>
 struct __attribute__((aligned(16))) PTile {
   float f32[PT][FP];
-  uint16_t h[P == VBGS_FP32 ? 1 : PT][FP];
+  uint16_t h[P == VBGS_FP32 || P == VBGS_FP8 ? 1 : PT][FP];
   uint16_t l[P == VBGS_BF16X3 ? PT : 1][FP];
+  uint8_t q8[P == VBGS_FP8 ? PT : 1][FP];
+  float ps8[PT];
   float nph[PT];
   double lse[PT];
 };
@@ -796,7 +839,14 @@ __device__ __forceinline__ void load_ptile(PTile<P>& T, const EArgs& a, int64_t 
     if (row < nvalid) v = reinterpret_cast<const uint4*>(a.phi32 + n0 * FP)[q];
     reinterpret_cast<uint4*>(&T.f32[0][0])[q] = v;
   }
-  if constexpr (P != VBGS_FP32) {
+  if constexpr (P == VBGS_FP8) {
+    const int row = t / (FP / 16);  // 64 rows x 32 B = 128 x 16 B
+    if (t < PT * FP / 16) {
+      uint4 v = {0, 0, 0, 0};
+      if (row < nvalid) v = reinterpret_cast<const uint4*>(a.phi8 + n0 * FP)[t];
+      reinterpret_cast<uint4*>(&T.q8[0][0])[t] = v;
+    }
+  } else if constexpr (P != VBGS_FP32) {
     const int row = t / (FP / 8);  // 64 rows x 64 B = 256 x 16 B
     uint4 v = {0, 0, 0, 0};
     if (row < nvalid) v = reinterpret_cast<const uint4*>(a.phih + n0 * FP)[t];
@@ -809,6 +859,7 @@ __device__ __forceinline__ void load_ptile(PTile<P>& T, const EArgs& a, int64_t 
   }
   if (t < PT) {
     const bool v = t < nvalid;
+    if constexpr (P == VBGS_FP8) T.ps8[t] = v ? a.phis[n0 + t] : 0.0f;
     T.nph[t] = v ? a.nphi[n0 + t] : 0.0f;
     T.lse[t] = v ? a.lse2[n0 + t] : INFINITY;
   }
@@ -821,7 +872,14 @@ __global__ __launch_bounds__(256) void k_pass2(const EArgs a) {
   const int64_t kb = (int64_t)blockIdx.x * CT + w * 16;
   const int64_t kc = kb + c;
   const bool kval = kc < a.K;
-  const Opnd<P> Bc = load_op<P>(a.c32 + kc * FP, a.ch + kc * FP, a.cl + kc * FP, g);
+  Opnd<P> Bc;
+  float csc = 1.0f;  // FP8 tier: factor undoing the component row's scaling
+  if constexpr (P == VBGS_FP8) {
+    Bc = load_op8(a.c8 + kc * FP, g);
+    csc = a.cs8[kc];
+  } else {
+    Bc = load_op<P>(a.c32 + kc * FP, a.ch + kc * FP, a.cl + kc * FP, g);
+  }
   const int64_t ntile = (a.N + PT - 1) / PT;
   const int64_t t0 = ntile * blockIdx.y / a.nsplit, t1 = ntile * (blockIdx.y + 1) / a.nsplit;
   // FP64 fold of the FP32 MFMA r^T phi tiles; lane holds comps kb + 4g + j at slots c and 16 + c
@@ -838,9 +896,18 @@ __global__ __launch_bounds__(256) void k_pass2(const EArgs a) {
 #pragma unroll
     for (int pb = 0; pb < PT / 16; ++pb) {
       const int r = pb * 16 + c;
-      const Opnd<P> A = load_op<P>(&T.f32[r][0], &T.h[P == VBGS_FP32 ? 0 : r][0], &T.l[P == VBGS_BF16X3 ? r : 0][0], g);
-      const f32x4 s = mfma_scores<P>(A, Bc);  // lane: points pb*16 + 4g + i, component kc
+      Opnd<P> A;
+      if constexpr (P == VBGS_FP8) {
+        A = load_op8(&T.q8[r][0], g);
+      } else {
+        A = load_op<P>(&T.f32[r][0], &T.h[P == VBGS_FP32 ? 0 : r][0], &T.l[P == VBGS_BF16X3 ? r : 0][0], g);
+      }
+      f32x4 s = mfma_scores<P>(A, Bc);  // lane: points pb*16 + 4g + i, component kc
       const int rb = pb * 16 + 4 * g;
+      if constexpr (P == VBGS_FP8) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = s[i] * T.ps8[rb + i] * csc;
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float rr = kval ? exp2f(s[i] - (float)T.lse[rb + i]) : 0.0f;
@@ -1861,6 +1928,10 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.ch = d.at<uint16_t>(L.ch);
   a.cl = d.at<uint16_t>(L.cl);
   a.nc = d.at<float>(L.nc);
+  a.phi8 = d.at<uint8_t>(L.phi8);
+  a.phis = d.at<float>(L.phis);
+  a.c8 = d.at<uint8_t>(L.c8);
+  a.cs8 = d.at<float>(L.cs8);
   a.lse2 = d.at<double>(L.lse2);
   a.lse_part = d.at<double>(L.lse_part);
   a.lse_out = lse_out;
@@ -1951,6 +2022,7 @@ hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int
   if (!c.exact) {
     if (c.prec == VBGS_FP32) VB_P1(VBGS_FP32, false);
     else if (c.prec == VBGS_BF16) VB_P1(VBGS_BF16, false);
+    else if (c.prec == VBGS_FP8) VB_P1(VBGS_FP8, false);
     else VB_P1(VBGS_BF16X3, false);
   }
 #undef VB_P1
@@ -1979,6 +2051,8 @@ hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int
     VB_P2(VBGS_FP32);
   } else if (c.prec == VBGS_BF16) {
     VB_P2(VBGS_BF16);
+  } else if (c.prec == VBGS_FP8) {
+    VB_P2(VBGS_FP8);
   } else {
     VB_P2(VBGS_BF16X3);
   }

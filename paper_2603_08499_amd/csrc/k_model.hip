@@ -203,6 +203,43 @@ __global__ __launch_bounds__(256) void k_alpha_final(const double* __restrict__ 
   }
 }
 
+// FP8 tier: rows of FP FP32 values -> OCP e4m3 bytes. Each row is scaled by the power of two 2^e that
+// puts its largest magnitude in [224, 448] (the scaling is exact), rounded to nearest even by the
+// hardware conversion; inv[r] = 2^-e undoes it on the scores.
+__global__ __launch_bounds__(256) void k_fp8_rows(const float* __restrict__ src, int64_t nrows,
+                                                  uint8_t* __restrict__ dst, float* __restrict__ inv) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= nrows) return;
+  float v[FP];
+  const f32x4* s4 = reinterpret_cast<const f32x4*>(src + r * FP);
+#pragma unroll
+  for (int q = 0; q < FP / 4; ++q) {
+    const f32x4 t = s4[q];
+    v[4 * q] = t[0];
+    v[4 * q + 1] = t[1];
+    v[4 * q + 2] = t[2];
+    v[4 * q + 3] = t[3];
+  }
+  float mx = 0.0f;
+#pragma unroll
+  for (int i = 0; i < FP; ++i) mx = fmaxf(mx, fabsf(v[i]));
+  float sc = 1.0f, un = 1.0f;
+  if (mx > 7.8886091e-31f && mx <= 3.4e38f) {  // 2^-100: rows below are left unscaled (they round to 0)
+    int e;
+    frexpf(448.0f / mx, &e);  // 448 / mx in [2^(e-1), 2^e)
+    sc = ldexpf(1.0f, e - 1);
+    un = ldexpf(1.0f, 1 - e);
+  }
+  uint32_t* d32 = reinterpret_cast<uint32_t*>(dst + r * FP);
+#pragma unroll
+  for (int q = 0; q < FP / 4; ++q) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * q] * sc, v[4 * q + 1] * sc, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * q + 2] * sc, v[4 * q + 3] * sc, w, true);
+    d32[q] = (uint32_t)w;
+  }
+  inv[r] = un;
+}
+
 hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s) {
   const Layout& L = *d.L;
   double* part = d.at<double>(L.mom_part);
@@ -212,6 +249,9 @@ hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStr
     hipLaunchKernelGGL(k_features, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, N, d.D, d.frame(),
                        d.at<float>(L.phi32), d.at<uint16_t>(L.phih), d.at<uint16_t>(L.phil), d.at<float>(L.nphi),
                        &d.frame()->flags);
+  if (N > 0 && L.fp8)
+    hipLaunchKernelGGL(k_fp8_rows, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, d.at<float>(L.phi32), N,
+                       d.at<uint8_t>(L.phi8), d.at<float>(L.phis));
   return hipGetLastError();
 }
 
@@ -449,6 +489,9 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
     default:
       return hipErrorInvalidValue;
   }
+  if (L.fp8)
+    hipLaunchKernelGGL(k_fp8_rows, dim3((unsigned)((L.Kpad + 255) / 256)), dim3(256), 0, s, d.at<float>(L.c32),
+                       L.Kpad, d.at<uint8_t>(L.c8), d.at<float>(L.cs8));
   return hipGetLastError();
 }
 

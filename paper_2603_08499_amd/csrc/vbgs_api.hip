@@ -94,7 +94,7 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "prior scalars need kappa0 > 0, alpha0 > 0, nu0 > D - 1";
     return VBGS_ERR_ARG;
   }
-  if (p->score_prec < VBGS_FP64 || p->score_prec > VBGS_AUTO) {
+  if (p->score_prec < VBGS_FP64 || p->score_prec > VBGS_FP8) {
     if (why) *why = "unknown score_prec";
     return VBGS_ERR_ARG;
   }
@@ -109,6 +109,10 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
   if (p->exact != 0 && p->exact != 1) {
     if (why) *why = "exact must be 0 or 1";
     return VBGS_ERR_ARG;
+  }
+  if (p->score_prec == VBGS_FP8 && p->exact != 0) {
+    if (why) *why = "VBGS_FP8 is a plain tier (exact = 0): as a screen its error bound would admit nearly every pair";
+    return VBGS_ERR_UNSUPPORTED;
   }
   if (p->score_prec == VBGS_AUTO && (p->exact != 1 || p->proposal)) {
     if (why) *why = "VBGS_AUTO chooses the screen of the exact mode: it needs exact = 1 and no proposal";
@@ -246,6 +250,11 @@ Layout make_layout(const vbgs_params& p) {
   L.ch = take((size_t)L.Kpad * FP * 2);
   L.cl = take((size_t)L.Kpad * FP * 2);
   L.nc = take((size_t)L.Kpad * 4);
+  L.fp8 = p.score_prec == VBGS_FP8 ? 1 : 0;
+  L.phi8 = take(L.fp8 ? (size_t)n * FP : 0);
+  L.phis = take(L.fp8 ? (size_t)n * 4 : 0);
+  L.c8 = take(L.fp8 ? (size_t)L.Kpad * FP : 0);
+  L.cs8 = take(L.fp8 ? (size_t)L.Kpad * 4 : 0);
   L.kl = take((size_t)K * 8);
   L.spart = take((size_t)ns * L.Kpad * stat_stride(p.D) * 8);
   L.stats = take((size_t)K * nfeat(p.D) * 8);

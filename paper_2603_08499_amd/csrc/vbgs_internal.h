@@ -112,6 +112,8 @@ __device__ __forceinline__ int lam_bin(float lam) {
 
 // Offsets (bytes) into the caller's workspace.
 struct Layout {
+  size_t phi8, phis, c8, cs8;  // FP8 tier: e4m3 rows and the factors that undo their scaling
+  int fp8;
   size_t frame, mom_part, phi32, phih, phil, nphi, lse2, lse_part, direct, c32, ch, cl, nc, kl,
       spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ccursor, ent_n, total;
   int64_t Kpad, n_lse_part;
@@ -322,6 +324,10 @@ struct EArgs {
   const uint16_t* ch;         // Kpad x 32
   const uint16_t* cl;         // Kpad x 32
   const float* nc;            // Kpad
+  const uint8_t* phi8;        // FP8 tier: N x 32 e4m3 features
+  const float* phis;          // N: factor undoing each feature row's scaling
+  const uint8_t* c8;          // Kpad x 32 e4m3 coefficients
+  const float* cs8;           // Kpad: factor undoing each coefficient row's scaling
   double* lse2;               // N (log2 units)
   double* lse_part;           // pass-1 workgroups
   double* lse_out;            // N (nats) or null

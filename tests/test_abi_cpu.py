@@ -64,6 +64,15 @@ def test_query_sizes_and_validation():
         with pytest.raises(P.VBGSError) as e:
             P.query_sizes(P.make_params(6, 10, 10, score_prec="auto", **args))
         assert e.value.status == -7
+    # the FP8 tier is a plain tier: the exact mode and the proposal reject it
+    P.query_sizes(P.make_params(6, 10, 10, score_prec="fp8", exact=False))
+    for args in (dict(exact=True), dict(exact=True, proposal=True)):
+        with pytest.raises(P.VBGSError) as e:
+            P.query_sizes(P.make_params(6, 10, 10, score_prec="fp8", **args))
+        assert e.value.status == -7
+    with pytest.raises(P.VBGSError) as e:
+        P.query_sizes(P.make_params(7, 10, 10, score_prec="fp8", exact=False))
+    assert e.value.status == -7
     # culling coordinates: 0 (automatic) or 1..min(D, 3)
     P.query_sizes(P.make_params(5, 10, 10, cull_dims=2))
     for args in (dict(D=6, cull_dims=4), dict(D=2, cull_dims=3), dict(D=6, cull_dims=-1)):

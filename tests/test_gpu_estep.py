@@ -83,7 +83,7 @@ def test_estep_parity_exact(dev, prec, exact, N, K, D):
 
 
 @gpu
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("bf16x3", 1e-1), ("bf16", 10.0)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("bf16x3", 1e-1), ("bf16", 10.0), ("fp8", 100.0)])
 def test_estep_plain_gemm_tiers_report_error(dev, prec, tol):
     X, pr = scenes.random_problem(2000, 200, 6, seed=3)
     p = R.NW.from_prior(pr)
@@ -97,6 +97,29 @@ def test_estep_plain_gemm_tiers_report_error(dev, prec, tol):
     print("plain %s: stats relerr %.3e  max|dLSE| %.3e" % (prec, es, np.abs(lse.cpu().numpy() - ls).max()))
     assert np.isfinite(st.cpu().numpy()).all()
     assert es < tol
+
+
+@gpu
+def test_fp8_tier_error_between_bounds(dev):
+    """The FP8 tier (OCP e4m3 operands, unit roundoff 2^-4) is reported, not assumed to pass. Its
+    score error is bounded by (2u + u^2) sum_f |c_f phi_f| per pair and should exceed the BF16 tier's
+    (u = 2^-8) by about their roundoff ratio: a wrong operand layout or a scale not undone would give
+    errors of the order of the scores themselves."""
+    X, pr = scenes.random_problem(2000, 200, 6, seed=3)
+    p = R.NW.from_prior(pr)
+    e = R.expectations(p)
+    ls = R.lse(X, p, e)
+    err = {}
+    for prec in ("bf16", "fp8"):
+        m = _model(dev, pr, X.shape[0], prec, exact=False)
+        lse, st = m.estep_stats(torch.from_numpy(X).to(dev))
+        torch.cuda.synchronize()
+        assert m.sync_status() == 0
+        assert np.isfinite(lse.cpu().numpy()).all() and np.isfinite(st.cpu().numpy()).all()
+        err[prec] = np.abs(lse.cpu().numpy() - ls).max()
+        m.close()
+    print("max|dLSE| bf16 %.3e fp8 %.3e (ratio %.1f)" % (err["bf16"], err["fp8"], err["fp8"] / err["bf16"]))
+    assert err["bf16"] < err["fp8"] < 256 * err["bf16"]
 
 
 @gpu
