@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "point-component pairs/s per VB update, mixed vs FP64; stats rel err"
-PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
+PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "fp8": 5.0e15, "fp32": 157.3e12, "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
 
 
