@@ -240,11 +240,14 @@ __global__ __launch_bounds__(256) void k_fp8_rows(const float* __restrict__ src,
   inv[r] = un;
 }
 
-hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s) {
+hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s, int part_sel) {
   const Layout& L = *d.L;
   double* part = d.at<double>(L.mom_part);
-  hipLaunchKernelGGL(k_moments_partial, dim3(MOM_BLOCKS), dim3(256), 0, s, X, N, d.D, part);
-  hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64), 0, s, part, N, d.D, d.frame());
+  if (part_sel != 1) {
+    hipLaunchKernelGGL(k_moments_partial, dim3(MOM_BLOCKS), dim3(256), 0, s, X, N, d.D, part);
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64), 0, s, part, N, d.D, d.frame());
+  }
+  if (part_sel == 0) return hipGetLastError();
   if (N > 0 && d.D <= 6)  // quadratic features fill 1 + D + D(D+1)/2 <= 32 slots only for D <= 6
     hipLaunchKernelGGL(k_features, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, N, d.D, d.frame(),
                        d.at<float>(L.phi32), d.at<uint16_t>(L.phih), d.at<uint16_t>(L.phil), d.at<float>(L.nphi),

@@ -299,14 +299,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const unsigned long long*
   }
 }
 
-// sorts keys[0, n) (tmp: n keys of scratch); four passes, so the result is back in keys
-static hipError_t radix_sort32(const DevPtrs& d, unsigned long long* keys, int64_t n, hipStream_t s) {
+// sorts keys[0, n) (tmp: n keys of scratch); four passes, so the result is back in keys. The
+// component sort (comps) has scratch of its own, so that it can run beside the point sort.
+static hipError_t radix_sort32(const DevPtrs& d, unsigned long long* keys, int64_t n, hipStream_t s, bool comps) {
   if (n <= 1) return hipSuccess;
   const Layout& L = *d.L;
-  unsigned long long* tmp = d.at<unsigned long long>(L.rx_tmp);
-  int32_t* hist = d.at<int32_t>(L.rx_hist);
-  int32_t* off = d.at<int32_t>(L.rx_off);
-  int32_t* part = d.at<int32_t>(L.rx_part);
+  unsigned long long* tmp = d.at<unsigned long long>(comps ? L.rx2_tmp : L.rx_tmp);
+  int32_t* hist = d.at<int32_t>(comps ? L.rx2_hist : L.rx_hist);
+  int32_t* off = d.at<int32_t>(comps ? L.rx2_off : L.rx_off);
+  int32_t* part = d.at<int32_t>(comps ? L.rx2_part : L.rx_part);
   const int64_t nb = (n + RX_B - 1) / RX_B;
   unsigned long long* src = keys;
   unsigned long long* dst = tmp;
@@ -329,7 +330,7 @@ hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipSt
   unsigned long long* keys = d.at<unsigned long long>(L.pkeys);
   hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, N, N, d.D, d.nsp,
                      d.frame(), keys);
-  hipError_t e = radix_sort32(d, keys, N, s);
+  hipError_t e = radix_sort32(d, keys, N, s, false);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, keys, N,
                      d.at<int32_t>(L.porder), (int32_t*)nullptr, d.at<uint32_t>(L.pcode));
@@ -345,7 +346,7 @@ hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_lam_anchor, dim3(1), dim3(64), 0, s, hist, d.K, d.frame());
   hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.post(), d.K, d.K, d.D,
                      d.split, d.nsp, d.frame(), keys);
-  hipError_t e = radix_sort32(d, keys, d.K, s);
+  hipError_t e = radix_sort32(d, keys, d.K, s, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, keys, d.K,
                      d.at<int32_t>(L.corder), d.at<int32_t>(L.cinv), d.at<uint32_t>(L.ccode));

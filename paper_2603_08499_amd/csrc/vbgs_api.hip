@@ -38,6 +38,10 @@ struct vbgs_ctx {
   uint64_t lse_version;
   bool have_stats;
   bool order_reset;  // the sweep's block costs are not measured yet
+  // side stream (default priority) for the component preparation, which overlaps the point
+  // preparation of the culled path; made on first use
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   int nsplit;
   float T2;
   std::string err;
@@ -281,6 +285,11 @@ Layout make_layout(const vbgs_params& p) {
     L.rx_hist = take(sparse ? (size_t)ne * 4 : 0);
     L.rx_off = take(sparse ? (size_t)(ne + 1) * 4 : 0);
     L.rx_part = take(sparse ? (size_t)((ne + 1023) / 1024 + 2) * 4 : 0);
+    const int64_t nbk = (K + RX_B - 1) / RX_B, nek = 256 * nbk;
+    L.rx2_tmp = take(sparse ? (size_t)K * 8 : 0);
+    L.rx2_hist = take(sparse ? (size_t)nek * 4 : 0);
+    L.rx2_off = take(sparse ? (size_t)(nek + 1) * 4 : 0);
+    L.rx2_part = take(sparse ? (size_t)((nek + 1023) / 1024 + 2) * 4 : 0);
   }
   L.corder = take(sparse ? (size_t)L.Kpad * 4 : 0);
   L.cinv = take(sparse ? (size_t)L.Kpad * 4 : 0);
@@ -483,25 +492,58 @@ static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s) {
   return e;
 }
 
+static hipError_t make_side(vbgs_ctx* c) {
+  if (c->side) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+  return e;
+}
+
 static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, void* stream) {
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
   cfg.cull = use_cull(c) ? 1 : 0;
   cfg.order_reset = c->order_reset ? 1 : 0;
-  hipError_t e;
-  {
-    Phase ph(c, 0, S(stream));
-    e = launch_frame_prep(d, X, N, S(stream));
-  }
   const bool cull = use_cull(c);
-  if (e == hipSuccess) {
-    Phase ph(c, 1, S(stream));
-    e = prepare_components(c, S(stream));
-  }
-  if (e == hipSuccess) {
-    Phase ph(c, 8, S(stream));
-    if (cull) e = launch_sort_points(d, X, N, S(stream));
-    if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 0);
+  const hipStream_t s = S(stream);
+  hipError_t e;
+  if (cull) {
+    // frame moments first (the components are centred and Morton-coded with them); then the
+    // components (sort, coefficient rows, tile bounds) on the side stream while the points
+    // (features, sort) go on; the sweep waits for both
+    e = make_side(c);
+    if (e == hipSuccess) {
+      Phase ph(c, 0, s);
+      e = launch_frame_prep(d, X, N, s, 0);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
+    if (e == hipSuccess) {
+      Phase ph(c, 1, c->side);
+      e = prepare_components(c, c->side);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->join, c->side);
+    if (e == hipSuccess) {
+      Phase ph(c, 8, s);
+      e = launch_frame_prep(d, X, N, s, 1);
+      if (e == hipSuccess) e = launch_sort_points(d, X, N, s);
+    }
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join, 0);
+    if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, s, 0);
+  } else {
+    {
+      Phase ph(c, 0, s);
+      e = launch_frame_prep(d, X, N, s);
+    }
+    if (e == hipSuccess) {
+      Phase ph(c, 1, s);
+      e = prepare_components(c, s);
+    }
+    if (e == hipSuccess) {
+      Phase ph(c, 8, s);
+      e = launch_pass1(d, cfg, X, N, lse_out, s, 0);
+    }
   }
   if (e == hipSuccess) {
     Phase ph(c, 2, S(stream));
@@ -936,6 +978,12 @@ const char* vbgs_last_error(const vbgs_ctx* c) { return c ? c->err.c_str() : "nu
 
 void vbgs_destroy(vbgs_ctx* c) {
   if (!c) return;
+  if (c->side) {  // its work precedes the join event that the caller's stream waited on
+    hipStreamSynchronize(c->side);
+    hipEventDestroy(c->fork);
+    hipEventDestroy(c->join);
+    hipStreamDestroy(c->side);
+  }
   if (c->timers_made)
     for (int p = 0; p < VBGS_NPHASE; ++p)
       for (int i = 0; i < PhaseTimer::RING; ++i) {

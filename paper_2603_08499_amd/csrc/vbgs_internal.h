@@ -126,6 +126,7 @@ struct Layout {
   size_t elbo_part;  // 2 x 256 partial sums of the ELBO reduction
   size_t scr_part, scr_gate;  // screen choice: 2 x 256 partial norm sums, two gate flags
   size_t rx_tmp, rx_hist, rx_off, rx_part;  // radix sort: ping-pong keys, digit histograms, scan
+  size_t rx2_tmp, rx2_hist, rx2_off, rx2_part;  // the same for the component sort (runs concurrently)
   // learned proposal (workspace)
   size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
       p_tdh2, p_tdp1, p_th2b, p_th2T, p_tloss, p_grads;
@@ -284,7 +285,8 @@ struct Init0 {
 };
 
 hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& init, hipStream_t s);
-hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
+// part: 0 frame moments, 1 features, 2 both
+hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s, int part = 2);
 hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv = nullptr);
 hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s);
 hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStream_t s);
