@@ -380,6 +380,27 @@ vbgs_status vbgs_query_sizes(const vbgs_params* p, size_t* state_bytes, size_t* 
   return VBGS_OK;
 }
 
+static bool use_cull(const vbgs_ctx* c) {
+  return c->p.score_prec != VBGS_FP64 && c->p.exact == 1 && c->p.cull == 1;
+}
+
+// the side stream and its two events (culled path only), made with the context so that no stream
+// is created while a caller's stream may be capturing; on failure nothing is left behind
+static hipError_t make_side(vbgs_ctx* c) {
+  if (c->side || !use_cull(c)) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (c->join) hipEventDestroy(c->join);
+    if (c->fork) hipEventDestroy(c->fork);
+    if (c->side) hipStreamDestroy(c->side);
+    c->side = nullptr;
+    c->fork = c->join = nullptr;
+  }
+  return e;
+}
+
 static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   vbgs_ctx* c = new (std::nothrow) vbgs_ctx();
   if (!c) return nullptr;
@@ -455,10 +476,15 @@ vbgs_status vbgs_init(vbgs_ctx** out, const vbgs_params* p, const double* m0, co
   in.split = p->modal_split;
   vbgs_ctx* c = new_ctx(p, state, workspace);
   if (!c) return VBGS_ERR_ARG;
-  hipError_t e = launch_init_state(c->dev(), m0, in, S(stream));
-  if (e == hipSuccess) e = launch_clear_flags(c->dev(), S(stream));
+  hipError_t e = make_side(c);
   if (e != hipSuccess) {
     delete c;
+    return VBGS_ERR_HIP;
+  }
+  e = launch_init_state(c->dev(), m0, in, S(stream));
+  if (e == hipSuccess) e = launch_clear_flags(c->dev(), S(stream));
+  if (e != hipSuccess) {
+    vbgs_destroy(c);  // releases the side stream too
     return VBGS_ERR_HIP;
   }
   *out = c;
@@ -472,14 +498,15 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
   if (!out || !state || !workspace || !aligned(state) || !aligned(workspace)) return VBGS_ERR_ARG;
   vbgs_ctx* c = new_ctx(p, state, workspace);
   if (!c) return VBGS_ERR_ARG;
+  if (make_side(c) != hipSuccess) {
+    delete c;
+    return VBGS_ERR_HIP;
+  }
   c->prop_ready = p->proposal == 1;  // a proposal state carries its weights
   *out = c;
   return VBGS_OK;
 }
 
-static bool use_cull(const vbgs_ctx* c) {
-  return c->p.score_prec != VBGS_FP64 && c->p.exact == 1 && c->p.cull == 1;
-}
 
 // expectations and coefficient rows; with culling the MFMA rows are written in spatial order and
 // per-tile bounds are built
@@ -492,13 +519,6 @@ static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s) {
   return e;
 }
 
-static hipError_t make_side(vbgs_ctx* c) {
-  if (c->side) return hipSuccess;
-  hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
-  return e;
-}
 
 static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, void* stream) {
   const DevPtrs d = c->dev();
@@ -512,7 +532,7 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     // frame moments first (the components are centred and Morton-coded with them); then the
     // components (sort, coefficient rows, tile bounds) on the side stream while the points
     // (features, sort) go on; the sweep waits for both
-    e = make_side(c);
+    e = c->side ? hipSuccess : hipErrorInvalidResourceHandle;  // made with the context
     if (e == hipSuccess) {
       Phase ph(c, 0, s);
       e = launch_frame_prep(d, X, N, s, 0);
