@@ -411,15 +411,15 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
 //   row k:   G_k - lambda_k |x_S - m_k,S|^2       (RowBound)
 // A pair whose bound lies below the point's running lower bound M minus the margin T is one the
 // per-pair screen would drop, so it is never screened. Each wave works on its own:
-//   1. pilot: its seed tiles (in each curvature class, those around the Morton positions of its
+//   1. pilot: the centre tiles (in each curvature class, the tiles at the Morton positions of its
 //      first and last point) are screened without recording, which brings every M close to its
 //      final value;
-//   2. the seed tiles again, now recording candidates;
+//   2. the seed tiles (the centres and their two neighbours), now recording candidates;
 //   3. every other tile, 64 at a time (one per lane): a tile is screened when its bound reaches
 //      M - T for at least one point of the wave; within it, a 16-row block is screened when one
 //      of its row bounds, taken over the wave's box, reaches the wave's smallest M - T.
-// Rows and bounds of a tile are loaded straight into registers (they stay resident in the
-// caches, being read by every wave), so waves never wait for one another.
+// Each wave stages its own tiles in LDS (the rows stay resident in the caches, being read by
+// every wave), so waves never wait for one another.
 __device__ __forceinline__ float box_d2(const TileInfo& t, const float* lo, const float* hi) {
   float d2 = 0.0f;
 #pragma unroll
