@@ -1,6 +1,7 @@
 // Spatial ordering for the culled exact sweep: 3-D Morton keys of points and component means,
-// a bitonic sort of 64-bit keys (key = code << 32 | index, so every key is unique and the order
-// is deterministic), and per-tile bounds of the sorted component rows.
+// a stable radix sort of 64-bit keys on their code (key = code << 32 | index, so every key is
+// unique and the order is deterministic; the reassignment step sorts with a bitonic network), and
+// per-tile bounds of the sorted component rows.
 #include "vbgs_internal.h"
 
 namespace vbgs {
