@@ -208,6 +208,72 @@ __device__ __forceinline__ f32x4 mfma_h(const HOp& A, const HOp& B) {
 // ---------------------------------------------------------------------------
 // streaming exact top-C per (point, lane group); 4 waves x 4 point blocks of 16
 // ---------------------------------------------------------------------------
+// A lower bound on each point's C-th best logit for C <= 32: every lane group keeps its eight best
+// logits in registers (a compare-exchange chain); the four groups' eighth-best values are each the
+// smallest of eight distinct logits of the point, so their minimum is at or below its 32nd best.
+// k_logits_topc starts its thresholds there, so that its candidate buffers fill (and are
+// reselected) far less often than from -inf.
+__global__ __launch_bounds__(256) void k_topc_thresh(const PArgs a, int64_t N) {
+  __shared__ ETile T[2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t p0 = (int64_t)blockIdx.x * 256 + w * 64;
+  HOp B[4];
+  float r[4][8];
+  bool val[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t p = p0 + 16 * b + c;
+    val[b] = p < N;
+    B[b] = val[b] ? load_h(a.h2b + p * VBGS_H, g) : zero_h();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[b][j] = -INFINITY;
+  }
+  ETileRegs R;
+  etile_fetch(R, a, 0);
+  etile_store(T[0], R);
+  __syncthreads();
+  const int64_t ntiles = a.Kpad / CT;
+  for (int64_t it = 0; it < ntiles; ++it) {
+    const int cur = (int)(it & 1);
+    if (it + 1 < ntiles) etile_fetch(R, a, (it + 1) * CT);
+    const ETile& Tc = T[cur];
+#pragma unroll
+    for (int cb = 0; cb < CT / 16; ++cb) {
+      const HOp A = load_h(&Tc.e[cb * 16 + c][0], g);
+      const f32x4 bt = *reinterpret_cast<const f32x4*>(&Tc.beta[cb * 16 + 4 * g]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const f32x4 zz = mfma_h(A, B[b]);
+        float z[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z[i] = zz[i] + bt[i];
+        const float mx = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
+        if (mx > r[b][7]) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float v = z[i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const float hi = fmaxf(r[b][j], v);
+              v = fminf(r[b][j], v);
+              r[b][j] = hi;
+            }
+          }
+        }
+      }
+    }
+    if (it + 1 < ntiles) etile_store(T[cur ^ 1], R);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    float t = r[b][7];
+    t = fminf(t, __shfl_xor(t, 16));
+    t = fminf(t, __shfl_xor(t, 32));
+    if (val[b] && g == 0) a.tthr[p0 + 16 * b + c] = t;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_logits_topc(const PArgs a, int64_t N) {
   __shared__ ETile T[2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
@@ -222,7 +288,9 @@ __global__ __launch_bounds__(256) void k_logits_topc(const PArgs a, int64_t N) {
     const int64_t p = p0 + 16 * b + c;
     val[b] = p < N;
     B[b] = val[b] ? load_h(a.h2b + p * VBGS_H, g) : zero_h();
-    zt[b] = -INFINITY;
+    // just below the lower bound on the C-th best, so that a logit equal to it still enters
+    const float t = a.tthr && val[b] ? a.tthr[p] : -INFINITY;
+    zt[b] = t == -INFINITY ? t : nextafterf(t, -INFINITY);
     cnt[b] = 0;
   }
   ETileRegs R;
@@ -793,7 +861,13 @@ hipError_t launch_mlp_fwd(const PArgs& a, const float* X, const int32_t* idx, in
 
 hipError_t launch_topc(const PArgs& a, const EArgsLite& e, int64_t N, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_logits_topc, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, N);
+  PArgs b = a;
+  if (a.C <= 32) {
+    hipLaunchKernelGGL(k_topc_thresh, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, N);
+  } else {
+    b.tthr = nullptr;  // eight per lane group bound only the 32nd best
+  }
+  hipLaunchKernelGGL(k_logits_topc, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, b, N);
   hipLaunchKernelGGL(k_topc_merge, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, e, N);
   return hipGetLastError();
 }

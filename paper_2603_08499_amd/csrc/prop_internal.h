@@ -39,6 +39,7 @@ struct PArgs {
   uint16_t* h2b;
   float* tz;
   int32_t *tk, *tcnt;
+  float* tthr;  // per point: lower bound on its C-th best logit (used for C <= 32), or null
   // training
   float *th1, *th2, *txs, *tlse, *tdh2, *tdp1;
   uint16_t *th2b, *th2T;

@@ -321,6 +321,7 @@ Layout make_layout(const vbgs_params& p) {
   L.p_tz = take(pr ? (size_t)n * 4 * 2 * C * 4 : 0);
   L.p_tk = take(pr ? (size_t)n * 4 * 2 * C * 4 : 0);
   L.p_tcnt = take(pr ? (size_t)n * 4 * 4 : 0);
+  L.p_tthr = take(pr ? (size_t)n * 4 : 0);
   L.p_aud = take(pr ? (size_t)n * 8 : 0);
   L.p_gate = take(pr ? 64 : 0);
   const size_t Bp = (size_t)L.Bpad_max;
@@ -770,6 +771,7 @@ static PArgs make_pargs(vbgs_ctx* c) {
   a.tz = reinterpret_cast<float*>(ws + L.p_tz);
   a.tk = reinterpret_cast<int32_t*>(ws + L.p_tk);
   a.tcnt = reinterpret_cast<int32_t*>(ws + L.p_tcnt);
+  a.tthr = reinterpret_cast<float*>(ws + L.p_tthr);
   a.th1 = reinterpret_cast<float*>(ws + L.p_th1);
   a.th2 = reinterpret_cast<float*>(ws + L.p_th2);
   a.txs = reinterpret_cast<float*>(ws + L.p_txs);
