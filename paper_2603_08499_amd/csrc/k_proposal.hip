@@ -519,6 +519,9 @@ __global__ __launch_bounds__(256) void k_train_lse(const PArgs a, int64_t B) {
   __shared__ ETile T[2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
   const int64_t p0 = (int64_t)blockIdx.x * 256 + w * 64;
+  // component slice blockIdx.y of gridDim.y: tiles [t0, t1)
+  const int64_t ntiles = a.Kpad / CT;
+  const int64_t t0 = ntiles * blockIdx.y / gridDim.y, t1 = ntiles * (blockIdx.y + 1) / gridDim.y;
   HOp Bh[4];
   float M[4], L[4];
   bool val[4];
@@ -531,14 +534,15 @@ __global__ __launch_bounds__(256) void k_train_lse(const PArgs a, int64_t B) {
     L[b] = 0.0f;
   }
   ETileRegs R;
-  etile_fetch(R, a, 0);
-  etile_store(T[0], R);
+  if (t0 < t1) {
+    etile_fetch(R, a, t0 * CT);
+    etile_store(T[0], R);
+  }
   __syncthreads();
-  const int64_t ntiles = a.Kpad / CT;
   const float l2e = (float)LOG2E;
-  for (int64_t it = 0; it < ntiles; ++it) {
-    const int cur = (int)(it & 1);
-    if (it + 1 < ntiles) etile_fetch(R, a, (it + 1) * CT);
+  for (int64_t it = t0; it < t1; ++it) {
+    const int cur = (int)((it - t0) & 1);
+    if (it + 1 < t1) etile_fetch(R, a, (it + 1) * CT);
     const ETile& Tc = T[cur];
 #pragma unroll
     for (int cb = 0; cb < CT / 16; ++cb) {
@@ -559,7 +563,7 @@ __global__ __launch_bounds__(256) void k_train_lse(const PArgs a, int64_t B) {
         for (int i = 0; i < 4; ++i) L[b] += exp2f(z[i] - M[b]);
       }
     }
-    if (it + 1 < ntiles) etile_store(T[cur ^ 1], R);
+    if (it + 1 < t1) etile_store(T[cur ^ 1], R);
     __syncthreads();
   }
 #pragma unroll
@@ -572,8 +576,27 @@ __global__ __launch_bounds__(256) void k_train_lse(const PArgs a, int64_t B) {
       m = mn;
     }
     const int64_t p = p0 + 16 * b + c;
-    if (g == 0 && val[b]) a.tlse[p] = (m + log2f(l)) * (float)LN2;
+    if (g == 0 && val[b]) {
+      float* o = a.tlpart + ((int64_t)blockIdx.y * B + p) * 2;
+      o[0] = m;
+      o[1] = l;
+    }
   }
+}
+
+// the slices' (max, sum) of each point merged in slice order: LSE in nats
+__global__ __launch_bounds__(256) void k_train_lse_merge(const PArgs a, int64_t B, int S) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= B) return;
+  float m = -INFINITY, l = 0.0f;
+  for (int s = 0; s < S; ++s) {
+    const float om = a.tlpart[((int64_t)s * B + p) * 2], ol = a.tlpart[((int64_t)s * B + p) * 2 + 1];
+    const float mn = fmaxf(m, om);
+    if (mn == -INFINITY) continue;
+    l = (m == -INFINITY ? 0.0f : l * exp2f(m - mn)) + (om == -INFINITY ? 0.0f : ol * exp2f(om - mn));
+    m = mn;
+  }
+  a.tlse[p] = (m + log2f(l)) * (float)LN2;
 }
 
 // ---------------------------------------------------------------------------
@@ -605,7 +628,9 @@ __global__ __launch_bounds__(256) void k_train_dh(const PArgs a, int64_t B) {
 #pragma unroll
     for (int f = 0; f < 8; ++f) acc[b][f] = f32x4{0.f, 0.f, 0.f, 0.f};
   const float l2e = (float)LOG2E, invB = 1.0f / (float)B;
-  for (int64_t k0 = 0; k0 < a.Kpad; k0 += CT) {
+  const int64_t ntiles = a.Kpad / CT;  // component slice blockIdx.y: tiles [t0, t1)
+  const int64_t t0 = ntiles * blockIdx.y / gridDim.y, t1 = ntiles * (blockIdx.y + 1) / gridDim.y;
+  for (int64_t k0 = t0 * CT; k0 < t1 * CT; k0 += CT) {
     __syncthreads();
     {
       const uint4* src = reinterpret_cast<const uint4*>(a.Ebf + k0 * VBGS_H);
@@ -650,8 +675,17 @@ __global__ __launch_bounds__(256) void k_train_dh(const PArgs a, int64_t B) {
       const int64_t p = p0 + 16 * b + 4 * g + i;
       if (p < B)
 #pragma unroll
-        for (int f = 0; f < 8; ++f) a.tdh2[p * VBGS_H + 16 * f + c] = acc[b][f][i];
+        for (int f = 0; f < 8; ++f) a.tdpart[((int64_t)blockIdx.y * B + p) * VBGS_H + 16 * f + c] = acc[b][f][i];
     }
+}
+
+// dh2 = the slices' partial rows added in slice order
+__global__ __launch_bounds__(256) void k_train_dh_sum(const PArgs a, int64_t B, int S) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= B * VBGS_H) return;
+  float v = 0.0f;
+  for (int s = 0; s < S; ++s) v += a.tdpart[(int64_t)s * B * VBGS_H + q];
+  a.tdh2[q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -914,8 +948,11 @@ hipError_t launch_train(const PArgs& a, const float* X, const int32_t* tk, const
   o.xs = a.txs;
   hipError_t e = launch_mlp_fwd(a, X, bidx, B, o, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_train_lse, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, a, B);
-  hipLaunchKernelGGL(k_train_dh, dim3((unsigned)((B + 127) / 128)), dim3(256), 0, s, a, B);
+  const int sl = train_lse_split(B), sd = train_dh_split(B);
+  hipLaunchKernelGGL(k_train_lse, dim3((unsigned)((B + 255) / 256), (unsigned)sl), dim3(256), 0, s, a, B);
+  hipLaunchKernelGGL(k_train_lse_merge, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, a, B, sl);
+  hipLaunchKernelGGL(k_train_dh, dim3((unsigned)((B + 127) / 128), (unsigned)sd), dim3(256), 0, s, a, B);
+  hipLaunchKernelGGL(k_train_dh_sum, dim3((unsigned)((B * VBGS_H + 255) / 256)), dim3(256), 0, s, a, B, sd);
   hipLaunchKernelGGL(k_train_de, dim3((unsigned)(a.Kpad / 64)), dim3(256), 0, s, a, B);
   hipLaunchKernelGGL(k_train_sparse, dim3((unsigned)((B + 127) / 128)), dim3(128), 0, s, a, tk, tr, bidx, B);
   hipLaunchKernelGGL(k_train_dh1, dim3((unsigned)((B * VBGS_H + 127) / 128)), dim3(128), 0, s, a, B);

@@ -42,10 +42,23 @@ struct PArgs {
   float* tthr;  // per point: lower bound on its C-th best logit (used for C <= 32), or null
   // training
   float *th1, *th2, *txs, *tlse, *tdh2, *tdp1;
+  float *tlpart, *tdpart;  // per component slice: partial (max, sum) of the logits, partial dh2 rows
   uint16_t *th2b, *th2T;
   double* tloss;
   float *grads, *gW1, *gb1, *gW2, *gb2, *gE, *gbeta;
 };
+
+// component slices of the training passes, so that a minibatch fills the GPU: the logits LSE
+// takes enough slices for ~512 workgroups (at most 32), the dh2 product at most 16 with no more than
+// 65536 partial rows
+inline int train_lse_split(int64_t B) {
+  const int64_t wg = (B + 255) / 256, s = (512 + wg - 1) / wg;
+  return (int)(s < 1 ? 1 : (s > 32 ? 32 : s));
+}
+inline int train_dh_split(int64_t B) {
+  const int64_t s = 65536 / (B > 0 ? B : 1);
+  return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
+}
 
 struct MlpOut {
   int64_t npad;  // rows written (rows >= n are zero)

@@ -331,6 +331,8 @@ Layout make_layout(const vbgs_params& p) {
   L.p_tlse = take(pr ? Bp * 4 : 0);
   L.p_tdh2 = take(pr ? Bp * H * 4 : 0);
   L.p_tdp1 = take(pr ? Bp * H * 4 : 0);
+  L.p_tlpart = take(pr ? (size_t)32 * Bp * 2 * 4 : 0);
+  L.p_tdpart = take(pr ? std::min<size_t>((size_t)16 * Bp, 65536) * H * 4 : 0);
   L.p_th2b = take(pr ? Bp * H * 2 : 0);
   L.p_th2T = take(pr ? Bp * H * 2 : 0);
   L.p_tloss = take(pr ? Bp * 8 : 0);
@@ -778,6 +780,8 @@ static PArgs make_pargs(vbgs_ctx* c) {
   a.tlse = reinterpret_cast<float*>(ws + L.p_tlse);
   a.tdh2 = reinterpret_cast<float*>(ws + L.p_tdh2);
   a.tdp1 = reinterpret_cast<float*>(ws + L.p_tdp1);
+  a.tlpart = reinterpret_cast<float*>(ws + L.p_tlpart);
+  a.tdpart = reinterpret_cast<float*>(ws + L.p_tdpart);
   a.th2b = reinterpret_cast<uint16_t*>(ws + L.p_th2b);
   a.th2T = reinterpret_cast<uint16_t*>(ws + L.p_th2T);
   a.tloss = reinterpret_cast<double*>(ws + L.p_tloss);
