@@ -761,37 +761,48 @@ __global__ __launch_bounds__(256) void k_train_de(const PArgs a, int64_t B) {
 // ---------------------------------------------------------------------------
 // training: sparse target term and per-point loss (thread per batch point)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(128) void k_train_sparse(const PArgs a, const int32_t* __restrict__ tk,
+// one wave per batch point, lane l taking features l and 64 + l
+__global__ __launch_bounds__(256) void k_train_sparse(const PArgs a, const int32_t* __restrict__ tk,
                                                       const float* __restrict__ tr, const int32_t* __restrict__ bidx,
                                                       int64_t B) {
-  const int64_t n = (int64_t)blockIdx.x * 128 + threadIdx.x;
-  if (n >= B) return;
+  static_assert(VBGS_H == 128, "two features per lane");
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= B) return;  // whole waves
   const int64_t row = bidx[n];
-  float wsum = 0.0f;
-  for (int j = 0; j < 64; ++j)
-    if (tk[row * 64 + j] >= 0) wsum += tr[row * 64 + j];
+  const int32_t kl = tk[row * 64 + lane];  // lane j holds target j
+  const float rl = kl >= 0 ? tr[row * 64 + lane] : 0.0f;
+  float wsum = rl;
+  for (int off = 32; off > 0; off >>= 1) wsum += __shfl_xor(wsum, off);
   if (!(wsum > 0.0f)) {  // no targets: only the softmax term (dense kernels) contributes
-    a.tloss[n] = (double)a.tlse[n];
+    if (lane == 0) a.tloss[n] = (double)a.tlse[n];
     return;
   }
   const float invB = 1.0f / (float)B;
-  const float* h2 = a.th2 + n * VBGS_H;
+  const float h0 = a.th2[n * VBGS_H + lane], h1 = a.th2[n * VBGS_H + 64 + lane];
+  float d0 = 0.0f, d1 = 0.0f;
   double zt = 0.0;
-  for (int j = 0; j < 64; ++j) {
-    const int32_t k = tk[row * 64 + j];
-    if (k < 0) continue;
-    const float wv = tr[row * 64 + j] / wsum;
+  unsigned long long live = __ballot(kl >= 0);
+  while (live) {
+    const int j = __ffsll((long long)live) - 1;
+    live &= live - 1ull;
+    const int32_t k = __shfl(kl, j);
+    const float wv = __shfl(rl, j) / wsum;
     const float* Ek = a.E + (int64_t)k * VBGS_H;
-    float z = a.beta[k];
-    for (int f = 0; f < VBGS_H; ++f) {
-      z = fmaf(h2[f], Ek[f], z);
-      a.tdh2[n * VBGS_H + f] -= invB * wv * Ek[f];
-      atomicAdd(&a.gE[(int64_t)k * VBGS_H + f], -invB * wv * h2[f]);
-    }
-    atomicAdd(&a.gbeta[k], -invB * wv);
+    const float e0 = Ek[lane], e1 = Ek[64 + lane];
+    float z = fmaf(h0, e0, h1 * e1);
+    for (int off = 32; off > 0; off >>= 1) z += __shfl_xor(z, off);
+    z += a.beta[k];
+    d0 -= invB * wv * e0;
+    d1 -= invB * wv * e1;
+    atomicAdd(&a.gE[(int64_t)k * VBGS_H + lane], -invB * wv * h0);
+    atomicAdd(&a.gE[(int64_t)k * VBGS_H + 64 + lane], -invB * wv * h1);
+    if (lane == 0) atomicAdd(&a.gbeta[k], -invB * wv);
     zt += (double)wv * (double)z;
   }
-  a.tloss[n] = (double)a.tlse[n] - zt;
+  a.tdh2[n * VBGS_H + lane] += d0;
+  a.tdh2[n * VBGS_H + 64 + lane] += d1;
+  if (lane == 0) a.tloss[n] = (double)a.tlse[n] - zt;
 }
 
 // ---------------------------------------------------------------------------
@@ -810,35 +821,51 @@ __global__ __launch_bounds__(128) void k_train_dh1(const PArgs a, int64_t B) {
   a.tdp1[n * VBGS_H + i] = a.th1[n * VBGS_H + i] > 0.0f ? s : 0.0f;
 }
 
+// hidden-layer weight gradients, index t over [gW2 (H x H), gb2 (H), gW1 (H x D), gb1 (H)]; the
+// batch is split into TRAIN_W_SPLIT slices (blockIdx.y), whose partial sums k_train_wgrad_sum adds
+// in slice order
+__device__ __forceinline__ float* wgrad_dst(const PArgs& a, int64_t t) {
+  const int H = VBGS_H;
+  const int64_t nW2 = (int64_t)H * H, nW1 = (int64_t)H * a.D;
+  if (t < nW2) return a.gW2 + t;
+  if (t < nW2 + H) return a.gb2 + (t - nW2);
+  if (t < nW2 + H + nW1) return a.gW1 + (t - nW2 - H);
+  return a.gb1 + (t - nW2 - H - nW1);
+}
+
 __global__ __launch_bounds__(256) void k_train_wgrad(const PArgs a, int64_t B) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int H = VBGS_H, D = a.D;
-  const int64_t nW2 = (int64_t)H * H, nW1 = (int64_t)H * D;
+  const int64_t nW2 = (int64_t)H * H, nW1 = (int64_t)H * D, nw = nW2 + H + nW1 + H;
+  const int64_t n0 = B * blockIdx.y / gridDim.y, n1 = B * (blockIdx.y + 1) / gridDim.y;
+  if (t >= nw) return;
+  float s = 0.0f;
   if (t < nW2) {  // gW2[j][i] = sum_n dpre2[n][j] h1[n][i]
     const int j = (int)(t / H), i = (int)(t % H);
-    float s = 0.0f;
-    for (int64_t n = 0; n < B; ++n) {
+    for (int64_t n = n0; n < n1; ++n) {
       const float d2 = a.th2[n * H + j] > 0.0f ? a.tdh2[n * H + j] : 0.0f;
       s = fmaf(d2, a.th1[n * H + i], s);
     }
-    a.gW2[t] = s;
   } else if (t < nW2 + H) {  // gb2
     const int j = (int)(t - nW2);
-    float s = 0.0f;
-    for (int64_t n = 0; n < B; ++n) s += a.th2[n * H + j] > 0.0f ? a.tdh2[n * H + j] : 0.0f;
-    a.gb2[j] = s;
+    for (int64_t n = n0; n < n1; ++n) s += a.th2[n * H + j] > 0.0f ? a.tdh2[n * H + j] : 0.0f;
   } else if (t < nW2 + H + nW1) {  // gW1[j][d] = sum_n dpre1[n][j] x'[n][d]
     const int64_t u = t - nW2 - H;
     const int j = (int)(u / D), d = (int)(u % D);
-    float s = 0.0f;
-    for (int64_t n = 0; n < B; ++n) s = fmaf(a.tdp1[n * H + j], a.txs[n * MAXD + d], s);
-    a.gW1[u] = s;
-  } else if (t < nW2 + H + nW1 + H) {  // gb1
+    for (int64_t n = n0; n < n1; ++n) s = fmaf(a.tdp1[n * H + j], a.txs[n * MAXD + d], s);
+  } else {  // gb1
     const int j = (int)(t - nW2 - H - nW1);
-    float s = 0.0f;
-    for (int64_t n = 0; n < B; ++n) s += a.tdp1[n * H + j];
-    a.gb1[j] = s;
+    for (int64_t n = n0; n < n1; ++n) s += a.tdp1[n * H + j];
   }
+  a.twpart[(int64_t)blockIdx.y * nw + t] = s;
+}
+
+__global__ __launch_bounds__(256) void k_train_wgrad_sum(const PArgs a, int64_t nw, int S) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nw) return;
+  float s = 0.0f;
+  for (int q = 0; q < S; ++q) s += a.twpart[(int64_t)q * nw + t];
+  *wgrad_dst(a, t) = s;
 }
 
 __global__ __launch_bounds__(256) void k_train_loss(const double* __restrict__ lp, int64_t B, double* out) {
@@ -954,10 +981,11 @@ hipError_t launch_train(const PArgs& a, const float* X, const int32_t* tk, const
   hipLaunchKernelGGL(k_train_dh, dim3((unsigned)((B + 127) / 128), (unsigned)sd), dim3(256), 0, s, a, B);
   hipLaunchKernelGGL(k_train_dh_sum, dim3((unsigned)((B * VBGS_H + 255) / 256)), dim3(256), 0, s, a, B, sd);
   hipLaunchKernelGGL(k_train_de, dim3((unsigned)(a.Kpad / 64)), dim3(256), 0, s, a, B);
-  hipLaunchKernelGGL(k_train_sparse, dim3((unsigned)((B + 127) / 128)), dim3(128), 0, s, a, tk, tr, bidx, B);
+  hipLaunchKernelGGL(k_train_sparse, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, a, tk, tr, bidx, B);
   hipLaunchKernelGGL(k_train_dh1, dim3((unsigned)((B * VBGS_H + 127) / 128)), dim3(128), 0, s, a, B);
   const int64_t nw = (int64_t)VBGS_H * VBGS_H + VBGS_H + (int64_t)VBGS_H * a.D + VBGS_H;
-  hipLaunchKernelGGL(k_train_wgrad, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, a, B);
+  hipLaunchKernelGGL(k_train_wgrad, dim3((unsigned)((nw + 255) / 256), TRAIN_W_SPLIT), dim3(256), 0, s, a, B);
+  hipLaunchKernelGGL(k_train_wgrad_sum, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, a, nw, TRAIN_W_SPLIT);
   if (loss_out) hipLaunchKernelGGL(k_train_loss, dim3(1), dim3(256), 0, s, a.tloss, B, loss_out);
   if (grads_out) {
     e = hipMemcpyAsync(grads_out, a.grads, (size_t)a.n_train * 4, hipMemcpyDeviceToDevice, s);

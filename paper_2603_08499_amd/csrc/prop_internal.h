@@ -43,6 +43,7 @@ struct PArgs {
   // training
   float *th1, *th2, *txs, *tlse, *tdh2, *tdp1;
   float *tlpart, *tdpart;  // per component slice: partial (max, sum) of the logits, partial dh2 rows
+  float* twpart;           // per batch slice: partial hidden-layer weight gradients
   uint16_t *th2b, *th2T;
   double* tloss;
   float *grads, *gW1, *gb1, *gW2, *gb2, *gE, *gbeta;
@@ -55,6 +56,7 @@ inline int train_lse_split(int64_t B) {
   const int64_t wg = (B + 255) / 256, s = (512 + wg - 1) / wg;
   return (int)(s < 1 ? 1 : (s > 32 ? 32 : s));
 }
+constexpr int TRAIN_W_SPLIT = 16;  // batch slices of the hidden-layer weight gradients
 inline int train_dh_split(int64_t B) {
   const int64_t s = 65536 / (B > 0 ? B : 1);
   return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));

@@ -333,6 +333,7 @@ Layout make_layout(const vbgs_params& p) {
   L.p_tdp1 = take(pr ? Bp * H * 4 : 0);
   L.p_tlpart = take(pr ? (size_t)32 * Bp * 2 * 4 : 0);
   L.p_tdpart = take(pr ? std::min<size_t>((size_t)16 * Bp, 65536) * H * 4 : 0);
+  L.p_twpart = take(pr ? (size_t)TRAIN_W_SPLIT * (H * H + 2 * H + H * MAXD) * 4 : 0);
   L.p_th2b = take(pr ? Bp * H * 2 : 0);
   L.p_th2T = take(pr ? Bp * H * 2 : 0);
   L.p_tloss = take(pr ? Bp * 8 : 0);
@@ -782,6 +783,7 @@ static PArgs make_pargs(vbgs_ctx* c) {
   a.tdp1 = reinterpret_cast<float*>(ws + L.p_tdp1);
   a.tlpart = reinterpret_cast<float*>(ws + L.p_tlpart);
   a.tdpart = reinterpret_cast<float*>(ws + L.p_tdpart);
+  a.twpart = reinterpret_cast<float*>(ws + L.p_twpart);
   a.th2b = reinterpret_cast<uint16_t*>(ws + L.p_th2b);
   a.th2T = reinterpret_cast<uint16_t*>(ws + L.p_th2T);
   a.tloss = reinterpret_cast<double*>(ws + L.p_tloss);
