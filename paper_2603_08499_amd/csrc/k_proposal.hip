@@ -395,41 +395,64 @@ __global__ __launch_bounds__(256) void k_topc_export(const EArgs e, int64_t N, i
 // ---------------------------------------------------------------------------
 // audit: dense exact LSE of the audited points, captured mass, fallback decision
 // ---------------------------------------------------------------------------
+// exact FP64 LSE of the audited points over all K: AP points per workgroup, so that each
+// coefficient row is read once for all of them; per point an online (max, sum) per thread, then a
+// fixed-order merge over lanes and waves
+constexpr int AP = 8;
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_audit_lse(const EArgsLite e, const int32_t* __restrict__ idx, int64_t n,
                                                    double* __restrict__ out) {
-  __shared__ double sm[256], sl[256];
-  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-    const int64_t p = idx[i];
-    const float* x = e.X + p * DT;
-    double m = -INFINITY, l = 0.0;
-    for (int64_t k = threadIdx.x; k < e.K; k += 256) {
+  __shared__ float xs[AP][DT];
+  __shared__ double wm[4][AP], wl[4][AP];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * AP;
+  const int np = (int)(n - i0 < AP ? n - i0 : AP);
+  if (tid < AP * DT) {
+    const int j = tid / DT, q = tid % DT;
+    xs[j][q] = j < np ? e.X[(int64_t)idx[i0 + j] * DT + q] : 0.0f;
+  }
+  __syncthreads();
+  double m[AP], l[AP];
+#pragma unroll
+  for (int j = 0; j < AP; ++j) {
+    m[j] = -INFINITY;
+    l[j] = 0.0;
+  }
+  for (int64_t k = tid; k < e.K; k += 256) {
+    const double* row = e.direct + k * e.dts;
+#pragma unroll
+    for (int j = 0; j < AP; ++j) {
+      if (j >= np) break;
       double d[DT];
-      const double s = direct_score2_dt<DT>(e.direct + k * e.dts, x, d);
-      if (s > m) {
-        l = l * exp2(m - s) + 1.0;
-        m = s;
+      const double sc = direct_score2_dt<DT>(row, &xs[j][0], d);
+      if (sc > m[j]) {
+        l[j] = l[j] * exp2(m[j] - sc) + 1.0;
+        m[j] = sc;
       } else {
-        l += exp2(s - m);
+        l[j] += exp2(sc - m[j]);
       }
     }
-    sm[threadIdx.x] = m;
-    sl[threadIdx.x] = l;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
-        const double m1 = sm[threadIdx.x], m2 = sm[threadIdx.x + w];
-        const double mn = fmax(m1, m2);
-        if (mn != -INFINITY) {
-          sl[threadIdx.x] = (m1 == -INFINITY ? 0.0 : sl[threadIdx.x] * exp2(m1 - mn)) +
-                            (m2 == -INFINITY ? 0.0 : sl[threadIdx.x + w] * exp2(m2 - mn));
-          sm[threadIdx.x] = mn;
-        }
-      }
-      __syncthreads();
+  }
+  auto merge = [](double& ma, double& la, double mb, double lb) {
+    const double mn = fmax(ma, mb);
+    if (mn == -INFINITY) return;
+    la = (ma == -INFINITY ? 0.0 : la * exp2(ma - mn)) + (mb == -INFINITY ? 0.0 : lb * exp2(mb - mn));
+    ma = mn;
+  };
+#pragma unroll
+  for (int j = 0; j < AP; ++j) {
+    for (int off = 32; off > 0; off >>= 1) merge(m[j], l[j], __shfl_xor(m[j], off), __shfl_xor(l[j], off));
+    if (lane == 0) {
+      wm[w][j] = m[j];
+      wl[w][j] = l[j];
     }
-    if (threadIdx.x == 0) out[i] = sm[0] + log2(sl[0]);
-    __syncthreads();
+  }
+  __syncthreads();
+  if (tid < np) {
+    double mm = wm[0][tid], ll = wl[0][tid];
+    for (int q = 1; q < 4; ++q) merge(mm, ll, wm[q][tid], wl[q][tid]);
+    out[i0 + tid] = mm + log2(ll);
   }
 }
 
@@ -945,7 +968,8 @@ hipError_t launch_audit(const EArgsLite& e, int D, const int32_t* idx, int64_t n
     switch (D) {
 #define VB_AU(DD) \
   case DD:        \
-    hipLaunchKernelGGL(k_audit_lse<DD>, dim3(256), dim3(256), 0, s, e, idx, n, aud); break;
+    hipLaunchKernelGGL(k_audit_lse<DD>, dim3((unsigned)((n + AP - 1) / AP)), dim3(256), 0, s, e, idx, n, aud); \
+    break;
       VB_AU(1) VB_AU(2) VB_AU(3) VB_AU(4) VB_AU(5) VB_AU(6)
 #undef VB_AU
       default:
