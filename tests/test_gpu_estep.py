@@ -199,6 +199,28 @@ def test_edge_cases(dev):
 
 
 @gpu
+@pytest.mark.parametrize("K", [1, 70])
+def test_fp8_tier_edges(dev, K):
+    """FP8 plain tier on empty, single and ragged batches and on K = 1: the device flags stay clear,
+    every output is finite, and the responsibilities of each point still sum to one (pass 2 recomputes
+    the same FP8 scores that pass 1 normalised)."""
+    X, pr = scenes.random_problem(600, K, 6, seed=31 + K)
+    m = _model(dev, pr, 600, "fp8", exact=False)
+    Xg = torch.from_numpy(X).to(dev)
+    for n in (0, 1, 65, 600):
+        lse, st = m.estep_stats(Xg[:n].contiguous())
+        F = m.elbo()
+        torch.cuda.synchronize()
+        assert m.sync_status() == 0
+        s = st.cpu().numpy()
+        assert np.isfinite(s).all() and np.isfinite(lse.cpu().numpy()).all() and np.isfinite(F.item())
+        if n == 0:
+            assert float(np.abs(s).max()) == 0.0
+        else:
+            assert abs(s[:, 0].sum() - n) < 1e-3 * n
+
+
+@gpu
 def test_d8_fp64_path(dev):
     X, pr = scenes.random_problem(500, 40, 8, seed=2)
     m = _model(dev, pr, 500, "fp64")
