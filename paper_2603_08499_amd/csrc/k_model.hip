@@ -294,7 +294,6 @@ struct CoefOut {
   uint16_t* ch;
   uint16_t* cl;
   float* nc;
-  double* kl;
 };
 
 __device__ void write_dead_row(const CoefOut& o, int64_t k, int dts, bool expanded) {
@@ -327,7 +326,6 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     return;
   }
   const double* q = post + k * REC;
-  const double* p = prior + k * REC;
   // one block (split = 0) or two independent Normal-Wishart blocks (see coord_block)
   const int nb = split > 0 ? 2 : 1;
   const double alpha = q[0];
@@ -346,7 +344,6 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
   if (!cholesky<D>(L)) {
     atomicOr(flags, FLAG_NOT_PD);
     write_dead_row(o, k, dts, D <= 6);
-    o.kl[k] = 0.0;
     o.lam[k] = 0.0f;
     return;
   }
@@ -436,6 +433,62 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
   }
   }
 
+}
+
+
+// KL(NW(q_k) || NW(p_k)) summed over the blocks, + the per-component part of KL(Dir(alpha) ||
+// Dir(alpha_p)); only the ELBO needs it, so it runs apart from the coefficient rows (beside the
+// sweep on the culled path). A non-positive-definite W^{-1} was flagged by k_coeffs; its KL is 0.
+template <int D>
+__global__ __launch_bounds__(128) void k_kl(const double* __restrict__ prior, const double* __restrict__ post,
+                                            int64_t K, const FrameInfo* __restrict__ fr, double* __restrict__ kl,
+                                            int* flags, int split) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double* q = post + k * REC;
+  const double* p = prior + k * REC;
+  const int nb = split > 0 ? 2 : 1;
+  const double alpha = q[0];
+  double kap[2], nuv[2];
+  int Db[2] = {split > 0 ? split : D, split > 0 ? D - split : 0};
+  for (int b = 0; b < 2; ++b) {
+    kap[b] = rec_kappa(q, D, b < nb ? b : 0);
+    nuv[b] = rec_nu(q, D, b < nb ? b : 0);
+  }
+  double m[D];
+  for (int i = 0; i < D; ++i) m[i] = q[3 + i];
+  double L[D][D];
+  load_winv<D>(q, L);
+  if (!cholesky<D>(L)) {
+    kl[k] = 0.0;
+    return;
+  }
+  double lndet_b[2] = {0.0, 0.0};
+  for (int i = 0; i < D; ++i) lndet_b[coord_block(i, split)] -= 2.0 * log(L[i][i]);
+  double Li[D][D];
+  for (int j = 0; j < D; ++j) {
+    for (int i = 0; i < D; ++i) Li[i][j] = 0.0;
+    Li[j][j] = 1.0 / L[j][j];
+    for (int i = j + 1; i < D; ++i) {
+      double v = 0.0;
+      for (int t = j; t < i; ++t) v += L[i][t] * Li[t][j];
+      Li[i][j] = -v / L[i][i];
+    }
+  }
+  double W[D][D];
+  for (int a = 0; a < D; ++a)
+    for (int b = a; b < D; ++b) {
+      double v = 0.0;
+      for (int t = b; t < D; ++t) v += Li[t][a] * Li[t][b];
+      W[a][b] = W[b][a] = v;
+    }
+  double ElnLam_b[2] = {0.0, 0.0};
+  for (int b = 0; b < nb; ++b) {
+    ElnLam_b[b] = Db[b] * LN2 + lndet_b[b];
+    for (int i = 1; i <= Db[b]; ++i) ElnLam_b[b] += vb_digamma(0.5 * (nuv[b] + 1.0 - i));
+  }
+  const double psi_sum = vb_digamma(fr->sum_alpha_q);
+  const double psi_a = vb_digamma(alpha);
   // KL(NW(q_k) || NW(p_k)), summed over the blocks, + the per-component part of
   // KL(Dir(alpha) || Dir(alpha_p))
   const double ap = p[0];
@@ -446,7 +499,7 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     for (int b = 0; b < D; ++b) Ap[a][b] = Lp[a][b];
   if (!cholesky<D>(Lp)) {
     atomicOr(flags, FLAG_NOT_PD);
-    o.kl[k] = 0.0;
+    kl[k] = 0.0;
     return;
   }
   double lndetp_b[2] = {0.0, 0.0};
@@ -470,7 +523,7 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
             0.5 * (nu - np) * ElnLam_b[bb] - 0.5 * nu * Dd + 0.5 * nu * tr;
   }
   const double kd = -lgamma(alpha) + lgamma(ap) + (alpha - ap) * (psi_a - psi_sum);
-  o.kl[k] = klnw + kd;
+  kl[k] = klnw + kd;
 }
 
 hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
@@ -479,7 +532,7 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
   hipLaunchKernelGGL(k_alpha_part, dim3(ALPHA_BLOCKS), dim3(256), 0, s, d.prior(), d.post(), d.K, apart);
   hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(256), 0, s, apart, d.frame());
   CoefOut o{d.K, cinv, cinv ? d.at<RowBound>(L.rowb) : nullptr, d.at<float>(L.lam), d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch),
-            d.at<uint16_t>(L.cl), d.at<float>(L.nc), d.at<double>(L.kl)};
+            d.at<uint16_t>(L.cl), d.at<float>(L.nc)};
   const dim3 grid((unsigned)((L.Kpad + 127) / 128)), blk(128);
   int* fl = &d.frame()->flags;
   switch (d.D) {
@@ -495,6 +548,23 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
   if (L.fp8)
     hipLaunchKernelGGL(k_fp8_rows, dim3((unsigned)((L.Kpad + 255) / 256)), dim3(256), 0, s, d.at<float>(L.c32),
                        L.Kpad, d.at<uint8_t>(L.c8), d.at<float>(L.cs8));
+  return hipGetLastError();
+}
+
+hipError_t launch_kl(const DevPtrs& d, hipStream_t s) {
+  const Layout& L = *d.L;
+  const dim3 grid((unsigned)((d.K + 127) / 128)), blk(128);
+  switch (d.D) {
+#define VB_CASE(DD) \
+  case DD:          \
+    hipLaunchKernelGGL(k_kl<DD>, grid, blk, 0, s, d.prior(), d.post(), d.K, d.frame(), d.at<double>(L.kl), \
+                       &d.frame()->flags, d.split);                                                        \
+    break;
+    VB_CASE(1) VB_CASE(2) VB_CASE(3) VB_CASE(4) VB_CASE(5) VB_CASE(6) VB_CASE(7) VB_CASE(8)
+#undef VB_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

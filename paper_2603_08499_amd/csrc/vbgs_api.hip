@@ -41,7 +41,7 @@ struct vbgs_ctx {
   // side stream (default priority) for the component preparation, which overlaps the point
   // preparation of the culled path; made on first use
   hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr;
   int nsplit;
   float T2;
   std::string err;
@@ -395,12 +395,14 @@ static hipError_t make_side(vbgs_ctx* c) {
   hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->kl_done, hipEventDisableTiming);
   if (e != hipSuccess) {
+    if (c->kl_done) hipEventDestroy(c->kl_done);
     if (c->join) hipEventDestroy(c->join);
     if (c->fork) hipEventDestroy(c->fork);
     if (c->side) hipStreamDestroy(c->side);
     c->side = nullptr;
-    c->fork = c->join = nullptr;
+    c->fork = c->join = c->kl_done = nullptr;
   }
   return e;
 }
@@ -514,12 +516,18 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
 
 // expectations and coefficient rows; with culling the MFMA rows are written in spatial order and
 // per-tile bounds are built
-static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s) {
+// (with_kl = false: the caller launches the KL terms itself, after what the sweep needs)
+static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s, bool with_kl = true) {
   const DevPtrs d = c->dev();
-  if (!use_cull(c)) return launch_coeffs(d, s);
-  hipError_t e = launch_sort_comps(d, s);
-  if (e == hipSuccess) e = launch_coeffs(d, s, d.at<int32_t>(c->L.cinv));
-  if (e == hipSuccess) e = launch_tile_info(d, s);
+  hipError_t e;
+  if (!use_cull(c)) {
+    e = launch_coeffs(d, s);
+  } else {
+    e = launch_sort_comps(d, s);
+    if (e == hipSuccess) e = launch_coeffs(d, s, d.at<int32_t>(c->L.cinv));
+    if (e == hipSuccess) e = launch_tile_info(d, s);
+  }
+  if (e == hipSuccess && with_kl) e = launch_kl(d, s);
   return e;
 }
 
@@ -545,9 +553,12 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
     if (e == hipSuccess) {
       Phase ph(c, 1, c->side);
-      e = prepare_components(c, c->side);
+      e = prepare_components(c, c->side, false);
     }
     if (e == hipSuccess) e = hipEventRecord(c->join, c->side);
+    // the KL terms (ELBO only) beside the sweep; the caller's stream waits for them after pass 1
+    if (e == hipSuccess) e = launch_kl(d, c->side);
+    if (e == hipSuccess) e = hipEventRecord(c->kl_done, c->side);
     if (e == hipSuccess) {
       Phase ph(c, 8, s);
       e = launch_frame_prep(d, X, N, s, 1);
@@ -578,6 +589,7 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     Phase ph(c, 9, S(stream));
     e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 2);
   }
+  if (e == hipSuccess && cull) e = hipStreamWaitEvent(s, c->kl_done, 0);
   return hipfail(c, e, "pass 1");
 }
 
@@ -1010,6 +1022,7 @@ void vbgs_destroy(vbgs_ctx* c) {
     hipStreamSynchronize(c->side);
     hipEventDestroy(c->fork);
     hipEventDestroy(c->join);
+    hipEventDestroy(c->kl_done);
     hipStreamDestroy(c->side);
   }
   if (c->timers_made)

@@ -290,6 +290,8 @@ hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& in
 // part: 0 frame moments, 1 features, 2 both
 hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s, int part = 2);
 hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv = nullptr);
+// per-component KL terms of the ELBO (after launch_coeffs: it reads the frame's alpha sum)
+hipError_t launch_kl(const DevPtrs& d, hipStream_t s);
 hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s);
 hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStream_t s);
 hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, double* kappa, double* m,
