@@ -1,6 +1,6 @@
 // Per-frame preparation and per-component FP64 kernels:
 //   frame moments and quadratic point features (the per-point statistics S_u of Alg. 1),
-//   posterior -> expectations -> score coefficients (+ KL terms for the ELBO),
+//   posterior -> expectations -> score coefficients, and the KL terms of the ELBO,
 //   conjugate update (Alg. 1: S <- S + Delta S, update_from_statistics), ELBO reduction.
 #include "vbgs_internal.h"
 
@@ -489,8 +489,7 @@ __global__ __launch_bounds__(128) void k_kl(const double* __restrict__ prior, co
   }
   const double psi_sum = vb_digamma(fr->sum_alpha_q);
   const double psi_a = vb_digamma(alpha);
-  // KL(NW(q_k) || NW(p_k)), summed over the blocks, + the per-component part of
-  // KL(Dir(alpha) || Dir(alpha_p))
+  // the prior's factors, then the KL per block
   const double ap = p[0];
   double Lp[D][D];
   load_winv<D>(p, Lp);
