@@ -1117,19 +1117,19 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
       for (int g = 0; g < 4; ++g) {
         const int cnt = a.cand_n[p * 4 + g];
         const int64_t e0 = (p * 4 + g) * CS;
-        // four candidates at a time, so that their rows are fetched together
-        for (int j = 0; j < cnt; j += 4) {
-          int32_t kk[4];
+        // eight candidates at a time, so that their rows are fetched together
+        for (int j = 0; j < cnt; j += 8) {
+          int32_t kk[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) kk[u] = j + u < cnt ? a.cand_k[e0 + j + u] : -1;
-          double sc[4];
+          for (int u = 0; u < 8; ++u) kk[u] = j + u < cnt ? a.cand_k[e0 + j + u] : -1;
+          double sc[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 8; ++u) {
             double d[DT];
             sc[u] = kk[u] >= 0 ? direct_score2_dt<DT>(a.direct + (int64_t)kk[u] * a.dts, x, d) : -INFINITY;
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 8; ++u)
             if (kk[u] >= 0) {
               online_add(m, l, sc[u]);
               a.cand_s[e0 + j + u] = (float)sc[u];
