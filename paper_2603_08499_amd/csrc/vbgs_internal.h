@@ -303,7 +303,7 @@ hipError_t launch_render_marginal(const DevPtrs& model, const DevPtrs& sp, doubl
 hipError_t launch_psnr(const float* a, const float* b, int64_t n, double* out, hipStream_t s);
 hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s);
 hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t* part, hipStream_t s);
-constexpr int RX_B = 2048;  // keys per workgroup of the radix sort
+constexpr int RX_B = 1024;  // keys per workgroup of the radix sort
 hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s);
 hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s);
 hipError_t launch_reassign(const DevPtrs& d, const float* X, int64_t N, const double* lse, const double* gumbel,
