@@ -302,7 +302,11 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const unsigned long long*
 
 // sorts keys[0, n) (tmp: n keys of scratch); four passes, so the result is back in keys. The
 // component sort (comps) has scratch of its own, so that it can run beside the point sort.
-static hipError_t radix_sort32(const DevPtrs& d, unsigned long long* keys, int64_t n, hipStream_t s, bool comps) {
+// passes 8-bit digits from the top of the code (4: all 32 bits; 3: the top 24, equal keys there
+// keeping index order); *sorted is the buffer that holds the result
+static hipError_t radix_sort32(const DevPtrs& d, unsigned long long* keys, int64_t n, hipStream_t s, bool comps,
+                               int passes, unsigned long long** sorted) {
+  *sorted = keys;
   if (n <= 1) return hipSuccess;
   const Layout& L = *d.L;
   unsigned long long* tmp = d.at<unsigned long long>(comps ? L.rx2_tmp : L.rx_tmp);
@@ -312,7 +316,7 @@ static hipError_t radix_sort32(const DevPtrs& d, unsigned long long* keys, int64
   const int64_t nb = (n + RX_B - 1) / RX_B;
   unsigned long long* src = keys;
   unsigned long long* dst = tmp;
-  for (int pass = 0; pass < 4; ++pass) {
+  for (int pass = 4 - passes; pass < 4; ++pass) {
     const int shift = 32 + 8 * pass;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(256), 0, s, src, n, shift, hist, nb);
     hipError_t e = launch_excl_scan(hist, 256 * nb, off, part, s);
@@ -322,8 +326,13 @@ static hipError_t radix_sort32(const DevPtrs& d, unsigned long long* keys, int64
     src = dst;
     dst = x;
   }
+  *sorted = src;
   return hipGetLastError();
 }
+
+// the top 24 bits of the codes (cells of 1/256 of the frame extent per axis) order the tiles as well as
+// all 32 do (same sweep time) with one pass fewer on each side of the fork
+constexpr int POINT_SORT_PASSES = 3, COMP_SORT_PASSES = 3;
 
 hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipStream_t s) {
   const Layout& L = *d.L;
@@ -331,9 +340,10 @@ hipError_t launch_sort_points(const DevPtrs& d, const float* X, int64_t N, hipSt
   unsigned long long* keys = d.at<unsigned long long>(L.pkeys);
   hipLaunchKernelGGL(k_point_keys, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, N, N, d.D, d.nsp,
                      d.frame(), keys);
-  hipError_t e = radix_sort32(d, keys, N, s, false);
+  unsigned long long* sorted;
+  hipError_t e = radix_sort32(d, keys, N, s, false, POINT_SORT_PASSES, &sorted);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, keys, N,
+  hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, sorted, N,
                      d.at<int32_t>(L.porder), (int32_t*)nullptr, d.at<uint32_t>(L.pcode));
   return hipGetLastError();
 }
@@ -347,9 +357,10 @@ hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
   hipLaunchKernelGGL(k_lam_anchor, dim3(1), dim3(64), 0, s, hist, d.K, d.frame());
   hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.post(), d.K, d.K, d.D,
                      d.split, d.nsp, d.frame(), keys);
-  hipError_t e = radix_sort32(d, keys, d.K, s, true);
+  unsigned long long* sorted;
+  hipError_t e = radix_sort32(d, keys, d.K, s, true, COMP_SORT_PASSES, &sorted);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, keys, d.K,
+  hipLaunchKernelGGL(k_unpack_order, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, sorted, d.K,
                      d.at<int32_t>(L.corder), d.at<int32_t>(L.cinv), d.at<uint32_t>(L.ccode));
   return hipGetLastError();
 }
