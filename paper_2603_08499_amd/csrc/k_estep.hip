@@ -1498,6 +1498,32 @@ __device__ __forceinline__ void fx_acc(Fx128& a, double v) {
 constexpr int HEAVY = 4096;
 constexpr int SG = 32;  // lanes per component group in the statistics kernels
 
+// The statistics of component k in raw coordinates: lane f of a group of SG lanes starting at lane
+// gb holds sum f centred at the component's mean m_k (v); the group's N_k and first moments come
+// by shuffles, and x = m_k + d gives N, S1 = m N + S1', S2_ij = m_i m_j N + m_i S1'_j + m_j S1'_i + S2'_ij.
+// Every lane of the wave takes part in the shuffles; `own` lanes write.
+template <int DT>
+__device__ __forceinline__ void comp_stats_emit(const EArgs& a, int64_t k, int f, int fi, int fj, double v, int gb,
+                                                bool own) {
+  constexpr int F = 1 + DT + DT * (DT + 1) / 2;
+  const double Nk = __shfl(v, gb);
+  const double ai = __shfl(v, gb + 1 + (fi >= 0 ? fi : 0));
+  const double aj = __shfl(v, gb + 1 + (fj >= 0 ? fj : 0));
+  if (!own) return;
+  double o = v;
+  if (fi >= 0) {
+    const double mi = a.direct[k * a.dts + 1 + fi];
+    if (fj < 0) {
+      o = mi * Nk + v;
+    } else {
+      const double mj = a.direct[k * a.dts + 1 + fj];
+      o = mi * mj * Nk + mi * aj + mj * ai + v;
+    }
+  }
+  a.stats[k * F + f] = o;
+  if (a.stats_out) a.stats_out[k * F + f] = o;
+}
+
 // Components with more than HEAVY pairs, one workgroup of 256 lanes per component (the workgroup
 // of components [64 b, 64 b + 64) takes its heavy ones in turn). Each chunk of 256 pairs is scored
 // one pair per lane into LDS; then group j of SG lanes takes pairs [SG j, SG j + SG) of the chunk,
@@ -1567,7 +1593,9 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
     }
     part[grp][l] = acc;
     __syncthreads();
-    if (grp == 0 && l < F) {
+    const bool own = grp == 0 && l < F;
+    double v = 0.0;
+    if (own) {
 #pragma unroll
       for (int j = 1; j < NG; ++j) {
         const Fx128 o = part[j][l];
@@ -1575,11 +1603,11 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
         acc.hi += o.hi + (lo < o.lo ? 1 : 0);
         acc.lo = lo;
       }
-      double v = (double)acc.hi + (double)acc.lo * 5.42101086242752217e-20;
+      v = (double)acc.hi + (double)acc.lo * 5.42101086242752217e-20;
       if (fi >= 0) v = v * a.frame->s[fi];
       if (fj >= 0) v = v * a.frame->s[fj];
-      a.spart[k * FP + l] = v;
     }
+    comp_stats_emit<DT>(a, k, l, fi, fj, v, (threadIdx.x & 63) & ~(SG - 1), own);
     __syncthreads();
   }
 }
@@ -1646,12 +1674,13 @@ __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
+  double v = 0.0;
   if (mine) {  // fixed point -> FP64, undo the scaling; raw coordinates centred at m_k
-    double v = (double)acc.hi + (double)acc.lo * 5.42101086242752217e-20;
+    v = (double)acc.hi + (double)acc.lo * 5.42101086242752217e-20;
     if (fi >= 0) v = v * a.frame->s[fi];
     if (fj >= 0) v = v * a.frame->s[fj];
-    a.spart[k * FP + l] = v;
   }
+  comp_stats_emit<DT>(a, k, l, fi, fj, v, (threadIdx.x & 63) & ~(SG - 1), mine);
 }
 
 __global__ void k_zero_i32(int32_t* p, int64_t n, const int32_t* gate) {
@@ -1908,9 +1937,13 @@ hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) 
       default:
         return hipErrorInvalidValue;
     }
-  } else {
-    hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(a.spart),
-                       a.Kpad * FP, nullptr);
+  } else {  // no points: zero statistics
+    const int64_t nst = a.K * (1 + D + D * (D + 1) / 2);
+    hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(a.stats), nst,
+                       nullptr);
+    if (a.stats_out)
+      hipLaunchKernelGGL(k_zero_u64, dim3(256), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(a.stats_out),
+                         nst, nullptr);
   }
   return hipGetLastError();
 }
@@ -1936,6 +1969,8 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.lse_part = d.at<double>(L.lse_part);
   a.lse_out = lse_out;
   a.spart = d.at<double>(L.spart);
+  a.stats = d.at<double>(L.stats);
+  a.stats_out = nullptr;
   a.cand_k = d.at<int32_t>(L.cand_k);
   a.cand_s = d.at<float>(L.cand_s);
   a.cand_n = d.at<int32_t>(L.cand_n);
@@ -2029,8 +2064,10 @@ hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int
   return hipGetLastError();
 }
 
-hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s) {
-  const EArgs a = make_eargs(d, c, X, N, nullptr);
+hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s,
+                        double* stats_out) {
+  EArgs a = make_eargs(d, c, X, N, nullptr);
+  a.stats_out = stats_out;  // the exact mode writes the final statistics here and in a.stats
   if (c.prec == VBGS_FP64) {
     const dim3 grid((unsigned)((d.K + 255) / 256), (unsigned)c.nsplit);
     switch (d.D) {
@@ -2062,6 +2099,7 @@ hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int
 
 hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, hipStream_t s) {
   const int mode = c.prec == VBGS_FP64 ? 0 : (c.exact ? 2 : 1);
+  if (mode == 2) return hipSuccess;  // the exact statistics kernels wrote the final values
   const int nsplit = mode == 2 ? 1 : c.nsplit;
   const dim3 grid((unsigned)((d.K + 255) / 256));
   switch (d.D) {

@@ -606,7 +606,7 @@ vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse
   hipError_t e;
   {
     Phase ph(c, 3, S(stream));
-    e = launch_pass2(d, cfg, X, N, S(stream));
+    e = launch_pass2(d, cfg, X, N, S(stream), stats_out);
   }
   if (e == hipSuccess) {
     Phase ph(c, 4, S(stream));
@@ -909,6 +909,7 @@ vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* c, const float* X, int64_t N, cons
   }
   if (e == hipSuccess) {
     Phase ph(c, 3, s);
+    ea.stats_out = stats_out;  // final statistics written by the sparse kernels
     e = launch_sparse_stats(ea, c->p.D, N, s);
   }
   if (e == hipSuccess) {

@@ -338,6 +338,8 @@ struct EArgs {
   double* lse_part;           // pass-1 workgroups
   double* lse_out;            // N (nats) or null
   double* spart;              // nsplit x Kpad x 32
+  double* stats;              // K x F statistics (exact mode: written by the statistics kernels)
+  double* stats_out;          // the caller's copy of them, or null
   int32_t* cand_k;            // exact sweep: N x 4 x CS component indices
   float* cand_s;              // N x 4 x CS exact scores (log2 units, rounded to FP32)
   int32_t* cand_n;            // N x 4 list lengths, -1 = overflowed point
@@ -376,7 +378,9 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
 // 1 (the screening sweep) and 2 (exact per-point LSE); other modes run everything in stage 1
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
                         hipStream_t s, int stage = -1);
-hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s);
+// stats_out (or null): the caller's statistics; the exact mode writes them in pass 2 (fold is then empty)
+hipError_t launch_pass2(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, hipStream_t s,
+                        double* stats_out);
 hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, hipStream_t s);
 // exact statistics from candidate lists (transpose + per-component sums) and exact per-point LSE
 hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull = 0);
