@@ -60,10 +60,12 @@ def _separated_weights(D, K, seed, X):
 
 
 @gpu
-def test_candidates_are_a_valid_top_c(dev):
+@pytest.mark.parametrize("C", [32, 13, 48, 64])
+def test_candidates_are_a_valid_top_c(dev, C):
+    """C <= 32 starts each selection from a per-point threshold pre-pass; C > 32 selects without one."""
     X, pr = scenes.random_problem(1500, 300, 6, seed=41)
     w = scenes.mlp_init(6, 128, pr.K, 42, X)
-    m = _model(dev, pr, X.shape[0], C=32)
+    m = _model(dev, pr, X.shape[0], C=C)
     m.proposal_set(**w)
     cand = m.proposal_candidates(torch.from_numpy(X).to(dev)).cpu().numpy()
     torch.cuda.synchronize()
@@ -76,8 +78,8 @@ def test_candidates_are_a_valid_top_c(dev):
     bad = 0
     for n in range(X.shape[0]):
         S = cand[n]
-        assert (S >= 0).all() and len(set(S.tolist())) == 32 and (np.diff(S) > 0).all()
-        zc = np.sort(z[n])[-32]
+        assert (S >= 0).all() and len(set(S.tolist())) == C and (np.diff(S) > 0).all()
+        zc = np.sort(z[n])[-C]
         eps = 1e-5 * mag[n].max() + 2 ** -8 * np.abs(hb[n]).max() * np.abs(Eb).max()
         inS = np.zeros(pr.K, bool)
         inS[S] = True
@@ -86,16 +88,17 @@ def test_candidates_are_a_valid_top_c(dev):
 
 
 @gpu
-def test_pruned_statistics_match_oracle(dev):
+@pytest.mark.parametrize("C", [24, 56])
+def test_pruned_statistics_match_oracle(dev, C):
     X, pr = scenes.random_problem(2000, 400, 6, seed=43)
     w = _separated_weights(6, pr.K, 44, X)
-    m = _model(dev, pr, X.shape[0], C=24)
+    m = _model(dev, pr, X.shape[0], C=C)
     m.proposal_set(**w)
     Xg = torch.from_numpy(X).to(dev)
     lse, st, rep = m.estep_stats_pruned(Xg)
     cand = m.proposal_candidates(Xg).cpu().numpy()
     torch.cuda.synchronize()
-    order = np.argsort(-w["beta"].astype(np.float64), kind="stable")[:24]
+    order = np.argsort(-w["beta"].astype(np.float64), kind="stable")[:C]
     ref_cand = np.tile(np.sort(order), (X.shape[0], 1))
     assert (cand == ref_cand).all()
     q = R.NW.from_prior(pr)
