@@ -159,24 +159,28 @@ struct __attribute__((aligned(16))) ETile {
   float beta[CT];
 };
 
+// native vectors: the staging registers of a tile stay in VGPRs (a struct of HIP's uint4 was kept
+// in per-lane scratch memory, a store and a reload of 80 B per lane per tile)
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
 struct ETileRegs {
-  uint4 v[4];
-  uint4 b;
+  u32x4_t v[4];
+  u32x4_t b;
 };
 
 __device__ __forceinline__ void etile_fetch(ETileRegs& R, const PArgs& a, int64_t k0) {
   const int t = threadIdx.x;  // 256 threads x 4 x 16 B = 16 KB
-  const uint4* src = reinterpret_cast<const uint4*>(a.Ebf + k0 * VBGS_H);
+  const u32x4_t* src = reinterpret_cast<const u32x4_t*>(a.Ebf + k0 * VBGS_H);
 #pragma unroll
   for (int q = 0; q < 4; ++q) R.v[q] = src[t + 256 * q];
-  if (t < CT / 4) R.b = reinterpret_cast<const uint4*>(a.betap + k0)[t];
+  R.b = t < CT / 4 ? reinterpret_cast<const u32x4_t*>(a.betap + k0)[t] : u32x4_t{0u, 0u, 0u, 0u};
 }
 
 __device__ __forceinline__ void etile_store(ETile& T, const ETileRegs& R) {
   const int t = threadIdx.x;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) reinterpret_cast<uint4*>(&T.e[0][0])[t + 256 * q] = R.v[q];
-  if (t < CT / 4) reinterpret_cast<uint4*>(T.beta)[t] = R.b;
+  for (int q = 0; q < 4; ++q) reinterpret_cast<u32x4_t*>(&T.e[0][0])[t + 256 * q] = R.v[q];
+  if (t < CT / 4) reinterpret_cast<u32x4_t*>(T.beta)[t] = R.b;
 }
 
 struct HOp {
