@@ -192,44 +192,45 @@ struct __attribute__((aligned(16))) CTile {
 };
 
 // one thread's share of a coefficient tile (16 B pieces), staged in registers so the global
-// loads of tile t + 1 overlap the MFMA work on tile t
+// loads of tile t + 1 overlap the MFMA work on tile t (native vectors: a struct of HIP's uint4 was
+// kept in per-lane scratch memory)
 template <int P>
 struct TileRegs {
-  uint4 v[P == VBGS_FP32 ? 2 : (P == VBGS_BF16X3 ? 2 : 1)];
-  uint4 nc, s8;
+  u32x4 v[P == VBGS_FP32 ? 2 : (P == VBGS_BF16X3 ? 2 : 1)];
+  u32x4 nc, s8;
 };
 
 template <int P>
 __device__ __forceinline__ void tile_fetch(TileRegs<P>& R, const EArgs& a, int64_t k0) {
   const int t = threadIdx.x;  // 256 threads
   if constexpr (P == VBGS_FP32) {
-    const uint4* src = reinterpret_cast<const uint4*>(a.c32 + k0 * FP);
+    const u32x4* src = reinterpret_cast<const u32x4*>(a.c32 + k0 * FP);
     R.v[0] = src[t];
     R.v[1] = src[t + 256];
   } else if constexpr (P == VBGS_FP8) {  // 64 rows x 32 B = 128 x 16 B, scales 16 x 16 B
-    if (t < CT * FP / 16) R.v[0] = reinterpret_cast<const uint4*>(a.c8 + k0 * FP)[t];
-    if (t < CT / 4) R.s8 = reinterpret_cast<const uint4*>(a.cs8 + k0)[t];
+    R.v[0] = t < CT * FP / 16 ? reinterpret_cast<const u32x4*>(a.c8 + k0 * FP)[t] : u32x4{0u, 0u, 0u, 0u};
+    R.s8 = t < CT / 4 ? reinterpret_cast<const u32x4*>(a.cs8 + k0)[t] : u32x4{0u, 0u, 0u, 0u};
   } else {
-    R.v[0] = reinterpret_cast<const uint4*>(a.ch + k0 * FP)[t];
-    if constexpr (P == VBGS_BF16X3) R.v[1] = reinterpret_cast<const uint4*>(a.cl + k0 * FP)[t];
+    R.v[0] = reinterpret_cast<const u32x4*>(a.ch + k0 * FP)[t];
+    if constexpr (P == VBGS_BF16X3) R.v[1] = reinterpret_cast<const u32x4*>(a.cl + k0 * FP)[t];
   }
-  if (t < CT / 4) R.nc = reinterpret_cast<const uint4*>(a.nc + k0)[t];
+  R.nc = t < CT / 4 ? reinterpret_cast<const u32x4*>(a.nc + k0)[t] : u32x4{0u, 0u, 0u, 0u};
 }
 
 template <int P>
 __device__ __forceinline__ void tile_store(CTile<P>& T, const TileRegs<P>& R) {
   const int t = threadIdx.x;
   if constexpr (P == VBGS_FP32) {
-    reinterpret_cast<uint4*>(&T.c32[0][0])[t] = R.v[0];
-    reinterpret_cast<uint4*>(&T.c32[0][0])[t + 256] = R.v[1];
+    reinterpret_cast<u32x4*>(&T.c32[0][0])[t] = R.v[0];
+    reinterpret_cast<u32x4*>(&T.c32[0][0])[t + 256] = R.v[1];
   } else if constexpr (P == VBGS_FP8) {
-    if (t < CT * FP / 16) reinterpret_cast<uint4*>(&T.q8[0][0])[t] = R.v[0];
-    if (t < CT / 4) reinterpret_cast<uint4*>(T.cs8)[t] = R.s8;
+    if (t < CT * FP / 16) reinterpret_cast<u32x4*>(&T.q8[0][0])[t] = R.v[0];
+    if (t < CT / 4) reinterpret_cast<u32x4*>(T.cs8)[t] = R.s8;
   } else {
-    reinterpret_cast<uint4*>(&T.h[0][0])[t] = R.v[0];
-    if constexpr (P == VBGS_BF16X3) reinterpret_cast<uint4*>(&T.l[0][0])[t] = R.v[1];
+    reinterpret_cast<u32x4*>(&T.h[0][0])[t] = R.v[0];
+    if constexpr (P == VBGS_BF16X3) reinterpret_cast<u32x4*>(&T.l[0][0])[t] = R.v[1];
   }
-  if (t < CT / 4) reinterpret_cast<uint4*>(T.nc)[t] = R.nc;
+  if (t < CT / 4) reinterpret_cast<u32x4*>(T.nc)[t] = R.nc;
 }
 
 // Record a screened pair (its score upper bound hi) in the point's list for this lane group.
