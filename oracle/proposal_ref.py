@@ -13,8 +13,12 @@ scored against. What it computes here:
 * training loss on exact responsibility targets (renormalised over the kept pairs):
   L = sum_n [ LSE_z(n) - sum_j rbar_nj z_{n, k_j} ] / B, its gradients, and one Adam step.
 
-Parity unpinned: none (the gradients are pinned by central finite differences, top-C by a
-full argsort, captured mass by its definition through the dense responsibilities).
+Parity unpinned: none. The network and logits are pinned by a hand-worked D = 3, H = 2, K = 3
+example; the loss and its beta gradient by their closed form at zero embeddings (logits = beta);
+the remaining gradients by central finite differences of that pinned loss; Adam by two
+hand-computed steps with the default betas and by the constant-gradient identity (each step moves
+lr sign(g)); top-C by a full argsort; captured mass by its definition through the dense
+responsibilities.
 """
 from __future__ import annotations
 
