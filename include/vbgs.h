@@ -143,8 +143,11 @@ vbgs_status vbgs_query_sizes(const vbgs_params* p, size_t* state_bytes, size_t* 
 vbgs_status vbgs_init(vbgs_ctx** out, const vbgs_params* p, const double* m0, const double* W0,
                       void* state, void* workspace, void* stream);
 
-/* Attach a context to an existing state buffer (resume from a checkpoint):
- * no kernel runs; the state must come from a context with the same params. */
+/* Attach a context to an existing state buffer (resume from a checkpoint, e.g. a copy of the
+ * state of an earlier context): no kernel runs here; the state must come from a context with the
+ * same params. The workspace may hold anything: its sticky flags and counters are cleared on the
+ * stream of the first call made with the new context, before that call's own work, so that
+ * continuing from the copy gives what the uninterrupted context would have given. */
 vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void* workspace);
 
 /* E-step + sufficient statistics of one frame at the current posterior.
@@ -268,7 +271,8 @@ vbgs_status vbgs_proposal_get(vbgs_ctx* ctx, float* W1, float* b1, float* W2, fl
  * each one's captured log-mass ln sum_{k in C_n} r_nk = LSE_C(n) - LSE(n) (nats). The frame falls
  * back to the dense exact E-step when ln(mean exp(captured)) < logmass_bound or more than
  * frac_bound of the audited points lie below logmass_bound; the decision is taken on the device
- * and the dense kernels run only then (no host synchronisation). n_audit = 0 disables the audit.
+ * and the dense kernels run only then (no host synchronisation). n_audit = 0 disables the audit:
+ * the pruned statistics stand unchecked and the report reads [0, NaN, NaN, NaN].
  * report (device, 4 FP64, or NULL): [fallback 0/1, ln mean captured mass, fraction below the
  * bound, minimum captured log-mass]. Outputs as vbgs_estep_stats. */
 vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* ctx, const float* X, int64_t N, const int32_t* audit_idx,

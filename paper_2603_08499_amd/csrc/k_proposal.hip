@@ -509,7 +509,15 @@ __global__ __launch_bounds__(256) void k_audit_decide(const double* __restrict__
   }
 }
 
-__global__ void k_set_gate(int32_t* gate, int32_t v) { gate[0] = v; }
+// no audit: the pruned statistics stand (gate 0); the report's captured-mass fields read NaN so
+// that an unaudited frame cannot pass for one whose candidates captured all of the mass
+__global__ void k_no_audit(int32_t* gate, double* report) {
+  gate[0] = 0;
+  if (report) {
+    report[0] = 0.0;
+    report[1] = report[2] = report[3] = __builtin_nan("");
+  }
+}
 
 // ---------------------------------------------------------------------------
 // training targets from an exact E-step: the kept pairs with r = 2^(s - LSE)
@@ -981,7 +989,7 @@ hipError_t launch_audit(const EArgsLite& e, int D, const int32_t* idx, int64_t n
     }
     hipLaunchKernelGGL(k_audit_decide, dim3(1), dim3(256), 0, s, lse2, idx, aud, n, bound, frac, gate, report);
   } else {
-    hipLaunchKernelGGL(k_set_gate, dim3(1), dim3(1), 0, s, gate, 0);
+    hipLaunchKernelGGL(k_no_audit, dim3(1), dim3(1), 0, s, gate, report);
   }
   return hipGetLastError();
 }

@@ -38,6 +38,7 @@ struct vbgs_ctx {
   uint64_t lse_version;
   bool have_stats;
   bool order_reset;  // the sweep's block costs are not measured yet
+  bool pending_clear;  // attached to a state: the workspace's flags and counters are not cleared yet
   // side stream (default priority) for the component preparation, which overlaps the point
   // preparation of the culled path; made on first use
   hipStream_t side = nullptr;
@@ -260,7 +261,9 @@ Layout make_layout(const vbgs_params& p) {
   L.c8 = take(L.fp8 ? (size_t)L.Kpad * FP : 0);
   L.cs8 = take(L.fp8 ? (size_t)L.Kpad * 4 : 0);
   L.kl = take((size_t)K * 8);
-  L.spart = take((size_t)ns * L.Kpad * stat_stride(p.D) * 8);
+  // pass-2 partials of the FP64 path and of the plain tiers (the exact MFMA mode sums in fixed point)
+  const bool exact_mfma = p.score_prec != VBGS_FP64 && p.exact == 1;
+  L.spart = take(exact_mfma ? 0 : (size_t)ns * L.Kpad * stat_stride(p.D) * 8);
   L.stats = take((size_t)K * nfeat(p.D) * 8);
   const bool sparse = p.score_prec != VBGS_FP64;  // exact MFMA mode: candidate lists + fixed-point sums
   L.cand_k = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
@@ -419,6 +422,7 @@ static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   c->lse_version = ~(uint64_t)0;
   c->have_stats = false;
   c->order_reset = true;
+  c->pending_clear = false;
   c->timing = false;
   c->timers_made = false;
   c->prop_ready = false;
@@ -509,9 +513,25 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
     return VBGS_ERR_HIP;
   }
   c->prop_ready = p->proposal == 1;  // a proposal state carries its weights
+  c->pending_clear = true;           // done on the stream of the first call that takes one
   *out = c;
   return VBGS_OK;
 }
+
+// after vbgs_attach the workspace may hold anything: its sticky flags and counters are cleared on
+// the stream of the first call, before that call's own work
+static hipError_t settle(vbgs_ctx* c, hipStream_t s) {
+  if (!c->pending_clear) return hipSuccess;
+  const hipError_t e = launch_clear_flags(c->dev(), s);
+  if (e == hipSuccess) c->pending_clear = false;
+  return e;
+}
+
+#define VBGS_SETTLE(c, stream)                                   \
+  do {                                                           \
+    const hipError_t e_ = settle((c), S(stream));                \
+    if (e_ != hipSuccess) return hipfail((c), e_, "clear flags"); \
+  } while (0)
 
 
 // expectations and coefficient rows; with culling the MFMA rows are written in spatial order and
@@ -598,6 +618,7 @@ vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse
   if (!c) return VBGS_ERR_ARG;
   if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
   if (N > 0 && !X) return fail(c, VBGS_ERR_ARG, "X is NULL");
+  VBGS_SETTLE(c, stream);
   vbgs_status st = run_pass1(c, X, N, lse_out, stream);
   if (st != VBGS_OK) return st;
   const DevPtrs d = c->dev();
@@ -623,6 +644,7 @@ vbgs_status vbgs_update(vbgs_ctx* c, int32_t commit, void* stream) {
   if (!c) return VBGS_ERR_ARG;
   if (commit != 0 && commit != 1) return fail(c, VBGS_ERR_ARG, "commit must be 0 or 1");
   if (!c->have_stats) return fail(c, VBGS_ERR_STATE, "vbgs_update needs a preceding vbgs_estep_stats");
+  VBGS_SETTLE(c, stream);
   hipError_t e;
   {
     Phase ph(c, 5, S(stream));
@@ -635,6 +657,7 @@ vbgs_status vbgs_update(vbgs_ctx* c, int32_t commit, void* stream) {
 
 vbgs_status vbgs_elbo(vbgs_ctx* c, const float* X, int64_t N, double* elbo_dev, void* stream) {
   if (!c || !elbo_dev) return VBGS_ERR_ARG;
+  VBGS_SETTLE(c, stream);
   if (!X) {
     if (c->last_N < 0 || c->lse_version != c->post_version)
       return fail(c, VBGS_ERR_STATE, "no LSE at the current posterior: pass X");
@@ -653,12 +676,14 @@ vbgs_status vbgs_elbo(vbgs_ctx* c, const float* X, int64_t N, double* elbo_dev, 
 vbgs_status vbgs_get_params(vbgs_ctx* c, int32_t which, double* alpha, double* kappa, double* m, double* Winv,
                             double* nu, void* stream) {
   if (!c || (which != 0 && which != 1) || !alpha || !kappa || !m || !Winv || !nu) return VBGS_ERR_ARG;
+  VBGS_SETTLE(c, stream);
   return hipfail(c, launch_get_set(c->dev(), which, 0, alpha, kappa, m, Winv, nu, S(stream)), "get_params");
 }
 
 vbgs_status vbgs_set_params(vbgs_ctx* c, int32_t which, const double* alpha, const double* kappa,
                             const double* m, const double* Winv, const double* nu, void* stream) {
   if (!c || (which != 0 && which != 1) || !alpha || !kappa || !m || !Winv || !nu) return VBGS_ERR_ARG;
+  VBGS_SETTLE(c, stream);
   hipError_t e = launch_get_set(c->dev(), which, 1, (double*)alpha, (double*)kappa, (double*)m, (double*)Winv,
                                 (double*)nu, S(stream));
   if (e != hipSuccess) return hipfail(c, e, "set_params");
@@ -674,6 +699,7 @@ vbgs_status vbgs_reassign(vbgs_ctx* c, const float* X, int64_t N, const double* 
   if (N >= (1ll << 25) || c->p.K >= (1ll << 25)) return fail(c, VBGS_ERR_UNSUPPORTED, "N and K must be below 2^25");
   if (n == 0) return VBGS_OK;
   if (!X || !lse || !gumbel) return VBGS_ERR_ARG;
+  VBGS_SETTLE(c, stream);
   hipError_t e = launch_reassign(c->dev(), X, N, lse, gumbel, n, out_points, out_comps, S(stream));
   if (e != hipSuccess) return hipfail(c, e, "reassign");
   c->post_version++;
@@ -693,6 +719,8 @@ vbgs_status vbgs_render(vbgs_ctx* model, vbgs_ctx* sp, const float* Xq, int64_t 
     return fail(sp, VBGS_ERR_UNSUPPORTED, "rendering needs the FP64 path or the exact MFMA mode");
   if (Nq < 0 || Nq > sp->p.n_max) return fail(sp, VBGS_ERR_SHAPE, "Nq outside 0..n_max of the position context");
   if (!regress || (Nq > 0 && (!Xq || !colour_out))) return fail(sp, VBGS_ERR_ARG, "null buffer");
+  VBGS_SETTLE(model, stream);
+  VBGS_SETTLE(sp, stream);
   hipError_t e = launch_render_marginal(model->dev(), sp->dev(), regress, S(stream));
   if (e != hipSuccess) return hipfail(sp, e, "render marginal");
   sp->post_version++;
@@ -716,6 +744,7 @@ vbgs_status vbgs_psnr(const float* a, const float* b, int64_t n, double* out, vo
 
 vbgs_status vbgs_sync_status(vbgs_ctx* c, void* stream) {
   if (!c) return VBGS_ERR_ARG;
+  VBGS_SETTLE(c, stream);
   int32_t flags = 0;
   hipError_t e = hipStreamSynchronize(S(stream));
   if (e == hipSuccess)
@@ -729,11 +758,14 @@ vbgs_status vbgs_sync_status(vbgs_ctx* c, void* stream) {
 
 vbgs_status vbgs_clear_flags(vbgs_ctx* c, void* stream) {
   if (!c) return VBGS_ERR_ARG;
-  return hipfail(c, launch_clear_flags(c->dev(), S(stream)), "clear_flags");
+  const hipError_t e = launch_clear_flags(c->dev(), S(stream));
+  if (e == hipSuccess) c->pending_clear = false;
+  return hipfail(c, e, "clear_flags");
 }
 
 vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[10], void* stream) {
   if (!c || !out) return VBGS_ERR_ARG;
+  VBGS_SETTLE(c, stream);
   FrameInfo f;
   hipError_t e = hipStreamSynchronize(S(stream));
   if (e == hipSuccess) e = hipMemcpy(&f, (char*)c->ws + c->L.frame, sizeof f, hipMemcpyDeviceToHost);
@@ -814,6 +846,7 @@ vbgs_status vbgs_proposal_set(vbgs_ctx* c, const float* W1, const float* b1, con
                               void* stream) {
   if (!c || !W1 || !b1 || !W2 || !b2 || !E || !beta || !mu_in || !inv_s_in) return VBGS_ERR_ARG;
   if (!c->p.proposal) return fail(c, VBGS_ERR_STATE, "params.proposal is 0");
+  VBGS_SETTLE(c, stream);
   PArgs a = make_pargs(c);
   const PropOffsets o(c->p.D, c->p.K);
   const hipStream_t s = S(stream);
@@ -841,6 +874,7 @@ vbgs_status vbgs_proposal_get(vbgs_ctx* c, float* W1, float* b1, float* W2, floa
                               void* stream) {
   if (!c || !W1 || !b1 || !W2 || !b2 || !E || !beta) return VBGS_ERR_ARG;
   if (!c->p.proposal) return fail(c, VBGS_ERR_STATE, "params.proposal is 0");
+  VBGS_SETTLE(c, stream);
   PArgs a = make_pargs(c);
   const PropOffsets o(c->p.D, c->p.K);
   const hipStream_t s = S(stream);
@@ -863,6 +897,7 @@ vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* c, const float* X, int64_t N, cons
   if ((N > 0 && !X) || n_audit < 0 || n_audit > N || (n_audit > 0 && !audit_idx))
     return fail(c, VBGS_ERR_ARG, "bad X / audit arguments");
   if (!isfinite(logmass_bound) || !(frac_bound >= 0.0)) return fail(c, VBGS_ERR_ARG, "bad bounds");
+  VBGS_SETTLE(c, stream);
   const hipStream_t s = S(stream);
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, 1, c->T2, 1};
@@ -928,6 +963,7 @@ vbgs_status vbgs_proposal_candidates(vbgs_ctx* c, const float* X, int64_t N, int
   if (!c || !cand_out) return VBGS_ERR_ARG;
   if (!c->p.proposal || !c->prop_ready) return fail(c, VBGS_ERR_STATE, "the proposal has no weights");
   if (N < 0 || N > c->p.n_max || (N > 0 && !X)) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+  VBGS_SETTLE(c, stream);
   const hipStream_t s = S(stream);
   PArgs pa = make_pargs(c);
   hipError_t e = hipSuccess;
@@ -951,6 +987,7 @@ vbgs_status vbgs_export_targets(vbgs_ctx* c, int64_t N, int32_t* tk, float* tr, 
   if (!c || !tk || !tr) return VBGS_ERR_ARG;
   if (c->p.score_prec == VBGS_FP64 || !c->p.exact) return fail(c, VBGS_ERR_UNSUPPORTED, "needs the exact MFMA mode");
   if (!c->have_stats || N != c->last_N) return fail(c, VBGS_ERR_STATE, "N must match the last E-step");
+  VBGS_SETTLE(c, stream);
   EstepCfg cfg{c->p.score_prec, 1, c->T2, 1};
   const EArgs ea = make_eargs(c->dev(), cfg, nullptr, N, nullptr);
   return hipfail(c, launch_export_targets(ea, N, tk, tr, S(stream)), "export_targets");
@@ -964,6 +1001,7 @@ vbgs_status vbgs_proposal_train_step(vbgs_ctx* c, const float* X, const int32_t*
   const int64_t Bt = c->p.train_batch > 0 ? c->p.train_batch : 4096;
   if (B < 1 || B > Bt) return fail(c, VBGS_ERR_SHAPE, "B outside 1..train_batch");
   if ((apply != 0 && apply != 1) || !(lr >= 0.0f)) return fail(c, VBGS_ERR_ARG, "bad apply / lr");
+  VBGS_SETTLE(c, stream);
   PArgs a = make_pargs(c);
   if (!c->prop_prepared) {
     const hipError_t e = launch_prop_prepare(a, S(stream));

@@ -244,17 +244,23 @@ class VBGS:
                                                _stream()))
         return o
 
-    def estep_stats_pruned(self, X, audit_idx=None, bound=float(np.log1p(-1e-4)), frac=0.01, lse=True, stats=True):
+    def estep_stats_pruned(self, X, audit_idx=None, bound=float(np.log1p(-1e-4)), frac=0.01, lse=True, stats=True,
+                           audit_n=4096, audit_seed=0):
+        """Pruned E-step. audit_idx: the audited points (int32, distinct); None draws min(audit_n, N)
+        of them without replacement from a generator seeded by audit_seed; an empty sequence turns the
+        audit off (the report's captured-mass fields then read NaN)."""
         X = self._points(X)
         N = X.shape[0]
         lse_out = torch.empty(N, dtype=torch.float64, device=self.device) if lse else None
         stats_out = torch.empty((self.K, self.F), dtype=torch.float64, device=self.device) if stats else None
         report = torch.zeros(4, dtype=torch.float64, device=self.device)
-        if audit_idx is not None:
-            audit_idx = torch.as_tensor(audit_idx, dtype=torch.int32).to(self.device).contiguous()
-            na = audit_idx.numel()
-        else:
-            na = 0
+        if audit_idx is None:
+            g = np.random.default_rng(audit_seed)
+            audit_idx = np.sort(g.choice(N, size=min(int(audit_n), N), replace=False)).astype(np.int32)
+        audit_idx = torch.as_tensor(audit_idx, dtype=torch.int32).to(self.device).contiguous()
+        na = audit_idx.numel()
+        if na == 0:
+            audit_idx = None
         self._audit = audit_idx
         self._check(self.lib.vbgs_estep_stats_pruned(self.ctx, _ptr(X), N, _ptr(audit_idx), na, float(bound),
                                                      float(frac), _ptr(lse_out), _ptr(stats_out), _ptr(report),

@@ -95,9 +95,11 @@ def test_pruned_statistics_match_oracle(dev, C):
     m = _model(dev, pr, X.shape[0], C=C)
     m.proposal_set(**w)
     Xg = torch.from_numpy(X).to(dev)
-    lse, st, rep = m.estep_stats_pruned(Xg)
+    lse, st, rep = m.estep_stats_pruned(Xg, audit_idx=[])
     cand = m.proposal_candidates(Xg).cpu().numpy()
     torch.cuda.synchronize()
+    r = rep.cpu().numpy()
+    assert r[0] == 0 and np.isnan(r[1:]).all()  # unaudited: no fallback, no captured-mass claim
     order = np.argsort(-w["beta"].astype(np.float64), kind="stable")[:C]
     ref_cand = np.tile(np.sort(order), (X.shape[0], 1))
     assert (cand == ref_cand).all()
