@@ -5,8 +5,12 @@ on one MI355X, in point-component pairs per second.
 Workload (default "c3"): 640x480 back-projected RGB-D frames of a seeded scene of 10000
 anisotropic Gaussians with per-Gaussian colours and depth noise sigma 0.005, D = 6,
 N = 307200 points per frame, K = 100000 components, the posterior committed as the next
-frame's prior after every update. Frames are generated on the host, copied to HBM before
-the timed region and cycled. A step is one whole fit step over one frame.
+frame's prior after every update. Frames are generated on the host and copied to HBM before
+the timed region; every warm-up and timed step takes the next frame of the stream (frames
+0 .. warmup + steps - 1), so the timed posterior is the one a real stream reaches. A step is
+one whole fit step over one frame. After the timed loop the FP64 oracle is run on a slice of
+the following frame at the GPU's last committed posterior (teacher forcing) and the GPU's
+E-step on the same slice is compared with it; the same oracle run, timed, is the CPU baseline.
 
 Prints one JSON line. Options: --gpus N (only 1: the path runs on one GPU),
 --steps K, --warmup W, --prec, --exact, --cull, --modal-split S, --workload {c3,c2,c4,c5,search},
@@ -239,11 +243,18 @@ def run_search(args):
     print(json.dumps(out))
 
 
-def run_steps(model, Xs, steps, torch):
-    for i in range(steps):
+def run_steps(model, Xs, steps, torch, first=0):
+    for i in range(first, first + steps):
         model.estep_stats(Xs[i % len(Xs)], lse=False, stats=False)
         model.elbo()
         model.update(commit=True)
+
+
+def oracle_slice(N, n):
+    """n/2 consecutive points of the raster order (an image band) and n/2 strided over the frame."""
+    band = np.arange(n // 2) + N // 2 - n // 4
+    strided = np.linspace(0, N - 1, n - n // 2).astype(np.int64)
+    return np.unique(np.concatenate([band, strided]))
 
 
 def main():
@@ -257,7 +268,8 @@ def main():
     ap.add_argument("--cull", type=int, default=1)
     ap.add_argument("--modal-split", type=int, default=0,
                     help="s > 0: two-factor likelihood over coordinates [0, s) and [s, D) (Sec. 2.1.2)")
-    ap.add_argument("--frames", type=int, default=4)
+    ap.add_argument("--frames", type=int, default=0,
+                    help="cycle this many frames (0: a distinct frame for every step, the stream as it is)")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -289,7 +301,8 @@ def main():
     import paper_2603_08499_amd as P
 
     dev = torch.device("cuda:0")
-    frames, pr, desc = workload(args.workload, args.frames)
+    n_frames = args.frames if args.frames > 0 else args.warmup + args.steps + 1
+    frames, pr, desc = workload(args.workload, n_frames)
     N, D, K = frames[0].shape[0], pr.D, pr.K
     if args.modal_split:
         desc += "; two-factor likelihood over coordinates [0,%d) and [%d,%d)" % (args.modal_split, args.modal_split, D)
@@ -317,7 +330,6 @@ def main():
         acc = {"stats_relerr_vs_fp64_gpu": max(rel), "stats_relerr_blocks": rel,
                "lse_maxabs_vs_fp64_gpu": float((lse_f - lse_m).abs().max())}
         del mf
-    lse_m_host = lse_m.cpu().numpy()
     del mm
     torch.cuda.synchronize()
     print("bench: accuracy done", acc, file=sys.stderr, flush=True)
@@ -339,7 +351,7 @@ def main():
     model.clear_flags()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_steps(model, Xs, args.steps, torch)
+    run_steps(model, Xs, args.steps, torch, first=args.warmup)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     phases = model.timing_read()
@@ -350,6 +362,53 @@ def main():
     status = model.sync_status()
     print("bench: mixed %.3f ms/step, phases %s" % (ms, {k: round(v[0] / max(v[1], 1), 4) for k, v in
                                                         phases.items() if v[1]}), file=sys.stderr, flush=True)
+
+    # ---- teacher-forced oracle parity on the next frame, which is also the CPU baseline ---------
+    # the GPU's committed posterior (= the next frame's prior) goes to the oracle; both score a slice
+    # of the next frame over all K components; the oracle's full FP64 step on it is timed
+    cpu, orc = None, None
+    if not args.no_cpu:
+        from oracle import vbgs_ref as R
+        nxt = (args.warmup + args.steps) % len(frames)
+        idx = oracle_slice(N, min(args.cpu_points, N))
+        Xc = np.ascontiguousarray(frames[nxt][idx])
+        post, prior = model.get_params("posterior"), model.get_params("prior")
+        lse_g, st_g = model.estep_stats(torch.from_numpy(Xc).to(dev))
+        F_g = model.elbo()
+        torch.cuda.synchronize()
+        lse_g, st_g, F_g = lse_g.cpu().numpy(), st_g.cpu().numpy(), float(F_g.item())
+        c0 = time.perf_counter()
+        if args.modal_split:
+            from oracle import factorised_ref as FR
+            toq = lambda d: FR.NW2(**{k: d[k].cpu().numpy() for k in ("alpha", "kappa", "m", "Winv", "nu")},
+                                   split=args.modal_split)
+            q, p = toq(post), toq(prior)
+            e = FR.expectations(q)
+            lse_c = FR.lse(Xc, q, e)
+            F_c = FR.elbo(lse_c.sum(), q, p, e)
+            st_c = FR.stats(Xc, q, lse_c, e)
+            FR.update(p, st_c)
+            ref = st_c.packed()
+        else:
+            tonw = lambda d: R.NW(**{k: d[k].cpu().numpy() for k in ("alpha", "kappa", "m", "Winv", "nu")})
+            q, p = tonw(post), tonw(prior)
+            r = R.cavi_step(Xc, q, p)
+            lse_c, F_c, ref = r.lse, r.elbo, r.stats.packed()
+        tc = time.perf_counter() - c0
+        blocks = [(0, 1), (1, 1 + D), (1 + D, ref.shape[1])]
+        rel = [R.relerr(ref[:, i:j], st_g[:, i:j]) for i, j in blocks]
+        orc = {"stats_relerr_vs_oracle": max(rel), "stats_relerr_vs_oracle_blocks": rel,
+               "lse_maxabs_vs_oracle": float(np.abs(lse_c - lse_g).max()),
+               "elbo_relerr_vs_oracle": abs(F_g - F_c) / abs(F_c),
+               "nk_maxabs_vs_oracle": float(np.abs(ref[:, 0] - st_g[:, 0]).max()),
+               "oracle_check": "frame %d (the one after the timed stream), %d points (a raster band and a "
+                               "strided sample) x all K=%d components, at the GPU's last committed posterior"
+                               % (nxt, Xc.shape[0], K)}
+        cpu = {"value": Xc.shape[0] * K / tc, "unit": "pairs/s", "cores": int(R.lib().oracle_threads()),
+               "kind": "oracle",
+               "sample": "the same %d points x all K=%d components, one full FP64 step (expectations, LSE, "
+                         "statistics with centred scatter, update, ELBO) in %.1f s" % (Xc.shape[0], K, tc)}
+        print("bench: oracle %.1f s, %s" % (tc, orc), file=sys.stderr, flush=True)
 
     # ---- reassignment step (Alg. 1, `reassign`), after the timed loop -------------------------
     reas = None
@@ -402,41 +461,19 @@ def main():
             "dense_equivalent_tflops": 2.0 * F * N * K / t_dom / 1e12,
             "pairs_rescored_pass1": cnt["refined_pass1"], "pairs_rescored_pass2": cnt["refined_pass2"]}
 
-    # ---- CPU baseline: the oracle on a bounded sample --------------------------------------------
-    cpu = None
-    if not args.no_cpu:
-        from oracle import vbgs_ref as R
-        ns = min(args.cpu_points, N)
-        idx = np.linspace(0, N - 1, ns).astype(np.int64)
-        Xc = frames[0][idx]
-        c0 = time.perf_counter()
-        if args.modal_split:
-            from oracle import factorised_ref as FR
-            p = FR.NW2.from_prior(pr, args.modal_split)
-            e = FR.expectations(p)
-            lse_c = FR.lse(Xc, p, e)
-            FR.elbo(lse_c.sum(), p, p, e)
-            FR.update(p, FR.stats(Xc, p, lse_c, e))
-        else:
-            p = R.NW.from_prior(pr)
-            lse_c = R.cavi_step(Xc, p, p).lse
-        tc = time.perf_counter() - c0
-        cpu = {"value": ns * K / tc, "unit": "pairs/s", "cores": int(R.lib().oracle_threads()), "kind": "oracle",
-               "sample": "%d evenly strided points of frame 0 x all K=%d components, one full FP64 step "
-                         "(expectations, LSE, statistics with centred scatter, update, ELBO) in %.1f s"
-                         % (ns, K, tc),
-               "lse_maxabs_vs_gpu_mixed": float(np.abs(lse_c - lse_m_host[idx]).max())}
-        print("bench: cpu oracle %.1f s" % tc, file=sys.stderr, flush=True)
-
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": args.prec + ("+f64" if args.exact else ""), "data": "synthetic",
            "config": {"workload": desc, "N": N, "K": K, "D": D, "score_prec": args.prec, "cull": args.cull,
-                      "modal_split": args.modal_split, "exact": bool(args.exact), "frames_cycled": args.frames},
+                      "modal_split": args.modal_split, "exact": bool(args.exact), "frames_cycled": args.frames,
+                      "frames": "%d distinct" % (args.warmup + args.steps) if args.frames <= 0 else
+                                "%d cycled" % args.frames},
            "phase_ms": {k: round(v, 5) for k, v in avg.items()},
            "fp64_gpu": fp64, "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
            "device_status": status, "roofline": roof, "cpu_baseline": cpu, "reassign": reas}
     out.update(acc)
+    if orc:
+        out.update(orc)
     print(json.dumps(out))
 
 
