@@ -160,6 +160,28 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
 vbgs_status vbgs_estep_stats(vbgs_ctx* ctx, const float* X, int64_t N, double* lse_out,
                              double* stats_out, void* stream);
 
+/* For callers that cannot allocate device memory or must not touch the context's workspace while
+ * they run (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * vbgs_estep_stats with, as its workspace, a static device array of VBGS_SCRATCH_BYTES inside the
+ * library instead of the context's workspace. Same kernels and launches, same results (bitwise).
+ * Allocates nothing: the array is part of the library's code object, one per GPU, held from the
+ * library's first use on that GPU until the process ends; its device address is looked up (not
+ * allocated) when a context is made.
+ *   X, N, lse_out, stats_out: as vbgs_estep_stats (caller-owned inputs and outputs).
+ *   The context's workspace and bookkeeping do not change: these statistics are not kept for
+ *   vbgs_update, vbgs_elbo(X = NULL) and vbgs_counters do not see this call; the sticky device
+ *   flags it raises are added to the context's (vbgs_sync_status reports them).
+ * Errors: VBGS_ERR_SHAPE (with the sizes in vbgs_last_error) when the params' workspace
+ * (vbgs_query_sizes) exceeds VBGS_SCRATCH_BYTES, e.g. D = 6 exact mode with N = 30000 and
+ * K = 4000 fits, c3's N = 307200, K = 100000 does not; VBGS_ERR_HIP if the array's address could
+ * not be found. Every call on one GPU, from any context, uses the same array, which keeps the last
+ * call's contents (each call clears what must start at zero): calls that overlap in time on one
+ * GPU within a process (different streams or threads, any contexts on that device) race and corrupt each
+ * other's results; order them on one stream. */
+#define VBGS_SCRATCH_BYTES ((size_t)64 << 20)
+vbgs_status vbgs_estep_stats_scratch(vbgs_ctx* ctx, const float* X, int64_t N, double* lse_out,
+                                     double* stats_out, void* stream);
+
 /* Conjugate update: posterior <- frame prior (+) the last statistics
  * (alpha += N_k, kappa += N_k, nu += N_k, kappa m += S1_k,
  * W^{-1} + kappa m m^T += S2_k). commit = 1 then copies the posterior into the

@@ -13,6 +13,7 @@ STATUS = {0: "VBGS_OK", -1: "VBGS_ERR_ARG", -2: "VBGS_ERR_SHAPE", -3: "VBGS_ERR_
 NPHASE = 10
 PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "proposal", "sort", "lse"]
 H = 128
+SCRATCH_BYTES = 64 << 20  # VBGS_SCRATCH_BYTES
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4, "fp8": 5}
 
 
@@ -48,6 +49,7 @@ def load():
         "vbgs_init": (i32, [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp]),
         "vbgs_attach": (i32, [ctypes.POINTER(vp), P, vp, vp]),
         "vbgs_estep_stats": (i32, [vp, vp, i64, vp, vp, vp]),
+        "vbgs_estep_stats_scratch": (i32, [vp, vp, i64, vp, vp, vp]),
         "vbgs_update": (i32, [vp, i32, vp]),
         "vbgs_elbo": (i32, [vp, vp, i64, vp, vp]),
         "vbgs_get_params": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),

@@ -879,4 +879,11 @@ hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_merge_flags(const FrameInfo* src, FrameInfo* dst) { dst->flags |= src->flags; }
+
+hipError_t launch_merge_flags(const FrameInfo* src, FrameInfo* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_flags, dim3(1), dim3(1), 0, s, src, dst);
+  return hipGetLastError();
+}
+
 }  // namespace vbgs

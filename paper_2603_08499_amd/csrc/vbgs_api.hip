@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -45,6 +46,8 @@ struct vbgs_ctx {
   hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr;
   int nsplit;
   float T2;
+  void* scratch = nullptr;  // device address of this device's static scratch (vbgs_estep_stats_scratch)
+  std::string scratch_err;
   std::string err;
   DevPtrs dev() const { return DevPtrs{(char*)ws, (double*)state, &L, p.D, p.K, p.modal_split, cull_ns()}; }
   // leading coordinates of the culling bounds: the spatial block of the two-factor model, the pixel
@@ -410,6 +413,46 @@ static hipError_t make_side(vbgs_ctx* c) {
   return e;
 }
 
+// ---- static scratch for callers that cannot allocate ----------------------------------------
+// One array per GPU in the library's code object, held until the process ends. In host code its
+// name stands for a host-side shadow, not a device address: the address of each GPU's copy is
+// looked up once per device with that device current, and only that address is ever used.
+static __device__ __align__(256) unsigned char scratch[VBGS_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEV];
+}  // namespace
+
+// device address of the current device's scratch (cached per device)
+static hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// looked up when a context is made (the device current then is the context's); a failure only
+// disables vbgs_estep_stats_scratch for this context, and is cleared from HIP's last-error state
+static void find_scratch(vbgs_ctx* c) {
+  const hipError_t e = scratch_address(&c->scratch);
+  if (e != hipSuccess) {
+    c->scratch = nullptr;
+    c->scratch_err = hipGetErrorString(e);
+    (void)hipGetLastError();
+  }
+}
+
 static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   vbgs_ctx* c = new (std::nothrow) vbgs_ctx();
   if (!c) return nullptr;
@@ -486,6 +529,7 @@ vbgs_status vbgs_init(vbgs_ctx** out, const vbgs_params* p, const double* m0, co
   in.split = p->modal_split;
   vbgs_ctx* c = new_ctx(p, state, workspace);
   if (!c) return VBGS_ERR_ARG;
+  find_scratch(c);
   hipError_t e = make_side(c);
   if (e != hipSuccess) {
     delete c;
@@ -508,6 +552,7 @@ vbgs_status vbgs_attach(vbgs_ctx** out, const vbgs_params* p, void* state, void*
   if (!out || !state || !workspace || !aligned(state) || !aligned(workspace)) return VBGS_ERR_ARG;
   vbgs_ctx* c = new_ctx(p, state, workspace);
   if (!c) return VBGS_ERR_ARG;
+  find_scratch(c);
   if (make_side(c) != hipSuccess) {
     delete c;
     return VBGS_ERR_HIP;
@@ -613,12 +658,9 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   return hipfail(c, e, "pass 1");
 }
 
-vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, double* stats_out,
-                             void* stream) {
-  if (!c) return VBGS_ERR_ARG;
-  if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
-  if (N > 0 && !X) return fail(c, VBGS_ERR_ARG, "X is NULL");
-  VBGS_SETTLE(c, stream);
+// E-step + statistics into the workspace the context points at (c->ws)
+static vbgs_status estep_body(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, double* stats_out,
+                              void* stream) {
   vbgs_status st = run_pass1(c, X, N, lse_out, stream);
   if (st != VBGS_OK) return st;
   const DevPtrs d = c->dev();
@@ -633,11 +675,49 @@ vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse
     Phase ph(c, 4, S(stream));
     e = launch_fold(d, cfg, stats_out, S(stream));
   }
-  if (e != hipSuccess) return hipfail(c, e, "pass 2");
+  return hipfail(c, e, "pass 2");
+}
+
+vbgs_status vbgs_estep_stats(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, double* stats_out,
+                             void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+  if (N > 0 && !X) return fail(c, VBGS_ERR_ARG, "X is NULL");
+  VBGS_SETTLE(c, stream);
+  const vbgs_status st = estep_body(c, X, N, lse_out, stats_out, stream);
+  if (st != VBGS_OK) return st;
   c->last_N = N;
   c->lse_version = c->post_version;
   c->have_stats = true;
   return VBGS_OK;
+}
+
+vbgs_status vbgs_estep_stats_scratch(vbgs_ctx* c, const float* X, int64_t N, double* lse_out, double* stats_out,
+                                     void* stream) {
+  if (!c) return VBGS_ERR_ARG;
+  if (N < 0 || N > c->p.n_max) return fail(c, VBGS_ERR_SHAPE, "N outside 0..n_max");
+  if (N > 0 && !X) return fail(c, VBGS_ERR_ARG, "X is NULL");
+  if (c->L.total > VBGS_SCRATCH_BYTES) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "these params need a %zu-byte workspace; the static scratch holds %zu bytes",
+             c->L.total, (size_t)VBGS_SCRATCH_BYTES);
+    return fail(c, VBGS_ERR_SHAPE, buf);
+  }
+  if (!c->scratch) return fail(c, VBGS_ERR_HIP, "static scratch unavailable: " + c->scratch_err);
+  VBGS_SETTLE(c, stream);
+  // the same launches as vbgs_estep_stats with the scratch as the workspace; the context's own
+  // workspace and bookkeeping are left as they were
+  void* const ws = c->ws;
+  const bool order_reset = c->order_reset;
+  c->ws = c->scratch;
+  c->order_reset = true;  // block costs in the scratch may come from another context
+  const DevPtrs sd = c->dev();
+  hipError_t e = launch_clear_flags(sd, S(stream));  // flags and counters start at zero
+  vbgs_status st = e == hipSuccess ? estep_body(c, X, N, lse_out, stats_out, stream) : hipfail(c, e, "scratch");
+  c->ws = ws;
+  c->order_reset = order_reset;
+  if (st != VBGS_OK) return st;
+  return hipfail(c, launch_merge_flags(sd.frame(), c->dev().frame(), S(stream)), "scratch flags");
 }
 
 vbgs_status vbgs_update(vbgs_ctx* c, int32_t commit, void* stream) {

@@ -297,6 +297,8 @@ hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStr
 hipError_t launch_get_set(const DevPtrs& d, int which, int set, double* alpha, double* kappa, double* m,
                           double* Winv, double* nu, hipStream_t s);
 hipError_t launch_clear_flags(const DevPtrs& d, hipStream_t s);
+// dst->flags |= src->flags (sticky device flags of one workspace added to another's)
+hipError_t launch_merge_flags(const FrameInfo* src, FrameInfo* dst, hipStream_t s);
 // rendering: the position marginal of the model's posterior written into the s-dimensional state
 // of sp, and reg[k] = [m_c, B]; the colour at query positions from sp's first pass
 hipError_t launch_render_marginal(const DevPtrs& model, const DevPtrs& sp, double* reg, hipStream_t s);

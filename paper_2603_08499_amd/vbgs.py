@@ -134,6 +134,19 @@ class VBGS:
                                               _ptr(stats_out if stats else None), _stream()))
         return (lse_out if lse else None), (stats_out if stats else None)
 
+    def estep_stats_scratch(self, X, lse=True, stats=True, lse_out=None, stats_out=None):
+        """estep_stats with the library's static scratch as the workspace (allocates nothing on the
+        device when lse_out / stats_out are given); the context's own statistics are left unchanged."""
+        X = self._points(X)
+        N = X.shape[0]
+        if lse and lse_out is None:
+            lse_out = torch.empty(N, dtype=torch.float64, device=self.device)
+        if stats and stats_out is None:
+            stats_out = torch.empty((self.K, self.F), dtype=torch.float64, device=self.device)
+        self._check(self.lib.vbgs_estep_stats_scratch(self.ctx, _ptr(X), N, _ptr(lse_out if lse else None),
+                                                      _ptr(stats_out if stats else None), _stream()))
+        return (lse_out if lse else None), (stats_out if stats else None)
+
     def update(self, commit=False):
         self._check(self.lib.vbgs_update(self.ctx, 1 if commit else 0, _stream()))
 
