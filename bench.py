@@ -51,23 +51,37 @@ def workload(name, n_frames):
 
 
 def run_c4(args):
-    """Learned-proposal workload (c4): c3 frames; frames 0..n_exact-1 run the exact E-step and give
-    training targets, the network is trained on them, then the timed frames run the pruned E-step
-    (top-C candidates, audit of 4096 seeded points, dense fallback on the device when the captured
-    log-mass falls below ln(1 - 1e-4)); the exact E-step on the same frames and state is timed beside it."""
+    """Learned-proposal workload (c4): a c3 stream (or, with --c4-scene c2, the c2 stream at
+    K = 10000); frames 0..n_exact-1 run the exact E-step and give training targets, the network is
+    trained on them, then every timed frame runs the pruned E-step (top-C candidates, audit of 4096
+    seeded points, dense fallback on the device when the captured log-mass falls below
+    ln(1 - 1e-4)), the ELBO and the committed update. A frame that falls back gives its exact
+    responsibilities as more training data and, with --c4-retrain, that many fine-tuning steps
+    (outside the frame's time). The exact E-step over the same frames from the same state is timed
+    beside it. After the stream, the next frame is checked against the oracle at the GPU's
+    committed posterior: the pruned statistics of a slice against the oracle's exact ones (the
+    approximation error) and against the oracle's pruned E-step on the GPU's candidates (parity)."""
     import torch
     import paper_2603_08499_amd as P
     from paper_2603_08499_amd import driver
     from synth import scenes
     dev = torch.device("cuda:0")
     n_ex, n_t = args.c4_exact, args.steps
-    scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
-    frames = [scenes.c3_frame(t, scene=scene) for t in range(n_ex + n_t)]
-    pr = scenes.c3_prior(frames[0])
+    if args.c4_scene == "c2":
+        scene = scenes.gauss_scene(2, 2000, 0.005, 0.05)
+        frames = [scenes.c2_frame(t, scene=scene) for t in range(n_ex + n_t + 1)]
+        pr = scenes.c2_prior(frames[0])
+        wdesc = "c2 stream (N=200000, K=10000, sliding window)"
+    else:
+        scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
+        frames = [scenes.c3_frame(t, scene=scene) for t in range(n_ex + n_t + 1)]
+        pr = scenes.c3_prior(frames[0])
+        wdesc = "c3 stream (N=307200, K=100000)"
     N, D, K, C = frames[0].shape[0], pr.D, pr.K, args.c4_C
     Xs = [torch.from_numpy(f).to(dev) for f in frames]
-    m = P.VBGS(D, K, N, pr.m0, pr.W0, device=dev, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
-               score_prec=args.prec, exact=True, proposal=True, C=C, train_batch=4096)
+    kw = dict(kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0, score_prec=args.prec, exact=True, proposal=True,
+              C=C, train_batch=4096, proposal_prec=args.c4_logits)
+    m = P.VBGS(D, K, N, pr.m0, pr.W0, device=dev, **kw)
     m.proposal_set(**scenes.mlp_init(D, 128, K, 3, frames[0]))
     print("bench c4: %d exact frames" % n_ex, file=sys.stderr, flush=True)
     driver.run_stream(m, Xs[:n_ex], n_exact=n_ex, train_steps=0)
@@ -83,45 +97,110 @@ def run_c4(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     state = m.state.clone()  # the exact comparator starts from the same posterior
-    logs = []
+    reps, t_fr, t_re = [], [], 0.0
     m.timing(True)
-    m.timing_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    phases = {}
     for i in range(n_t):
+        X = Xs[n_ex + i]
         g = np.random.default_rng([11, i])
-        idx = np.sort(g.choice(N, size=4096, replace=False)).astype(np.int32)
-        _, _, rep = m.estep_stats_pruned(Xs[n_ex + i], audit_idx=idx, lse=False, stats=False)
+        idx = np.sort(g.choice(N, size=min(4096, N), replace=False)).astype(np.int32)
+        m.timing_read()  # discards what fine-tuning recorded
+        t0 = time.perf_counter()
+        _, _, rep = m.estep_stats_pruned(X, audit_idx=idx, lse=False, stats=False)
         m.elbo()
         m.update(commit=True)
-        logs.append(rep)
-    torch.cuda.synchronize()
-    t_pruned = (time.perf_counter() - t0) / n_t
-    phases = m.timing_read()
-    reps = np.stack([r.cpu().numpy() for r in logs])
-    mx = P.VBGS(D, K, N, None, None, device=dev, state=state, kappa0=pr.kappa0, nu0=pr.nu0, alpha0=pr.alpha0,
-                score_prec=args.prec, exact=True, proposal=True, C=C, train_batch=4096)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+        torch.cuda.synchronize()
+        t_fr.append(time.perf_counter() - t0)
+        for k, v in m.timing_read().items():  # this frame's phases only
+            a0, a1 = phases.get(k, (0.0, 0))
+            phases[k] = (a0 + v[0], a1 + v[1])
+        r = rep.cpu().numpy()
+        reps.append(r)
+        if r[0] and args.c4_retrain > 0:  # the fallback ran the exact E-step: its pairs are targets
+            r0 = time.perf_counter()
+            data.append((X, *m.export_targets(N)))
+            driver.train_on_targets(m, data, args.c4_retrain, 4096, 1e-3, 100 + i)
+            torch.cuda.synchronize()
+            t_re += time.perf_counter() - r0
+    m.timing(False)
+    reps = np.stack(reps)
+    print("bench c4: pruned frames done, fallback rate %.3f" % reps[:, 0].mean(), file=sys.stderr, flush=True)
+    mx = P.VBGS(D, K, N, None, None, device=dev, state=state, **kw)
+    t_ex = []
     for i in range(n_t):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         mx.estep_stats(Xs[n_ex + i], lse=False, stats=False)
         mx.elbo()
         mx.update(commit=True)
-    torch.cuda.synchronize()
-    t_exact = (time.perf_counter() - t0) / n_t
+        torch.cuda.synchronize()
+        t_ex.append(time.perf_counter() - t0)
+    del mx
+    # teacher-forced check on the next frame: pruned statistics of a slice at the committed posterior
+    orc = None
+    if not args.no_cpu:
+        from oracle import proposal_ref as PR
+        from oracle import vbgs_ref as R
+        idx = oracle_slice(N, min(args.cpu_points, N))
+        Xc = np.ascontiguousarray(frames[n_ex + n_t][idx])
+        Xg = torch.from_numpy(Xc).to(dev)
+        post = m.get_params("posterior")
+        lse_g, st_g, _ = m.estep_stats_pruned(Xg, audit_idx=[])
+        cand = m.proposal_candidates(Xg)
+        torch.cuda.synchronize()
+        lse_g, st_g, cand = lse_g.cpu().numpy(), st_g.cpu().numpy(), cand.cpu().numpy()
+        q = R.NW(**{k: post[k].cpu().numpy() for k in ("alpha", "kappa", "m", "Winv", "nu")})
+        e = R.expectations(q)
+        c0 = time.perf_counter()
+        ls = R.lse(Xc, q, e)
+        ex = R.stats(Xc, q, ls, e, scatter=False).packed()
+        tc = time.perf_counter() - c0
+        lse_p, pst = PR.pruned_estep(Xc, q, cand, e)
+        pp = pst.packed()
+        blocks = [(0, 1), (1, 1 + D), (1 + D, ex.shape[1])]
+        cap = PR.captured_log_mass(lse_p, ls)
+        orc = {"pruned_stats_relerr_vs_oracle_exact": max(R.relerr(ex[:, i:j], st_g[:, i:j]) for i, j in blocks),
+               "pruned_stats_relerr_vs_oracle_pruned": max(R.relerr(pp[:, i:j], st_g[:, i:j]) for i, j in blocks),
+               "pruned_lse_maxabs_vs_oracle_pruned": float(np.abs(lse_p - lse_g).max()),
+               "slice_ln_mean_captured": float(np.log(np.mean(np.exp(cap)))),
+               "slice_below_bound_fraction": float(np.mean(cap < np.log1p(-1e-4))),
+               "oracle_check": "frame %d (after the stream), %d points (a raster band and a strided sample), "
+                               "at the GPU's committed posterior, no audit (the pruned statistics as they are)"
+                               % (n_ex + n_t, Xc.shape[0]),
+               "oracle_s": tc}
+        print("bench c4: oracle %s" % orc, file=sys.stderr, flush=True)
     avg = {k: v[0] / v[1] for k, v in phases.items() if v[1]}
+    t_pruned, t_exact = float(np.mean(t_fr)), float(np.mean(t_ex))
+    # the proposal phase (network forward, h2 rows to e4m3 for FP8, the two logits passes over all
+    # K, the top-C merge): its logits contractions are 2 passes x 2 N Kpad 128 flops
+    kpad = (K + 63) // 64 * 64
+    lflops = 2 * 2.0 * N * kpad * 128
+    lpeak = PEAK["fp8"] if args.c4_logits == "fp8" else PEAK["bf16"]
+    t_prop = avg.get("proposal", 0.0) * 1e-3
+    logits_roof = {"bound": "mfma", "kernels": "proposal phase (k_mlp_fwd, k_topc_thresh, k_logits_topc, "
+                   "k_topc_merge%s)" % (", k_rows128_fp8" if args.c4_logits == "fp8" else ""),
+                   "precision": args.c4_logits, "flops_per_frame": lflops, "phase_ms": t_prop * 1e3,
+                   "achieved": lflops / t_prop / 1e12 if t_prop > 0 else None, "peak": lpeak / 1e12,
+                   "unit": "TFLOP/s", "frac": lflops / t_prop / lpeak if t_prop > 0 else None}
     value = N * K / t_pruned
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": n_t, "warmup": n_ex,
            "ms_per_step": t_pruned * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16+f64", "data": "synthetic",
-           "config": {"workload": "c4: c3 frames with the learned top-C proposal; %d exact training frames, "
-                                  "%d pruned frames, C=%d, audit 4096, bound ln(1-1e-4)" % (n_ex, n_t, C),
-                      "N": N, "K": K, "D": D, "C": C},
+           "dtype": "%s+f64" % args.c4_logits, "data": "synthetic",
+           "config": {"workload": "c4: %s with the learned top-C proposal; %d exact training frames, %d pruned "
+                                  "frames, C=%d, %s logits, audit 4096, bound ln(1-1e-4)"
+                                  % (wdesc, n_ex, n_t, C, args.c4_logits),
+                      "N": N, "K": K, "D": D, "C": C, "logits": args.c4_logits},
            "pairs_per_s_candidates": N * C / t_pruned, "exact_ms_per_step": t_exact * 1e3,
+           "pruned_ms_per_frame": [round(x * 1e3, 3) for x in t_fr],
+           "exact_ms_per_frame": [round(x * 1e3, 3) for x in t_ex],
            "speedup_vs_exact": t_exact / t_pruned, "fallback_rate": float(reps[:, 0].mean()),
+           "fallback_frames": [int(i) for i in np.nonzero(reps[:, 0])[0]],
            "ln_captured_mass": reps[:, 1].tolist(), "below_bound_fraction": reps[:, 2].tolist(),
-           "train_steps": steps, "train_s": t_train, "train_loss_first_last": [losses[0], losses[-1]] if losses else None,
-           "phase_ms": {k: round(v, 5) for k, v in avg.items()}}
+           "train_steps": steps, "train_s": t_train, "retrain_steps_per_fallback": args.c4_retrain,
+           "retrain_s": t_re, "train_loss_first_last": [losses[0], losses[-1]] if losses else None,
+           "phase_ms": {k: round(v, 5) for k, v in avg.items()}, "logits_roofline": logits_roof}
+    if orc:
+        out.update(orc)
     print(json.dumps(out))
 
 
@@ -283,7 +362,11 @@ def main():
     ap.add_argument("--c5-prec", default="auto", help="screen precision of --workload c5")
     ap.add_argument("--c5-cpu-pixels", type=int, default=2048)
     ap.add_argument("--c4-exact", type=int, default=10)
-    ap.add_argument("--c4-train-steps", type=int, default=1500)
+    ap.add_argument("--c4-train-steps", type=int, default=15000)
+    ap.add_argument("--c4-retrain", type=int, default=500,
+                    help="fine-tuning steps after a frame that fell back (untimed)")
+    ap.add_argument("--c4-scene", default="c3", help="c3 (K=100000) or c2 (K=10000)")
+    ap.add_argument("--c4-logits", default="bf16", help="precision of the proposal's logits: bf16 or fp8")
     ap.add_argument("--c4-C", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -116,7 +116,12 @@ typedef struct {
                               u, v, r, g, b) and min(D, 3) otherwise. Any choice gives the same
                               results; coordinates with a much weaker precision than the others
                               only loosen the bounds (slower). */
-  int32_t reserved0;       /* must be zero */
+  int32_t proposal_prec;   /* precision of the proposal's logits h2 . E_k: 0 or VBGS_BF16 (default):
+                              v_mfma_f32_16x16x32_bf16, four per 16 x 16 block; VBGS_FP8: every h2 row
+                              and embedding row scaled by the power of two that puts its largest
+                              magnitude in [224, 448], rounded to OCP e4m3 (nearest even), one
+                              v_mfma_scale_f32_16x16x128_f8f6f4 per block (block scales 1), the two
+                              row factors undone on the FP32 products. Training stays BF16. */
   int64_t reserved[3];     /* must be zero */
 } vbgs_params;
 

@@ -24,7 +24,7 @@ class Params(ctypes.Structure):
                 ("screen_margin", ctypes.c_double), ("n_split", ctypes.c_int32), ("proposal", ctypes.c_int32),
                 ("C", ctypes.c_int32), ("train_batch", ctypes.c_int32), ("cull", ctypes.c_int32),
                 ("modal_split", ctypes.c_int32), ("cull_dims", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved", ctypes.c_int64 * 3)]
+                ("proposal_prec", ctypes.c_int32), ("reserved", ctypes.c_int64 * 3)]
 
 
 _lib = None

@@ -209,55 +209,181 @@ __device__ __forceinline__ f32x4 mfma_h(const HOp& A, const HOp& B) {
   return acc;
 }
 
+// ---- FP8 logits: OCP e4m3 operands, the whole depth 128 in one v_mfma_scale_f32_16x16x128_f8f6f4 ----
+// Each embedding row and each point's h2 row is scaled by the power of two that puts its largest
+// magnitude in [224, 448] (k_rows128_fp8); the MFMA's block scales stay 1 (E8M0 127) and the two row
+// factors are undone on the FP32 products: z = acc * sh_n * se_k + beta_k. Lane group g holds
+// contraction slots [32 g, 32 g + 32) of both operands (the same slots on both sides, so the
+// unit's order of the 32 bytes within a lane does not matter).
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+
+struct __attribute__((aligned(16))) ETile8 {
+  uint8_t e[CT][VBGS_H];  // 8 KB
+  float beta[CT];
+  float se[CT];  // factors undoing each row's scaling
+};
+
+struct ETile8Regs {
+  u32x4_t v[2];
+  u32x4_t b;  // threads 0..15: beta, 16..31: se
+};
+
+__device__ __forceinline__ void etile8_fetch(ETile8Regs& R, const PArgs& a, int64_t k0) {
+  const int t = threadIdx.x;  // 256 threads x 2 x 16 B = 8 KB
+  const u32x4_t* src = reinterpret_cast<const u32x4_t*>(a.E8 + k0 * VBGS_H);
+#pragma unroll
+  for (int q = 0; q < 2; ++q) R.v[q] = src[t + 256 * q];
+  R.b = t < CT / 4 ? reinterpret_cast<const u32x4_t*>(a.betap + k0)[t]
+                   : (t < CT / 2 ? reinterpret_cast<const u32x4_t*>(a.sE + k0)[t - CT / 4] : u32x4_t{0u, 0u, 0u, 0u});
+}
+
+__device__ __forceinline__ void etile8_store(ETile8& T, const ETile8Regs& R) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) reinterpret_cast<u32x4_t*>(&T.e[0][0])[t + 256 * q] = R.v[q];
+  if (t < CT / 4) reinterpret_cast<u32x4_t*>(T.beta)[t] = R.b;
+  else if (t < CT / 2) reinterpret_cast<u32x4_t*>(T.se)[t - CT / 4] = R.b;
+}
+
+__device__ __forceinline__ v8i_t load_h8(const uint8_t* row, int g) {
+  return *reinterpret_cast<const v8i_t*>(row + 32 * g);
+}
+
+__device__ __forceinline__ f32x4 mfma_h8(const v8i_t& A, const v8i_t& B) {
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(A, B, zero, 0, 0, 0, 127, 0, 127);
+}
+
+// the logits passes over either operand precision
+template <bool F8>
+struct Logits;
+
+template <>
+struct Logits<false> {
+  typedef ETile Tile;
+  typedef ETileRegs Regs;
+  typedef HOp Op;
+  static __device__ __forceinline__ void fetch(Regs& R, const PArgs& a, int64_t k0) { etile_fetch(R, a, k0); }
+  static __device__ __forceinline__ void store(Tile& T, const Regs& R) { etile_store(T, R); }
+  static __device__ __forceinline__ Op point(const PArgs& a, int64_t p, int g) { return load_h(a.h2b + p * VBGS_H, g); }
+  static __device__ __forceinline__ Op zero() { return zero_h(); }
+  static __device__ __forceinline__ float pscale(const PArgs&, int64_t) { return 1.0f; }
+  static __device__ __forceinline__ Op row(const Tile& T, int r, int g) { return load_h(&T.e[r][0], g); }
+  // logits of rows 16 cb + 4 g + i (i < 4) of the tile for the lane's point
+  static __device__ __forceinline__ void logits(const Tile& T, int cb, int g, const Op& A, const Op& B, float,
+                                                float* z) {
+    const f32x4 zz = mfma_h(A, B);
+    const f32x4 bt = *reinterpret_cast<const f32x4*>(&T.beta[cb * 16 + 4 * g]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = zz[i] + bt[i];
+  }
+};
+
+template <>
+struct Logits<true> {
+  typedef ETile8 Tile;
+  typedef ETile8Regs Regs;
+  typedef v8i_t Op;
+  static __device__ __forceinline__ void fetch(Regs& R, const PArgs& a, int64_t k0) { etile8_fetch(R, a, k0); }
+  static __device__ __forceinline__ void store(Tile& T, const Regs& R) { etile8_store(T, R); }
+  static __device__ __forceinline__ Op point(const PArgs& a, int64_t p, int g) { return load_h8(a.h8 + p * VBGS_H, g); }
+  static __device__ __forceinline__ Op zero() { return v8i_t{0, 0, 0, 0, 0, 0, 0, 0}; }
+  static __device__ __forceinline__ float pscale(const PArgs& a, int64_t p) { return a.sh[p]; }
+  static __device__ __forceinline__ Op row(const Tile& T, int r, int g) { return load_h8(&T.e[r][0], g); }
+  static __device__ __forceinline__ void logits(const Tile& T, int cb, int g, const Op& A, const Op& B, float sh,
+                                                float* z) {
+    const f32x4 zz = mfma_h8(A, B);
+    const f32x4 bt = *reinterpret_cast<const f32x4*>(&T.beta[cb * 16 + 4 * g]);
+    const f32x4 se = *reinterpret_cast<const f32x4*>(&T.se[cb * 16 + 4 * g]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[i] = fmaf(zz[i], sh * se[i], bt[i]);
+  }
+};
+
+// rows of 128 values -> OCP e4m3 bytes, each row scaled by the power of two that puts its largest
+// magnitude in [224, 448] (exact), rounded to nearest even by the hardware conversion; inv[r] undoes
+// the scaling. Rows r >= nvalid (padding) are zero with factor 1. Input FP32 or BF16 (uint16).
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows128_fp8(const T* __restrict__ src, int64_t nrows, int64_t nvalid,
+                                                     uint8_t* __restrict__ dst, float* __restrict__ inv) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= nrows) return;
+  auto val = [&](int f) -> float {
+    if constexpr (sizeof(T) == 2) return __uint_as_float((uint32_t)src[r * VBGS_H + f] << 16);
+    else return src[r * VBGS_H + f];
+  };
+  float mx = 0.0f;
+  if (r < nvalid)
+    for (int f = 0; f < VBGS_H; ++f) mx = fmaxf(mx, fabsf(val(f)));
+  float sc = 1.0f, un = 1.0f;
+  if (mx > 7.8886091e-31f && mx <= 3.4e38f) {  // 2^-100: rows below are left unscaled (they round to 0)
+    int e;
+    frexpf(448.0f / mx, &e);  // 448 / mx in [2^(e-1), 2^e)
+    sc = ldexpf(1.0f, e - 1);
+    un = ldexpf(1.0f, 1 - e);
+  }
+  uint32_t* d32 = reinterpret_cast<uint32_t*>(dst + r * VBGS_H);
+  for (int q = 0; q < VBGS_H / 4; ++q) {
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (r < nvalid)
+      for (int i = 0; i < 4; ++i) v[i] = val(4 * q + i) * sc;
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+    d32[q] = (uint32_t)w;
+  }
+  inv[r] = un;
+}
+
 // ---------------------------------------------------------------------------
 // streaming exact top-C per (point, lane group); 4 waves x 4 point blocks of 16
 // ---------------------------------------------------------------------------
-// A lower bound on each point's C-th best logit for C <= 32: every lane group keeps its eight best
-// logits in registers (a compare-exchange chain); the four groups' eighth-best values are each the
-// smallest of eight distinct logits of the point, so their minimum is at or below its 32nd best.
+// A lower bound on each point's C-th best logit for C <= 4 NB: every lane group keeps its NB best
+// logits in registers (a compare-exchange chain); the four groups' NB-th best values are each the
+// smallest of NB distinct logits of the point, so their minimum is at or below its (4 NB)-th best.
 // k_logits_topc starts its thresholds there, so that its candidate buffers fill (and are
-// reselected) far less often than from -inf.
+// reselected) far less often than from -inf. NB = 8 serves C <= 32, NB = 16 serves C <= 64.
+template <int NB, bool F8>
 __global__ __launch_bounds__(256) void k_topc_thresh(const PArgs a, int64_t N) {
-  __shared__ ETile T[2];
+  typedef Logits<F8> LG;
+  __shared__ typename LG::Tile T[2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
   const int64_t p0 = (int64_t)blockIdx.x * 256 + w * 64;
-  HOp B[4];
-  float r[4][8];
+  typename LG::Op B[4];
+  float shp[4];
+  float r[4][NB];
   bool val[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int64_t p = p0 + 16 * b + c;
     val[b] = p < N;
-    B[b] = val[b] ? load_h(a.h2b + p * VBGS_H, g) : zero_h();
+    B[b] = val[b] ? LG::point(a, p, g) : LG::zero();
+    shp[b] = val[b] ? LG::pscale(a, p) : 1.0f;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) r[b][j] = -INFINITY;
+    for (int j = 0; j < NB; ++j) r[b][j] = -INFINITY;
   }
-  ETileRegs R;
-  etile_fetch(R, a, 0);
-  etile_store(T[0], R);
+  typename LG::Regs R;
+  LG::fetch(R, a, 0);
+  LG::store(T[0], R);
   __syncthreads();
   const int64_t ntiles = a.Kpad / CT;
   for (int64_t it = 0; it < ntiles; ++it) {
     const int cur = (int)(it & 1);
-    if (it + 1 < ntiles) etile_fetch(R, a, (it + 1) * CT);
-    const ETile& Tc = T[cur];
+    if (it + 1 < ntiles) LG::fetch(R, a, (it + 1) * CT);
+    const typename LG::Tile& Tc = T[cur];
 #pragma unroll
     for (int cb = 0; cb < CT / 16; ++cb) {
-      const HOp A = load_h(&Tc.e[cb * 16 + c][0], g);
-      const f32x4 bt = *reinterpret_cast<const f32x4*>(&Tc.beta[cb * 16 + 4 * g]);
+      const typename LG::Op A = LG::row(Tc, cb * 16 + c, g);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const f32x4 zz = mfma_h(A, B[b]);
         float z[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) z[i] = zz[i] + bt[i];
+        LG::logits(Tc, cb, g, A, B[b], shp[b], z);
         const float mx = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
-        if (mx > r[b][7]) {
+        if (mx > r[b][NB - 1]) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             float v = z[i];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < NB; ++j) {
               const float hi = fmaxf(r[b][j], v);
               v = fminf(r[b][j], v);
               r[b][j] = hi;
@@ -266,24 +392,27 @@ __global__ __launch_bounds__(256) void k_topc_thresh(const PArgs a, int64_t N) {
         }
       }
     }
-    if (it + 1 < ntiles) etile_store(T[cur ^ 1], R);
+    if (it + 1 < ntiles) LG::store(T[cur ^ 1], R);
     __syncthreads();
   }
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    float t = r[b][7];
+    float t = r[b][NB - 1];
     t = fminf(t, __shfl_xor(t, 16));
     t = fminf(t, __shfl_xor(t, 32));
     if (val[b] && g == 0) a.tthr[p0 + 16 * b + c] = t;
   }
 }
 
+template <bool F8>
 __global__ __launch_bounds__(256) void k_logits_topc(const PArgs a, int64_t N) {
-  __shared__ ETile T[2];
+  typedef Logits<F8> LG;
+  __shared__ typename LG::Tile T[2];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
   const int64_t p0 = (int64_t)blockIdx.x * 256 + w * 64;
   const int C = a.C, CAP = 2 * a.C;
-  HOp B[4];
+  typename LG::Op B[4];
+  float shp[4];
   float zt[4];
   int cnt[4];
   bool val[4];
@@ -291,31 +420,29 @@ __global__ __launch_bounds__(256) void k_logits_topc(const PArgs a, int64_t N) {
   for (int b = 0; b < 4; ++b) {
     const int64_t p = p0 + 16 * b + c;
     val[b] = p < N;
-    B[b] = val[b] ? load_h(a.h2b + p * VBGS_H, g) : zero_h();
+    B[b] = val[b] ? LG::point(a, p, g) : LG::zero();
+    shp[b] = val[b] ? LG::pscale(a, p) : 1.0f;
     // just below the lower bound on the C-th best, so that a logit equal to it still enters
     const float t = a.tthr && val[b] ? a.tthr[p] : -INFINITY;
     zt[b] = t == -INFINITY ? t : nextafterf(t, -INFINITY);
     cnt[b] = 0;
   }
-  ETileRegs R;
-  etile_fetch(R, a, 0);
-  etile_store(T[0], R);
+  typename LG::Regs R;
+  LG::fetch(R, a, 0);
+  LG::store(T[0], R);
   __syncthreads();
   const int64_t ntiles = a.Kpad / CT;
   for (int64_t it = 0; it < ntiles; ++it) {
     const int cur = (int)(it & 1);
-    if (it + 1 < ntiles) etile_fetch(R, a, (it + 1) * CT);
-    const ETile& Tc = T[cur];
+    if (it + 1 < ntiles) LG::fetch(R, a, (it + 1) * CT);
+    const typename LG::Tile& Tc = T[cur];
 #pragma unroll
     for (int cb = 0; cb < CT / 16; ++cb) {
-      const HOp A = load_h(&Tc.e[cb * 16 + c][0], g);
-      const f32x4 bt = *reinterpret_cast<const f32x4*>(&Tc.beta[cb * 16 + 4 * g]);
+      const typename LG::Op A = LG::row(Tc, cb * 16 + c, g);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const f32x4 zz = mfma_h(A, B[b]);
         float z[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) z[i] = zz[i] + bt[i];
+        LG::logits(Tc, cb, g, A, B[b], shp[b], z);
         const float mx = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
         if (val[b] && mx > zt[b]) {
           const int64_t p = p0 + 16 * b + c;
@@ -337,7 +464,7 @@ __global__ __launch_bounds__(256) void k_logits_topc(const PArgs a, int64_t N) {
         }
       }
     }
-    if (it + 1 < ntiles) etile_store(T[cur ^ 1], R);
+    if (it + 1 < ntiles) LG::store(T[cur ^ 1], R);
     __syncthreads();
   }
 #pragma unroll
@@ -945,6 +1072,9 @@ __global__ void k_zero_f32(float* p, int64_t n) {
 hipError_t launch_prop_prepare(const PArgs& a, hipStream_t s) {
   const int64_t n = std::max<int64_t>(a.Kpad * VBGS_H, (int64_t)VBGS_H * VBGS_H);
   hipLaunchKernelGGL(k_prop_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  if (a.f8)  // embedding rows as scaled e4m3 for the FP8 logits
+    hipLaunchKernelGGL(k_rows128_fp8<float>, dim3((unsigned)((a.Kpad + 255) / 256)), dim3(256), 0, s, a.E, a.Kpad,
+                       a.K, a.E8, a.sE);
   return hipGetLastError();
 }
 
@@ -957,13 +1087,17 @@ hipError_t launch_mlp_fwd(const PArgs& a, const float* X, const int32_t* idx, in
 
 hipError_t launch_topc(const PArgs& a, const EArgsLite& e, int64_t N, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  PArgs b = a;
-  if (a.C <= 32) {
-    hipLaunchKernelGGL(k_topc_thresh, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, N);
+  const dim3 grid((unsigned)((N + 255) / 256));
+  if (a.f8) {  // the points' h2 rows as scaled e4m3
+    hipLaunchKernelGGL(k_rows128_fp8<uint16_t>, grid, dim3(256), 0, s, a.h2b, N, N, a.h8, a.sh);
+    if (a.C <= 32) hipLaunchKernelGGL((k_topc_thresh<8, true>), grid, dim3(256), 0, s, a, N);
+    else hipLaunchKernelGGL((k_topc_thresh<16, true>), grid, dim3(256), 0, s, a, N);
+    hipLaunchKernelGGL(k_logits_topc<true>, grid, dim3(256), 0, s, a, N);
   } else {
-    b.tthr = nullptr;  // eight per lane group bound only the 32nd best
+    if (a.C <= 32) hipLaunchKernelGGL((k_topc_thresh<8, false>), grid, dim3(256), 0, s, a, N);
+    else hipLaunchKernelGGL((k_topc_thresh<16, false>), grid, dim3(256), 0, s, a, N);
+    hipLaunchKernelGGL(k_logits_topc<false>, grid, dim3(256), 0, s, a, N);
   }
-  hipLaunchKernelGGL(k_logits_topc, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, b, N);
   hipLaunchKernelGGL(k_topc_merge, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, e, N);
   return hipGetLastError();
 }

@@ -39,7 +39,11 @@ struct PArgs {
   uint16_t* h2b;
   float* tz;
   int32_t *tk, *tcnt;
-  float* tthr;  // per point: lower bound on its C-th best logit (used for C <= 32), or null
+  float* tthr;  // per point: lower bound on its C-th best logit
+  // FP8 logits (f8 = 1): e4m3 embedding rows and point rows with the factors undoing their scaling
+  int f8;
+  uint8_t *E8, *h8;
+  float *sE, *sh;
   // training
   float *th1, *th2, *txs, *tlse, *tdh2, *tdp1;
   float *tlpart, *tdpart;  // per component slice: partial (max, sum) of the logits, partial dh2 rows

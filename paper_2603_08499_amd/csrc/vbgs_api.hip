@@ -162,8 +162,8 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "cull_dims must be in 0..min(D, 3)";
     return VBGS_ERR_ARG;
   }
-  if (p->reserved0 != 0) {
-    if (why) *why = "reserved fields must be zero";
+  if (p->proposal_prec != 0 && p->proposal_prec != VBGS_BF16 && p->proposal_prec != VBGS_FP8) {
+    if (why) *why = "proposal_prec must be 0, VBGS_BF16 or VBGS_FP8";
     return VBGS_ERR_ARG;
   }
   for (int i = 0; i < 3; ++i)
@@ -328,6 +328,11 @@ Layout make_layout(const vbgs_params& p) {
   L.p_tk = take(pr ? (size_t)n * 4 * 2 * C * 4 : 0);
   L.p_tcnt = take(pr ? (size_t)n * 4 * 4 : 0);
   L.p_tthr = take(pr ? (size_t)n * 4 : 0);
+  const bool f8 = pr && p.proposal_prec == VBGS_FP8;
+  L.p_E8 = take(f8 ? (size_t)L.Kpad * H : 0);
+  L.p_sE = take(f8 ? (size_t)L.Kpad * 4 : 0);
+  L.p_h8 = take(f8 ? (size_t)n * H : 0);
+  L.p_sh = take(f8 ? (size_t)n * 4 : 0);
   L.p_aud = take(pr ? (size_t)n * 8 : 0);
   L.p_gate = take(pr ? 64 : 0);
   const size_t Bp = (size_t)L.Bpad_max;
@@ -899,6 +904,11 @@ static PArgs make_pargs(vbgs_ctx* c) {
   a.tk = reinterpret_cast<int32_t*>(ws + L.p_tk);
   a.tcnt = reinterpret_cast<int32_t*>(ws + L.p_tcnt);
   a.tthr = reinterpret_cast<float*>(ws + L.p_tthr);
+  a.f8 = c->p.proposal_prec == VBGS_FP8 ? 1 : 0;
+  a.E8 = reinterpret_cast<uint8_t*>(ws + L.p_E8);
+  a.sE = reinterpret_cast<float*>(ws + L.p_sE);
+  a.h8 = reinterpret_cast<uint8_t*>(ws + L.p_h8);
+  a.sh = reinterpret_cast<float*>(ws + L.p_sh);
   a.th1 = reinterpret_cast<float*>(ws + L.p_th1);
   a.th2 = reinterpret_cast<float*>(ws + L.p_th2);
   a.txs = reinterpret_cast<float*>(ws + L.p_txs);

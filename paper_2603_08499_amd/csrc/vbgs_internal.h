@@ -129,6 +129,7 @@ struct Layout {
   size_t rx2_tmp, rx2_hist, rx2_off, rx2_part;  // the same for the component sort (runs concurrently)
   // learned proposal (workspace)
   size_t p_tthr;  // per point: lower bound on its C-th best logit
+  size_t p_E8, p_sE, p_h8, p_sh;  // FP8 logits: e4m3 embedding and point rows, their scale factors
   size_t p_tlpart, p_tdpart, p_twpart;  // training: per-slice partial LSE, dh2 rows, weight gradients
   size_t p_Ebf, p_EbfT, p_betap, p_W2T, p_h2b, p_tz, p_tk, p_tcnt, p_aud, p_gate, p_th1, p_th2, p_txs, p_tlse,
       p_tdh2, p_tdp1, p_th2b, p_th2T, p_tloss, p_grads;

@@ -30,7 +30,7 @@ def _stream(s=None):
 
 def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec=None, exact=True,
                 screen_margin=0.0, n_split=0, proposal=False, C=32, train_batch=4096, cull=True, modal_split=0,
-                cull_dims=0):
+                cull_dims=0, proposal_prec=0):
     p = _lib.Params()
     L = _lib.load()
     st = L.vbgs_default_params(ctypes.byref(p), int(D), int(K), int(n_max))
@@ -51,6 +51,7 @@ def make_params(D, K, n_max, kappa0=1.0, nu0=None, alpha0=1.0, score_prec=None, 
     p.cull = 1 if cull else 0
     p.modal_split = int(modal_split)
     p.cull_dims = int(cull_dims)
+    p.proposal_prec = _lib.PREC[proposal_prec] if isinstance(proposal_prec, str) else int(proposal_prec)
     return p
 
 

@@ -38,6 +38,21 @@ def _bf16(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def _e4m3_rows(a):
+    """Each row scaled by the power of two 2^e that puts its largest magnitude in [224, 448], rounded to
+    OCP e4m3 (3 mantissa bits, exponent bias 7, subnormal step 2^-9) to nearest even; returns the
+    represented values with the scaling undone (FP64)."""
+    a = np.asarray(a, np.float64)
+    mx = np.abs(a).max(axis=1, keepdims=True)
+    e = np.where(mx > 0, np.floor(np.log2(448.0 / np.where(mx > 0, mx, 1.0))), 0.0)
+    sc = np.exp2(e)
+    v = a * sc
+    ex = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** -6)))
+    step = np.exp2(ex - 3)  # normal numbers: 3 mantissa bits; below 2^-6 the subnormal step 2^-9
+    q = np.round(v / step) * step  # numpy rounds halves to even
+    return q / sc
+
+
 def _oracle_mlp(w):
     return PR.MLP(**{k: np.asarray(v, np.float64) for k, v in w.items()})
 
@@ -62,7 +77,8 @@ def _separated_weights(D, K, seed, X):
 @gpu
 @pytest.mark.parametrize("C", [32, 13, 48, 64])
 def test_candidates_are_a_valid_top_c(dev, C):
-    """C <= 32 starts each selection from a per-point threshold pre-pass; C > 32 selects without one."""
+    """Each selection starts from a per-point threshold pre-pass (eight logits per lane group for C <= 32,
+    sixteen for C <= 64)."""
     X, pr = scenes.random_problem(1500, 300, 6, seed=41)
     w = scenes.mlp_init(6, 128, pr.K, 42, X)
     m = _model(dev, pr, X.shape[0], C=C)
@@ -88,11 +104,47 @@ def test_candidates_are_a_valid_top_c(dev, C):
 
 
 @gpu
-@pytest.mark.parametrize("C", [24, 56])
-def test_pruned_statistics_match_oracle(dev, C):
+@pytest.mark.parametrize("C", [32, 64])
+def test_fp8_candidates_are_a_valid_top_c(dev, C):
+    """FP8 logits (per-row scaled e4m3 operands, one 16x16x128 MFMA per block): the oracle takes the top-C
+    decision on the same e4m3 values (h2 rounded to FP32, then BF16, then scaled e4m3; E scaled e4m3;
+    exact products, FP64 sums). Every point: no candidate more than one e4m3 step of the largest term
+    below the C-th logit (a rounding flip of h2 between the oracle's and the GPU's FP32 arithmetic);
+    at least 98% of the points: within the FP32 accumulation tolerance."""
+    X, pr = scenes.random_problem(1500, 300, 6, seed=41)
+    w = scenes.mlp_init(6, 128, pr.K, 42, X)
+    m = _model(dev, pr, X.shape[0], C=C, proposal_prec="fp8")
+    m.proposal_set(**w)
+    cand = m.proposal_candidates(torch.from_numpy(X).to(dev)).cpu().numpy()
+    torch.cuda.synchronize()
+    _, _, h2 = PR.forward(_oracle_mlp(w), X)
+    h8 = _e4m3_rows(_bf16(h2.astype(np.float32)))
+    E8 = _e4m3_rows(np.asarray(w["E"], np.float32))
+    z = h8 @ E8.T + w["beta"].astype(np.float64)
+    mag = np.abs(h8) @ np.abs(E8).T
+    loose_bad, strict_bad = 0, 0
+    for n in range(X.shape[0]):
+        S = cand[n]
+        assert (S >= 0).all() and len(set(S.tolist())) == C and (np.diff(S) > 0).all()
+        zc = np.sort(z[n])[-C]
+        inS = np.zeros(pr.K, bool)
+        inS[S] = True
+        strict = 1e-5 * mag[n].max()
+        loose = strict + 2.0 ** -3 * np.abs(h8[n]).max() * np.abs(E8).max()
+        viol = lambda eps: (z[n][inS] < zc - eps).any() or (z[n][~inS] > zc + eps).any()
+        loose_bad += int(viol(loose))
+        strict_bad += int(viol(strict))
+    print("fp8 top-%d: points outside the FP32 tolerance %d, outside one e4m3 step %d (of %d)"
+          % (C, strict_bad, loose_bad, X.shape[0]))
+    assert loose_bad == 0 and strict_bad <= 0.02 * X.shape[0]
+
+
+@gpu
+@pytest.mark.parametrize("C,lp", [(24, "bf16"), (56, "bf16"), (32, "fp8"), (64, "fp8")])
+def test_pruned_statistics_match_oracle(dev, C, lp):
     X, pr = scenes.random_problem(2000, 400, 6, seed=43)
     w = _separated_weights(6, pr.K, 44, X)
-    m = _model(dev, pr, X.shape[0], C=C)
+    m = _model(dev, pr, X.shape[0], C=C, proposal_prec=lp)
     m.proposal_set(**w)
     Xg = torch.from_numpy(X).to(dev)
     lse, st, rep = m.estep_stats_pruned(Xg, audit_idx=[])
