@@ -524,6 +524,21 @@ def main():
         fp64 = {"value": N * K / (ms64 * 1e-3), "ms_per_step": ms64, "steps": args.fp64_steps}
         del m64
         print("bench: fp64 %.3f ms/step" % ms64, file=sys.stderr, flush=True)
+    # the same culling with every surviving pair scored in FP64 (no MFMA): what the culling alone buys
+    fp64c = None
+    if not args.no_fp64 and args.fp64_steps > 0 and args.exact and args.cull and not args.modal_split:
+        mc = new_model("fp64_culled", 1)
+        run_steps(mc, Xs, 1, torch)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        run_steps(mc, Xs, args.fp64_steps, torch, first=1)
+        torch.cuda.synchronize()
+        msc = (time.perf_counter() - s0) / args.fp64_steps * 1e3
+        fp64c = {"value": N * K / (msc * 1e-3), "ms_per_step": msc, "steps": args.fp64_steps,
+                 "what": "culled exact path with FP64 direct scores of the pairs within the tile and row bounds "
+                         "(no MFMA), same LSE and statistics kernels"}
+        del mc
+        print("bench: culled fp64 %.3f ms/step" % msc, file=sys.stderr, flush=True)
 
     # ---- roofline of the dominant kernel (live HIP-event durations) -----------------------------
     F = 1 + D + D * (D + 1) // 2
@@ -553,6 +568,7 @@ def main():
                                 "%d cycled" % args.frames},
            "phase_ms": {k: round(v, 5) for k, v in avg.items()},
            "fp64_gpu": fp64, "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
+           "fp64_culled_gpu": fp64c, "speedup_vs_fp64_culled_gpu": (value / fp64c["value"]) if fp64c else None,
            "device_status": status, "roofline": roof, "cpu_baseline": cpu, "reassign": reas}
     out.update(acc)
     if orc:

@@ -75,6 +75,10 @@ typedef enum {
                        (2^-12 |c| |phi| for the mean coefficient-row and feature norms) exceeds
                        32 log2 units, else the FP32 screen; the choice is made on the device and
                        reported by vbgs_counters (the results are exact either way) */
+  VBGS_FP64_CULLED = 6,  /* exact = 1, cull = 1 only: a comparator with the culled sweep's point blocks,
+                       seeds and tile / row bounds, every pair within the bounds scored directly in FP64
+                       (no MFMA), then the exact mode's LSE and statistics: what the culling alone gives,
+                       against the same results. Same params limits as the MFMA precisions (D <= 6). */
   VBGS_FP8 = 5      /* exact = 0 only (a plain tier whose error is reported): every feature and
                        coefficient row scaled by a power of two so that its largest magnitude lies
                        in [224, 448], rounded to OCP e4m3 (nearest even), v_mfma_f32_16x16x32_fp8_fp8

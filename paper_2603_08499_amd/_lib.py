@@ -14,7 +14,7 @@ NPHASE = 10
 PHASES = ["prep", "coeffs", "pass1", "pass2", "fold", "update", "elbo", "proposal", "sort", "lse"]
 H = 128
 SCRATCH_BYTES = 64 << 20  # VBGS_SCRATCH_BYTES
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4, "fp8": 5}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "auto": 4, "fp8": 5, "fp64_culled": 6}
 
 
 class Params(ctypes.Structure):

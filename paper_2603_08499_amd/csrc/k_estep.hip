@@ -56,6 +56,8 @@ template <>
 struct Opnd<VBGS_FP8> {
   long q;  // eight e4m3 bytes, slots 8 g .. 8 g + 7
 };
+template <>
+struct Opnd<VBGS_FP64_CULLED> {};  // the FP64 comparator's sweep scores directly, without MFMA operands
 
 // FP8 tier: this lane's eight e4m3 slots of a row
 __device__ __forceinline__ Opnd<VBGS_FP8> load_op8(const uint8_t* row, int g) {
@@ -68,7 +70,8 @@ template <int P>
 __device__ __forceinline__ Opnd<P> load_op(const float* f32row, const uint16_t* hrow, const uint16_t* lrow,
                                            int g) {
   Opnd<P> o;
-  if constexpr (P == VBGS_FP32) {
+  if constexpr (P == VBGS_FP64_CULLED) {
+  } else if constexpr (P == VBGS_FP32) {
     o.a = *reinterpret_cast<const f32x4*>(f32row + 8 * g);
     o.b = *reinterpret_cast<const f32x4*>(f32row + 8 * g + 4);
   } else if constexpr (P == VBGS_BF16) {
@@ -83,7 +86,8 @@ __device__ __forceinline__ Opnd<P> load_op(const float* f32row, const uint16_t* 
 template <int P>
 __device__ __forceinline__ Opnd<P> zero_op() {
   Opnd<P> o;
-  if constexpr (P == VBGS_FP32) {
+  if constexpr (P == VBGS_FP64_CULLED) {
+  } else if constexpr (P == VBGS_FP32) {
     o.a = f32x4{0.f, 0.f, 0.f, 0.f};
     o.b = o.a;
   } else if constexpr (P == VBGS_FP8) {
@@ -459,6 +463,9 @@ __device__ __forceinline__ int64_t find_tiles8(const TileInfo* __restrict__ ti, 
   return L;
 }
 
+// tiles that at most this many of a wave's points reach are scored directly (direct_tile)
+constexpr int DIRECT_MAX = 2;
+
 // Workgroups are dealt to the eight XCDs in turn; renumber them so that each XCD takes one
 // contiguous range of the Morton order, whose component tiles then stay in that XCD's L2.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
@@ -472,7 +479,8 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 template <int P>
 struct TileStage {
-  u32x4 a[CT / 16][2][64];  // coefficient rows: [16-row block][hi / lo (FP32: first / second half)][lane]
+  static constexpr int NB = P == VBGS_FP64_CULLED ? 1 : CT / 16;  // (the FP64 comparator stages nothing)
+  u32x4 a[NB][2][64];  // coefficient rows: [16-row block][hi / lo (FP32: first / second half)][lane]
   u32x4 rb[2][64];          // RowBound of row `lane`, two 16-byte halves
   int32_t krow[64];         // component of row `lane`
 };
@@ -605,6 +613,106 @@ __device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int
   }
 }
 
+// FP64 score (log2 units) of one pair in direct form, for the run-time D of the wave
+__device__ __forceinline__ double direct_score2_rt(const double* __restrict__ row, const float* __restrict__ x, int D) {
+  double d[MAXD];
+  switch (D) {
+    case 1: return direct_score2_dt<1>(row, x, d);
+    case 2: return direct_score2_dt<2>(row, x, d);
+    case 3: return direct_score2_dt<3>(row, x, d);
+    case 4: return direct_score2_dt<4>(row, x, d);
+    case 5: return direct_score2_dt<5>(row, x, d);
+    default: return direct_score2_dt<6>(row, x, d);
+  }
+}
+
+// Tiles that only a few of the wave's points reach (points far from every component, whose
+// bounds reach many tiles that the rest of the wave never needs) are not staged for the MFMA
+// screen: lane = row, each reaching point in turn is tested against the row bounds and the pairs
+// that pass are scored exactly in FP64 (the same score the exact LSE gives them later), raise the
+// point's M and are recorded like screened pairs (error bound 0). pm: the wave's points (lane
+// index = point slot) that reach the tile; buf: 64 LDS entries for the recorded pairs.
+// a lane's row of a tile for direct scoring: its bound and component (rows past K: no component)
+struct DirectRow {
+  float G, Lam, m[3];
+  int32_t k;
+};
+
+__device__ __forceinline__ DirectRow load_direct_row(const EArgs& a, int64_t t, int lane) {
+  DirectRow d{-INFINITY, 0.0f, {0.0f, 0.0f, 0.0f}, -1};
+  const int64_t r = t * CT + lane;
+  if (r < a.K) {
+    const RowBound rb = a.rowb[r];
+    d.G = rb.G;
+    d.Lam = rb.Lam;
+    d.m[0] = rb.m[0];
+    d.m[1] = rb.m[1];
+    d.m[2] = rb.m[2];
+    d.k = a.corder[r];
+  }
+  return d;
+}
+
+template <int P>
+__device__ __forceinline__ void direct_tile(const EArgs& a, SweepWave<P>& S, const DirectRow& dr, unsigned long long pm,
+                                            bool rec, int lane, float* __restrict__ mv, const int32_t* __restrict__ pid,
+                                            const float4* __restrict__ pts, float2* __restrict__ buf) {
+  const int g = lane >> 4, c = lane & 15;
+  const bool rv = dr.k >= 0;
+  const float rg = dr.G, rl = dr.Lam, rm[3] = {dr.m[0], dr.m[1], dr.m[2]};
+  const int32_t k = rv ? dr.k : 0;
+  const double* row = a.direct + (int64_t)k * a.dts;
+  const float margin = a.T2 + 1.0f;
+  while (pm) {
+    const int p = __ffsll((long long)pm) - 1;  // wave-uniform
+    pm &= pm - 1ull;
+    const float4 xp = pts[p];
+    const float xq[3] = {xp.x, xp.y, xp.z};
+    float d2 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const float gap = fmaxf(fabsf(xq[q] - rm[q]) - fabsf(rm[q]) * 2.384185791015625e-7f, 0.0f);
+      d2 = fmaf(gap, gap, d2);
+    }
+    const float Mp = mv[p];
+    const bool pass = rv && rg - rl * d2 >= Mp - margin;
+    double s2 = -INFINITY;
+    if (pass) s2 = direct_score2_rt(row, a.X + (int64_t)pid[p] * a.D, a.D);
+    // the largest exact score is a lower bound on the point's maximum (rounded down)
+    float smax = pass ? __double2float_rd(s2) : -INFINITY;
+    for (int o = 1; o < 64; o <<= 1) smax = fmaxf(smax, __shfl_xor(smax, o));
+    const float Mn = fmaxf(Mp, smax);
+    const int pb = p >> 4;
+#pragma unroll
+    for (int b = 0; b < P1_PB; ++b)
+      if (b == pb && c == (p & 15)) S.M[b] = fmaxf(S.M[b], Mn);
+    if (lane == 0) mv[p] = Mn;
+    if (rec) {
+      const float hi = pass ? __double2float_ru(s2) : -INFINITY;
+      const unsigned long long km = __ballot(pass && hi >= Mn - a.T2);
+      if (km) {
+        if (pass && hi >= Mn - a.T2) {
+          const int idx = __builtin_amdgcn_mbcnt_hi((unsigned)(km >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)km, 0u));
+          buf[idx] = make_float2(__int_as_float(k), hi);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int cnt = __popcll(km);
+        if (c == (p & 15)) {  // the point's four lane groups take every fourth pair
+#pragma unroll
+          for (int b = 0; b < P1_PB; ++b)
+            if (b == pb && S.val[b])
+              for (int i = g; i < cnt; i += 4) {
+                const float2 e = buf[i];
+                record_candidate(a, pid[p], g, __float_as_int(e.x), e.y, S.M[b] - a.T2, S.cn[b], S.ovf[b]);
+                ++S.nref;
+              }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+}
+
 // make each point's M the largest over its four lane groups and publish it for the tile tests
 template <int P>
 __device__ __forceinline__ void share_m(SweepWave<P>& S, int lane, float* __restrict__ mv) {
@@ -629,6 +737,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ uint8_t bms[1][64];  // per tile of the current chunk: the 16-point blocks it reaches
   __shared__ int32_t tks[1][64];  // component indices of the tile being screened
   __shared__ TileStage<P> stg;    // operands of the tile being screened or the next one
+  __shared__ float2 dbuf[1][64];  // pairs of a directly scored tile: component (bits), score
   const uint64_t t_start = wall_clock64();
   const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
   if (blockIdx.x == 0 && lane == 0) a.bprev[0] = gridDim.x;  // read by the next launch's k_block_order
@@ -730,12 +839,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int npil = ncen, nst = npil + nseed;
     auto seed_at = [&](int i) { return (int64_t)__builtin_amdgcn_readfirstlane(seeds[w][i < npil ? i : i - npil]); };
     for (int i = 0; i < nst; ++i) {
-      const int64_t tn = i + 1 < nst ? seed_at(i + 1) : -1;
-      screen_tile<P>(a, S, seed_at(i), tn, i > 0, i >= npil, lane, 0xFu, mv, pid, tks[w], stg);
+      if constexpr (P == VBGS_FP64_CULLED) {
+        const unsigned long long all = __ballot(mv[lane] < INFINITY);  // the wave's valid points
+        direct_tile<P>(a, S, load_direct_row(a, seed_at(i), lane), all, i >= npil, lane, mv, pid, pts[w], dbuf[w]);
+      } else {
+        const int64_t tn = i + 1 < nst ? seed_at(i + 1) : -1;
+        screen_tile<P>(a, S, seed_at(i), tn, i > 0, i >= npil, lane, 0xFu, mv, pid, tks[w], stg);
+      }
       share_m<P>(S, lane, mv);
     }
     const float margin = a.T2 + 1.0f;
     const float4 xme = pts[w][lane];  // this lane's point (lane = point of the wave)
+    uint32_t* slist = a.slist + jb * ntiles;  // the block's directly scored tiles
+    int64_t nsl = 0;
     for (int64_t base = 0; base < ntiles; base += 64) {
       share_m<P>(S, lane, mv);
       // lane = tile: the wave's box against the tile bound
@@ -754,7 +870,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       }
       // lane = point: each candidate tile against every point's own bound and M
       const float thr_me = mv[lane] - margin;
-      unsigned long long cm = __ballot(cand), m = 0ull;
+      unsigned long long cm = __ballot(cand), m = 0ull, msp = 0ull;
       while (cm) {
         const int i = __ffsll((long long)cm) - 1;
         cm &= cm - 1ull;
@@ -770,7 +886,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
           d2 = fmaf(gap, gap, d2);
         }
         const unsigned long long pm = __ballot(tG - tL * d2 >= thr_me);
-        if (pm != 0ull) {
+        if (pm != 0ull && (P == VBGS_FP64_CULLED || __popcll(pm) <= DIRECT_MAX)) {
+          msp |= 1ull << i;  // few points reach it: direct FP64 scoring after the screened tiles
+        } else if (pm != 0ull) {
           m |= 1ull << i;
           // which 16-point blocks (lane = point, block = lane / 16) reach the tile
           const unsigned bmi = ((pm & 0xFFFFull) ? 1u : 0u) | ((pm & 0xFFFF0000ull) ? 2u : 0u) |
@@ -779,15 +897,52 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         }
       }
       __builtin_amdgcn_wave_barrier();
-      bool staged = false;
-      while (m) {
-        const int i = __ffsll((long long)m) - 1;
-        m &= m - 1ull;
-        const int64_t tn = m ? base + (__ffsll((long long)m) - 1) : -1;
-        screen_tile<P>(a, S, base + i, tn, staged, true, lane, __builtin_amdgcn_readfirstlane(bms[w][i]), mv, pid,
-                       tks[w], stg);
-        staged = tn >= 0;
+      if constexpr (P != VBGS_FP64_CULLED) {
+        bool staged = false;
+        while (m) {
+          const int i = __ffsll((long long)m) - 1;
+          m &= m - 1ull;
+          const int64_t tn = m ? base + (__ffsll((long long)m) - 1) : -1;
+          screen_tile<P>(a, S, base + i, tn, staged, true, lane, __builtin_amdgcn_readfirstlane(bms[w][i]), mv, pid,
+                         tks[w], stg);
+          staged = tn >= 0;
+        }
       }
+      // the tiles that few points reach wait in the block's list until every screened tile has
+      // raised the points' M (fewer pairs pass then, and the screen's registers are free)
+      while (msp) {
+        const int i = __ffsll((long long)msp) - 1;
+        msp &= msp - 1ull;
+        if (lane == 0) slist[nsl] = (uint32_t)(base + i);
+        ++nsl;
+      }
+    }
+    share_m<P>(S, lane, mv);
+    // the next listed tile's bounds are fetched while the current one is scored
+    int64_t tnx = nsl > 0 ? (int64_t)__builtin_amdgcn_readfirstlane((int)slist[0]) : 0;
+    TileInfo tinx{};
+    DirectRow drnx{};
+    if (nsl > 0) {
+      tinx = a.tinfo[tnx];
+      drnx = load_direct_row(a, tnx, lane);
+    }
+    for (int64_t q = 0; q < nsl; ++q) {
+      const TileInfo ti = tinx;
+      const DirectRow dr = drnx;
+      if (q + 1 < nsl) {
+        tnx = (int64_t)__builtin_amdgcn_readfirstlane((int)slist[q + 1]);
+        tinx = a.tinfo[tnx];
+        drnx = load_direct_row(a, tnx, lane);
+      }
+      float d2 = 0.0f;
+      const float xq[3] = {xme.x, xme.y, xme.z};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float gap = fmaxf(fmaxf(ti.lo[i] - xq[i], xq[i] - ti.hi[i]), 0.0f);
+        d2 = fmaf(gap, gap, d2);
+      }
+      const unsigned long long pm = __ballot(ti.G - ti.Lam * d2 >= mv[lane] - margin);
+      if (pm) direct_tile<P>(a, S, dr, pm, true, lane, mv, pid, pts[w], dbuf[w]);
     }
     share_m<P>(S, lane, mv);
   }
@@ -1866,6 +2021,7 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
       if (run_f32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), gw, dim3(64), 0, s, af);
       if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), gw, dim3(64), 0, s, a);
       if (run_bf3) hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), gw, dim3(64), 0, s, ab);
+      if (prec == VBGS_FP64_CULLED) hipLaunchKernelGGL((k_sweep<VBGS_FP64_CULLED>), gw, dim3(64), 0, s, a);
     } else {
       if (run_f32) hipLaunchKernelGGL((k_pass1<VBGS_FP32, true>), grid, dim3(256), 0, s, af);
       if (prec == VBGS_BF16) hipLaunchKernelGGL((k_pass1<VBGS_BF16, true>), grid, dim3(256), 0, s, a);
@@ -1999,6 +2155,7 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.T2 = c.T2;
   a.cull = c.cull;
   a.nsp = d.nsp;
+  a.slist = d.at<uint32_t>(L.slist);
   a.bcost = d.at<float>(L.bcost);
   a.bcode = d.at<uint32_t>(L.bcode);
   a.border = d.at<int32_t>(L.border);

@@ -102,7 +102,7 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
     if (why) *why = "prior scalars need kappa0 > 0, alpha0 > 0, nu0 > D - 1";
     return VBGS_ERR_ARG;
   }
-  if (p->score_prec < VBGS_FP64 || p->score_prec > VBGS_FP8) {
+  if (p->score_prec < VBGS_FP64 || p->score_prec > VBGS_FP64_CULLED) {
     if (why) *why = "unknown score_prec";
     return VBGS_ERR_ARG;
   }
@@ -117,6 +117,10 @@ vbgs_status check_params(const vbgs_params* p, std::string* why) {
   if (p->exact != 0 && p->exact != 1) {
     if (why) *why = "exact must be 0 or 1";
     return VBGS_ERR_ARG;
+  }
+  if (p->score_prec == VBGS_FP64_CULLED && (p->exact != 1 || p->cull != 1 || p->proposal || p->modal_split)) {
+    if (why) *why = "VBGS_FP64_CULLED is the culled exact sweep with FP64 scores: exact = 1, cull = 1, no proposal, one block";
+    return VBGS_ERR_UNSUPPORTED;
   }
   if (p->score_prec == VBGS_FP8 && p->exact != 0) {
     if (why) *why = "VBGS_FP8 is a plain tier (exact = 0): as a screen its error bound would admit nearly every pair";
@@ -313,6 +317,7 @@ Layout make_layout(const vbgs_params& p) {
   L.bcode = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.border = take(sparse ? (size_t)((n + 63) / 64) * 4 : 0);
   L.bprev = take(8);
+  L.slist = take(sparse ? (size_t)((n + 63) / 64) * (L.Kpad / CT) * 4 : 0);
   // learned proposal
   const bool pr = p.proposal == 1;
   const int C = p.C > 0 ? p.C : 32;

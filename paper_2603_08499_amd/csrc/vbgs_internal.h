@@ -123,6 +123,7 @@ struct Layout {
   size_t bcost, bcode, border;  // per 64-point block of the culled sweep: measured time, Morton code
                                 // of its first point, dispatch order
   size_t bprev;                 // number of blocks of the last sweep (int64)
+  size_t slist;                 // per block, the tiles it scores directly (uint32, Kpad / 64 per block)
   size_t elbo_part;  // 2 x 256 partial sums of the ELBO reduction
   size_t scr_part, scr_gate;  // screen choice: 2 x 256 partial norm sums, two gate flags
   size_t rx_tmp, rx_hist, rx_off, rx_part;  // radix sort: ping-pong keys, digit histograms, scan
@@ -366,6 +367,7 @@ struct EArgs {
   uint32_t* bcode;            // and the Morton code of its first point then
   int32_t* border;            // culled sweep: dispatch position -> block (costliest first per XCD)
   int64_t* bprev;             // culled sweep: blocks of the last launch (their bcost / bcode entries)
+  uint32_t* slist;            // culled sweep: per 64-point block, its tiles scored directly (Kpad / 64 each)
   int64_t nb_cap;             // capacity of bcost / border
   double* scr_part;           // screen choice: partial sums of the row and feature norms
   int32_t* scr_gate;          // screen choice: [run split BF16, run FP32]

@@ -16,7 +16,8 @@ from synth import scenes
 
 gpu = pytest.mark.gpu
 
-EXACT_TIERS = [("fp64", True), ("fp32", True), ("bf16", True), ("bf16x3", True), ("auto", True)]
+EXACT_TIERS = [("fp64", True), ("fp32", True), ("bf16", True), ("bf16x3", True), ("auto", True),
+               ("fp64_culled", True)]
 
 
 @pytest.fixture(scope="module")
@@ -277,13 +278,14 @@ def test_elbo_state_error_after_update(dev):
 
 
 @gpu
-def test_full_k_c3_slice(dev):
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64_culled"])
+def test_full_k_c3_slice(dev, prec):
     """All K = 100000 components of the c3 configuration against a raster slice of 4096 points."""
     scene = scenes.gauss_scene(3, 10000, 0.003, 0.03)
     X0 = scenes.c3_frame(0, scene=scene)
     pr = scenes.c3_prior(X0)
     X = np.ascontiguousarray(X0[150000:154096])
-    m = _model(dev, pr, X.shape[0], "bf16x3", True)
+    m = _model(dev, pr, X.shape[0], prec, True)
     lse, st = m.estep_stats(torch.from_numpy(X).to(dev))
     F = m.elbo()
     torch.cuda.synchronize()
@@ -341,20 +343,22 @@ def test_cull_matches_unculled(dev, case):
         X, pr = scenes.random_problem(20000, 2000, 6, seed=77)
     Xd = torch.from_numpy(X).to(dev)
     out = []
-    for cull in (0, 1):
-        m = _model(dev, pr, X.shape[0], "bf16x3", True, cull=cull)
+    # unculled split-BF16 screen, culled split-BF16 screen, culled FP64 direct scoring (no MFMA)
+    for prec, cull in (("bf16x3", 0), ("bf16x3", 1), ("fp64_culled", 1)):
+        m = _model(dev, pr, X.shape[0], prec, True, cull=cull)
         lse, st = m.estep_stats(Xd)
         F = m.elbo()
         torch.cuda.synchronize()
         assert m.sync_status() == 0
         out.append((lse.cpu().numpy(), st.cpu().numpy(), F.item(), m.counters()))
         m.close()
-    (l0, s0, F0, c0), (l1, s1, F1, c1) = out
-    dl = np.abs(l0 - l1).max()
-    es = _stat_err(s0, s1, 6)
-    print("  culled vs unculled: max|dLSE| %.2e stats relerr %.2e dF %.2e" % (dl, es, abs(F0 - F1)),
-          "counters unculled", c0, "culled", c1)
-    assert dl < 1e-9 and es < 1e-9 and abs(F0 - F1) <= 1e-11 * abs(F0)
+    (l0, s0, F0, c0), (l1, s1, F1, c1), (l2, s2, F2, c2) = out
+    for name, (l, st, F) in (("culled", (l1, s1, F1)), ("culled FP64", (l2, s2, F2))):
+        dl = np.abs(l0 - l).max()
+        es = _stat_err(s0, st, 6)
+        print("  %s vs unculled: max|dLSE| %.2e stats relerr %.2e dF %.2e" % (name, dl, es, abs(F0 - F)))
+        assert dl < 1e-9 and es < 1e-9 and abs(F0 - F) <= 1e-11 * abs(F0)
+    print("  counters unculled", c0, "culled", c1, "culled FP64", c2)
     if case == "c3_slice":
         # results are exact whatever the point and component orders; the fraction of blocks the
         # culled sweep screens shows that the spatial sorts and tile bounds do their work

@@ -255,7 +255,7 @@ def test_training_gradients_match_oracle(dev):
         o += rg.size
     print("loss %.6f vs %.6f; grad relerr W1 b1 W2 b2 E beta:" % (loss.item(), L), ["%.2e" % e for e in errs])
     assert abs(loss.item() - L) < 1e-3 * abs(L)
-    assert max(errs) < 2e-2
+    assert max(errs) < 1e-2  # BF16 tier bound of the gradient pin; measured ~1.5e-3
 
 
 @gpu
