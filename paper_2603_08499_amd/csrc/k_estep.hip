@@ -946,20 +946,61 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
     share_m<P>(S, lane, mv);
   }
+  unsigned kept = 0;
 #pragma unroll
   for (int b = 0; b < P1_PB; ++b) {
     int o = S.ovf[b] ? 1 : 0;
     o |= __shfl_xor(o, 16);
     o |= __shfl_xor(o, 32);
+    const int32_t p = pid[16 * b + c];
     if (S.val[b]) {
-      const int32_t p = pid[16 * b + c];
       a.cand_n[(int64_t)p * 4 + g] = o ? -1 : S.cn[b];
       if (o && g == 0) {
         a.over_list[atomicAdd(&a.frame->n_over, 1)] = p;
         a.lse2[p] = (double)S.M[b];  // lower bound on the point's largest score, for the rescan's culling
       }
     }
+    // The exact LSE of the wave's points, here rather than in a pass of its own: the block's
+    // pairs are rescored while it still holds its slot, which fills the GPU during the sweep's
+    // tail. Each lane rescores the list it wrote (list g of point 16 b + c) in FP64, the point's
+    // four lists merge by shuffles, and the pairs within the margin of the LSE are kept and
+    // counted per component for the statistics (overflowed points: the rescan does all of it).
+    const bool live = S.val[b] && !o;
+    double mm = -INFINITY, ll = 0.0;
+    int32_t* ck = a.cand_k + ((int64_t)p * 4 + g) * CS;
+    float* cs = a.cand_s + ((int64_t)p * 4 + g) * CS;
+    if (live) {
+      const float* xp = a.X + (int64_t)p * a.D;
+      for (int j = 0; j < S.cn[b]; ++j) {
+        const double sc = direct_score2_rt(a.direct + (int64_t)ck[j] * a.dts, xp, a.D);
+        online_add(mm, ll, sc);
+        cs[j] = (float)sc;
+      }
+    }
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      const double m2 = __shfl_xor(mm, off), l2 = __shfl_xor(ll, off);
+      const double mn = fmax(mm, m2);
+      if (mn > -INFINITY) {
+        ll = (mm == -INFINITY ? 0.0 : ll * exp2(mm - mn)) + (m2 == -INFINITY ? 0.0 : l2 * exp2(m2 - mn));
+        mm = mn;
+      }
+    }
+    if (live) {
+      const double L2 = mm + log2(ll);
+      if (g == 0) a.lse2[p] = L2;
+      const float thr = (float)(L2 - (double)a.T2);  // FP32 rounding is monotone (see evict_candidates)
+      for (int j = 0; j < S.cn[b]; ++j) {
+        if (cs[j] >= thr) {
+          atomicAdd(&a.ccount[ck[j]], 1);
+          ++kept;
+        } else {
+          ck[j] = -1;
+        }
+      }
+    }
   }
+  count_refined(&a.frame->refined2, kept);
   count_refined(&a.frame->refined1, S.nref);
   if (lane == 0) {
     a.bcost[jb] = (float)(wall_clock64() - t_start);
@@ -1313,6 +1354,24 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
   }
   red[tid] = L2;
   count_refined(&a.frame->refined2, kept);
+  __syncthreads();
+  if (tid == 0) {
+    double sacc = 0.0;
+    for (int i = 0; i < 256; ++i) sacc += red[i];
+    a.lse_part[blockIdx.x] = sacc;
+  }
+}
+
+// After the culled sweep (which computed the LSE of its points) and the overflow rescan: per 256
+// points the fixed-order partial sum of the LSEs for the ELBO, and the LSEs in nats if requested.
+__global__ __launch_bounds__(256) void k_lse_finish(const EArgs a) {
+  __shared__ double red[256];
+  if (a.gate && a.gate[0] == 0) return;
+  const int tid = threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+  const double L2 = p < a.N ? a.lse2[p] : 0.0;
+  if (p < a.N && a.lse_out) a.lse_out[p] = L2 * LN2;
+  red[tid] = L2;
   __syncthreads();
   if (tid == 0) {
     double sacc = 0.0;
@@ -2001,10 +2060,14 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, a.gate);
     hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1, a.gate);
     hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, a.gate);
-  } else if (stage == 1) {
-    const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
+  } else if (stage == 1) {  // the screen's choice and, with culling, the blocks' dispatch order
     hipLaunchKernelGGL(k_screen_part, dim3(SCR_BLOCKS), dim3(256), 0, s, a.nc, a.Kpad, a.nphi, N, a.scr_part);
     hipLaunchKernelGGL(k_screen_pick, dim3(1), dim3(256), 0, s, a.scr_part, a.K, N, prec, a.frame, a.scr_gate);
+    if (cull)
+      hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, (int64_t)((N + 63) / 64),
+                         a.nb_cap, a.bprev, a.border, a.order_reset);
+  } else if (stage == 3) {  // the screening sweep
+    const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
     // VBGS_AUTO: both screens are enqueued, each gated by the choice (the other exits at once)
     EArgs ab = a, af = a;
     if (prec == VBGS_AUTO) {
@@ -2016,8 +2079,6 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     const bool run_bf3 = prec == VBGS_BF16X3 || prec == VBGS_AUTO, run_f32 = prec == VBGS_FP32 || prec == VBGS_AUTO;
     if (cull) {
       const dim3 gw((unsigned)((N + 63) / 64));  // one 64-point wave per workgroup
-      hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, (int64_t)gw.x,
-                         a.nb_cap, a.bprev, a.border, a.order_reset);
       if (run_f32) hipLaunchKernelGGL((k_sweep<VBGS_FP32>), gw, dim3(64), 0, s, af);
       if (prec == VBGS_BF16) hipLaunchKernelGGL((k_sweep<VBGS_BF16>), gw, dim3(64), 0, s, a);
       if (run_bf3) hipLaunchKernelGGL((k_sweep<VBGS_BF16X3>), gw, dim3(64), 0, s, ab);
@@ -2030,10 +2091,11 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
   } else {
     const dim3 gp((unsigned)((N + 255) / 256));
     switch (D) {
-#define VB_LSE(DD)                                                    \
-  case DD:                                                            \
-    hipLaunchKernelGGL(k_over_lse<DD>, dim3(256), dim3(256), 0, s, a); \
-    hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, a);      \
+#define VB_LSE(DD)                                                                   \
+  case DD:                                                                           \
+    hipLaunchKernelGGL(k_over_lse<DD>, dim3(256), dim3(256), 0, s, a);                \
+    if (cull) hipLaunchKernelGGL(k_lse_finish, gp, dim3(256), 0, s, a); /* LSE: sweep */ \
+    else hipLaunchKernelGGL(k_point_lse<DD>, gp, dim3(256), 0, s, a);                \
     break;
       VB_LSE(1) VB_LSE(2) VB_LSE(3) VB_LSE(4) VB_LSE(5) VB_LSE(6)
 #undef VB_LSE
@@ -2046,7 +2108,8 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
 
 hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull) {
   hipError_t e = hipSuccess;
-  for (int stage = 0; stage < 3 && e == hipSuccess; ++stage) e = exact_stage(a, prec, D, N, s, cull, stage);
+  for (const int stage : {0, 1, 3, 2})
+    if (e == hipSuccess) e = exact_stage(a, prec, D, N, s, cull, stage);
   return e;
 }
 
@@ -2196,7 +2259,7 @@ hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int
     if (stage >= 0) return exact_stage(a, c.prec, d.D, N, s, c.cull, stage);
     return launch_exact_sweep(a, c.prec, d.D, N, s, c.cull);
   }
-  if (stage == 0 || stage == 2) return hipSuccess;
+  if (stage == 0 || stage == 1 || stage == 2) return hipSuccess;  // the whole pass is stage 3 (or -1)
   if (c.prec == VBGS_FP64) {
     const dim3 grid((unsigned)((N + 255) / 256));
     switch (d.D) {

@@ -655,9 +655,10 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
       e = launch_pass1(d, cfg, X, N, lse_out, s, 0);
     }
   }
+  if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 1);
   if (e == hipSuccess) {
-    Phase ph(c, 2, S(stream));
-    e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 1);
+    Phase ph(c, 2, S(stream));  // the screening sweep alone (exact mode), or the whole first pass
+    e = launch_pass1(d, cfg, X, N, lse_out, S(stream), 3);
     if (cfg.cull && N > 0) c->order_reset = false;
   }
   if (e == hipSuccess) {

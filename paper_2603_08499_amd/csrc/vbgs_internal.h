@@ -380,7 +380,8 @@ struct EArgs {
 };
 EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out);
 // stage -1: the whole first pass; exact MFMA mode in stages 0 (clear the transpose counters),
-// 1 (the screening sweep) and 2 (exact per-point LSE); other modes run everything in stage 1
+// 1 (screen choice and dispatch order), 3 (the screening sweep) and 2 (exact per-point LSE), in
+// that order; other modes run the whole pass in stage 3
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
                         hipStream_t s, int stage = -1);
 // stats_out (or null): the caller's statistics; the exact mode writes them in pass 2 (fold is then empty)
