@@ -737,7 +737,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ uint8_t bms[1][64];  // per tile of the current chunk: the 16-point blocks it reaches
   __shared__ int32_t tks[1][64];  // component indices of the tile being screened
   __shared__ TileStage<P> stg;    // operands of the tile being screened or the next one
-  __shared__ float2 dbuf[1][64];  // pairs of a directly scored tile: component (bits), score
+  // pairs of a directly scored tile: component (bits), score. Direct tiles are scored only while no
+  // tile is staged (the FP64 comparator stages none), so they share the stage's memory, which keeps
+  // the workgroup within the LDS that twelve of them per CU may hold.
+  float2* const dbuf = reinterpret_cast<float2*>(&stg.a[0][0][0]);
+  static_assert(sizeof(stg.a) >= 64 * sizeof(float2), "direct-tile buffer");
   const uint64_t t_start = wall_clock64();
   const int lane = threadIdx.x, w = 0, g = lane >> 4, c = lane & 15;
   if (blockIdx.x == 0 && lane == 0) a.bprev[0] = gridDim.x;  // read by the next launch's k_block_order
@@ -841,7 +845,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     for (int i = 0; i < nst; ++i) {
       if constexpr (P == VBGS_FP64_CULLED) {
         const unsigned long long all = __ballot(mv[lane] < INFINITY);  // the wave's valid points
-        direct_tile<P>(a, S, load_direct_row(a, seed_at(i), lane), all, i >= npil, lane, mv, pid, pts[w], dbuf[w]);
+        direct_tile<P>(a, S, load_direct_row(a, seed_at(i), lane), all, i >= npil, lane, mv, pid, pts[w], dbuf);
       } else {
         const int64_t tn = i + 1 < nst ? seed_at(i + 1) : -1;
         screen_tile<P>(a, S, seed_at(i), tn, i > 0, i >= npil, lane, 0xFu, mv, pid, tks[w], stg);
@@ -942,7 +946,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         d2 = fmaf(gap, gap, d2);
       }
       const unsigned long long pm = __ballot(ti.G - ti.Lam * d2 >= mv[lane] - margin);
-      if (pm) direct_tile<P>(a, S, dr, pm, true, lane, mv, pid, pts[w], dbuf[w]);
+      if (pm) direct_tile<P>(a, S, dr, pm, true, lane, mv, pid, pts[w], dbuf);
     }
     share_m<P>(S, lane, mv);
   }
@@ -1133,6 +1137,7 @@ __global__ __launch_bounds__(256) void k_pass2(const EArgs a) {
 // exact (to 2^-64 per term) and independent of the order of the additions, so the statistics
 // are bitwise reproducible without sorting the contributions by component.
 __device__ __forceinline__ void fx_add(unsigned long long* cell, double v) {
+#pragma clang fp contract(off)  // (as in fx_acc)
   double hi_d = floor(v);
   double frac = v - hi_d;  // exact, in [0, 1]
   if (frac >= 1.0) {
@@ -1696,6 +1701,8 @@ struct Fx128 {
 };
 
 __device__ __forceinline__ void fx_acc(Fx128& a, double v) {
+  // no fusion of v - hi_d with the product that made v: every path converts the same rounded v
+#pragma clang fp contract(off)
   double hi_d = floor(v);
   double frac = v - hi_d;
   if (frac >= 1.0) {
