@@ -1180,15 +1180,19 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n, const int32_t* gate
 // Workgroups go to the eight XCDs in turn and each XCD takes one contiguous range of the point
 // blocks (xcd_block). Within its range, an XCD starts the blocks predicted to take longest first
 // (longest processing time first), so that the long blocks do not form the tail. A block's
-// predicted cost is the time the previous launch on the same context measured for the block
-// that covered the same place: the previous blocks are in Morton order, so the one whose first
-// point's code is the largest not above this block's first code (the same block when the points
-// are the same, as in coordinate-ascent steps on one frame; a neighbour in space on a new frame).
-// A range longer than BO_MAX, or a reset, keeps the Morton order. Any order gives the same results.
+// predicted cost is the longest time the previous launch on the same context measured for the
+// blocks that covered the same stretch of the Morton order: the previous blocks are in Morton
+// order, so those from the one whose first code is the largest not above this block's first code
+// to the one whose first code is the largest not above its last code (the same block when the
+// points are the same, as in coordinate-ascent steps on one frame; its neighbours in space on a
+// new frame, where a block that straddles a costly one is likely costly too). A range longer than
+// BO_MAX, or a reset, keeps the Morton order. Any order gives the same results.
+constexpr int BO_SPAN = 32;  // previous blocks looked at per block
 constexpr int BO_MAX = 4096;
 
 __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost, const uint32_t* __restrict__ bcode,
-                                                      const uint32_t* __restrict__ pcode, int64_t nb, int64_t cap,
+                                                      const uint32_t* __restrict__ pcode, int64_t N, int64_t nb,
+                                                      int64_t cap,
                                                       const int64_t* __restrict__ bprev,
                                                       int32_t* __restrict__ border, int reset) {
   __shared__ unsigned long long key[BO_MAX];
@@ -1207,16 +1211,24 @@ __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost,
   while (n2 < len) n2 <<= 1;
   for (int i = tid; i < n2; i += 1024) {
     if (i < len) {
-      // the previous block covering this block's first point: last code <= this one (else the first)
-      const uint32_t code = pcode[(start + i) * 64];
-      int64_t lo = 0, hi = np - 1;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (bcode[mid] <= code) lo = mid;
-        else hi = mid - 1;
+      // the previous blocks covering this block's first and last points: last code <= each (else
+      // the first block)
+      auto cover = [&](uint32_t code) {
+        int64_t lo = 0, hi = np - 1;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi + 1) >> 1;
+          if (bcode[mid] <= code) lo = mid;
+          else hi = mid - 1;
+        }
+        return lo;
+      };
+      const int64_t jf = (start + i) * 64, jl = min(jf + 63, N - 1);
+      const int64_t b0 = cover(pcode[jf]), b1 = cover(pcode[jl]);
+      float v = 0.0f;
+      for (int64_t b = b0; b <= b1 && b < b0 + BO_SPAN; ++b) {
+        const float c = bcost[b];
+        v = c > v ? c : v;  // (NaN and negative costs count as 0)
       }
-      float v = bcost[lo];
-      v = v > 0.0f ? v : 0.0f;  // also maps NaN to 0
       key[i] = ((unsigned long long)(0xFFFFFFFFu - __float_as_uint(v)) << 32) | (unsigned)i;
     } else {
       key[i] = ~0ull;
@@ -2071,7 +2083,7 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     hipLaunchKernelGGL(k_screen_part, dim3(SCR_BLOCKS), dim3(256), 0, s, a.nc, a.Kpad, a.nphi, N, a.scr_part);
     hipLaunchKernelGGL(k_screen_pick, dim3(1), dim3(256), 0, s, a.scr_part, a.K, N, prec, a.frame, a.scr_gate);
     if (cull)
-      hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, (int64_t)((N + 63) / 64),
+      hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, N, (int64_t)((N + 63) / 64),
                          a.nb_cap, a.bprev, a.border, a.order_reset);
   } else if (stage == 3) {  // the screening sweep
     const dim3 grid((unsigned)((N + P1_PTS - 1) / P1_PTS));
