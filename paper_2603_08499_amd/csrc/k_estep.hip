@@ -922,31 +922,46 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       }
     }
     share_m<P>(S, lane, mv);
-    // the next listed tile's bounds are fetched while the current one is scored
-    int64_t tnx = nsl > 0 ? (int64_t)__builtin_amdgcn_readfirstlane((int)slist[0]) : 0;
-    TileInfo tinx{};
-    DirectRow drnx{};
-    if (nsl > 0) {
-      tinx = a.tinfo[tnx];
-      drnx = load_direct_row(a, tnx, lane);
-    }
-    for (int64_t q = 0; q < nsl; ++q) {
-      const TileInfo ti = tinx;
-      const DirectRow dr = drnx;
-      if (q + 1 < nsl) {
-        tnx = (int64_t)__builtin_amdgcn_readfirstlane((int)slist[q + 1]);
-        tinx = a.tinfo[tnx];
-        drnx = load_direct_row(a, tnx, lane);
-      }
-      float d2 = 0.0f;
+    // The listed tiles, 64 at a time: lane = tile loads its bound, then (lane = point) each tile in
+    // turn is tested against every point with the point's current M, as in the chunk scan. M only
+    // grows, so the tiles that no point reaches at the start of the batch are dropped at once; the
+    // others are tested again when their turn comes, with the rows of the next one in flight.
+    auto reach = [&](const TileInfo& tb, int i) {
+      const float tG = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tb.G), i));
+      const float tL = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tb.Lam), i));
       const float xq[3] = {xme.x, xme.y, xme.z};
+      float d2 = 0.0f;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const float gap = fmaxf(fmaxf(ti.lo[i] - xq[i], xq[i] - ti.hi[i]), 0.0f);
+      for (int q = 0; q < 3; ++q) {
+        const float tlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tb.lo[q]), i));
+        const float thi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tb.hi[q]), i));
+        const float gap = fmaxf(fmaxf(tlo - xq[q], xq[q] - thi), 0.0f);
         d2 = fmaf(gap, gap, d2);
       }
-      const unsigned long long pm = __ballot(ti.G - ti.Lam * d2 >= mv[lane] - margin);
-      if (pm) direct_tile<P>(a, S, dr, pm, true, lane, mv, pid, pts[w], dbuf);
+      return __ballot(tG - tL * d2 >= mv[lane] - margin);
+    };
+    for (int64_t base = 0; base < nsl; base += 64) {
+      const int64_t q = base + lane;
+      TileInfo tb{};
+      int32_t tl = 0;
+      if (q < nsl) {
+        tl = (int32_t)slist[q];
+        tb = a.tinfo[tl];
+      }
+      const int nq = (int)min((int64_t)64, nsl - base);
+      unsigned long long keep = 0ull;
+      for (int i = 0; i < nq; ++i)
+        if (reach(tb, i)) keep |= 1ull << i;
+      DirectRow drn{};
+      if (keep) drn = load_direct_row(a, __builtin_amdgcn_readlane(tl, __ffsll((long long)keep) - 1), lane);
+      while (keep) {
+        const int i = __ffsll((long long)keep) - 1;
+        keep &= keep - 1ull;
+        const DirectRow dr = drn;
+        if (keep) drn = load_direct_row(a, __builtin_amdgcn_readlane(tl, __ffsll((long long)keep) - 1), lane);
+        const unsigned long long pm = reach(tb, i);
+        if (pm) direct_tile<P>(a, S, dr, pm, true, lane, mv, pid, pts[w], dbuf);
+      }
     }
     share_m<P>(S, lane, mv);
   }
