@@ -101,7 +101,6 @@ __device__ __forceinline__ Opnd<P> zero_op() {
 
 // Empty asm that reads the operand registers: it makes the compiler wait for their loads at this
 // point, so loads issued together stay together instead of being sunk next to each use.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <int P>
 __device__ __forceinline__ void operands_ready(const Opnd<P>& o) {
   if constexpr (P == VBGS_FP32) {
@@ -1618,8 +1617,8 @@ __global__ __launch_bounds__(256) void k_over_stats(const EArgs a) {
 }
 
 // ---- transpose of the kept pairs: exclusive scan of the per-component counts (one workgroup) ----
-// exclusive scan of the per-component pair counts (off[K] = total) in three coalesced steps:
-// block sums, a scan of the block sums, and the local scans with their block offsets
+// exclusive scan of the per-component pair counts (off[K] = total) in two coalesced steps: block
+// sums, then the local scans, each block adding the sums of the blocks before it
 constexpr int SCAN_B = 1024;
 __global__ __launch_bounds__(256) void k_scan_blocks(const int32_t* __restrict__ cnt, int64_t K,
                                                      int32_t* __restrict__ bsum) {
@@ -1654,25 +1653,22 @@ __device__ __forceinline__ int32_t block_excl_scan256(int32_t v, int32_t* sh, in
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_scan_tops(int32_t* __restrict__ bsum, int64_t nb, int32_t* __restrict__ off,
-                                                   int64_t K) {
-  __shared__ int32_t sh[256];
-  int32_t carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
-    const int64_t b = b0 + threadIdx.x;
-    const int32_t v = b < nb ? bsum[b] : 0;
-    int32_t total;
-    const int32_t e = block_excl_scan256(v, sh, total);
-    if (b < nb) bsum[b] = carry + e;
-    carry += total;
-  }
-  if (threadIdx.x == 0) off[K] = carry;
-}
-
+// each block starts from the sum of the block sums before it (a strided sum and a tree in LDS);
+// the last block also writes the total
 __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ cnt, int64_t K,
                                                     const int32_t* __restrict__ bsum, int32_t* __restrict__ off) {
   __shared__ int32_t sh[256];
   const int t = threadIdx.x;
+  int32_t pre = 0;
+  for (int64_t b = t; b < (int64_t)blockIdx.x; b += 256) pre += bsum[b];
+  sh[t] = pre;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const int32_t base = sh[0];
+  __syncthreads();
   const int64_t k0 = (int64_t)blockIdx.x * SCAN_B + 4 * t;
   int32_t c[4], v = 0;
 #pragma unroll
@@ -1681,12 +1677,13 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ 
     v += c[i];
   }
   int32_t total;
-  int32_t run = bsum[blockIdx.x] + block_excl_scan256(v, sh, total);
+  int32_t run = base + block_excl_scan256(v, sh, total);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if (k0 + i < K) off[k0 + i] = run;
     run += c[i];
   }
+  if (blockIdx.x == gridDim.x - 1 && t == 255) off[K] = run;
 }
 
 // exclusive scan of n counts: off[i] = sum_{j < i} cnt[j], off[n] = total; part: ceil(n / SCAN_B) + 1
@@ -1694,7 +1691,6 @@ hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t
   const int64_t nsb = (n + SCAN_B - 1) / SCAN_B;
   if (nsb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part);
-  hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(256), 0, s, part, nsb, off, n);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part, off);
   return hipGetLastError();
 }
@@ -2179,7 +2175,6 @@ hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) 
   case DD:                                                                                \
     hipLaunchKernelGGL(k_over_stats<DD>, dim3(256), dim3(256), 0, s, a);                  \
     hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part); \
-    hipLaunchKernelGGL(k_scan_tops, dim3(1), dim3(256), 0, s, a.scan_part, nsb, a.coffset, a.K);         \
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part,   \
                        a.coffset);                                                                       \
     hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                          \

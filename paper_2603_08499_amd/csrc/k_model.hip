@@ -143,13 +143,20 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ X, i
   for (int i = 0; i < FP; ++i) nn += (double)f[i] * (double)f[i];
   f32x4* p32 = reinterpret_cast<f32x4*>(phi32 + n * FP);
   for (int q = 0; q < FP / 4; ++q) p32[q] = f32x4{f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]};
-  uint32_t* ph = reinterpret_cast<uint32_t*>(phih + n * FP);
-  uint32_t* pl = reinterpret_cast<uint32_t*>(phil + n * FP);
+  uint32_t hw[FP / 2], lw[FP / 2];
+#pragma unroll
   for (int q = 0; q < FP / 2; ++q) {
     const uint16_t h0 = f2bf(f[2 * q]), h1 = f2bf(f[2 * q + 1]);
     const uint16_t l0 = f2bf(f[2 * q] - bf2f(h0)), l1 = f2bf(f[2 * q + 1] - bf2f(h1));
-    ph[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-    pl[q] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    hw[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    lw[q] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+  }
+  u32x4* ph = reinterpret_cast<u32x4*>(phih + n * FP);
+  u32x4* pl = reinterpret_cast<u32x4*>(phil + n * FP);
+#pragma unroll
+  for (int q = 0; q < FP / 8; ++q) {
+    ph[q] = u32x4{hw[4 * q], hw[4 * q + 1], hw[4 * q + 2], hw[4 * q + 3]};
+    pl[q] = u32x4{lw[4 * q], lw[4 * q + 1], lw[4 * q + 2], lw[4 * q + 3]};
   }
   nphi[n] = (float)(sqrt(nn) * (1.0 + 1e-6));
 }
@@ -379,8 +386,9 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
   double g = Elnpi;
   for (int b = 0; b < nb; ++b) g += 0.5 * ElnLam_b[b] - 0.5 * Db[b] * LN2PI - 0.5 * Db[b] / kap[b];
 
-  // direct-form row (raw coordinates, log2 units)
-  double* T = o.direct + k * dts;
+  // direct-form row (raw coordinates, log2 units), built in registers and written 16 bytes at a
+  // time (each thread writes a row of its own)
+  double T[dts];
   T[0] = LOG2E * g;
   for (int i = 0; i < D; ++i) T[1 + i] = m[i];
   for (int i = 0; i < D; ++i) {
@@ -388,6 +396,11 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     for (int j = 0; j <= i; ++j) T[1 + D + i * (i + 1) / 2 + j] = us * Li[i][j];
   }
   for (int i = 1 + D + D * (D + 1) / 2; i < dts; ++i) T[i] = 0.0;
+  {
+    f64x2* Tg = reinterpret_cast<f64x2*>(o.direct + k * dts);
+#pragma unroll
+    for (int i = 0; i < dts / 2; ++i) Tg[i] = f64x2{T[2 * i], T[2 * i + 1]};
+  }
 
   // expanded coefficients in centred/scaled coordinates x' = (x - mu) / s (MFMA paths: D <= 6)
   if constexpr (D <= 6) {
@@ -414,21 +427,38 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     }
   double nn = 0.0;
   const int64_t row = o.cinv ? (int64_t)o.cinv[k] : k;
+  // the row's three formats, written 16 bytes at a time
+  float v[FP];
+  uint32_t hw[FP / 2], lw[FP / 2];
+#pragma unroll
   for (int i = 0; i < FP; ++i) {
-    const float v = (float)c[i];
-    o.c32[row * FP + i] = v;
-    const uint16_t h = f2bf(v);
-    o.ch[row * FP + i] = h;
-    o.cl[row * FP + i] = f2bf(v - bf2f(h));
+    v[i] = (float)c[i];
     nn += c[i] * c[i];
   }
-  o.nc[row] = (float)(sqrt(nn) * (1.0 + 1e-6));
+#pragma unroll
+  for (int i = 0; i < FP / 2; ++i) {
+    const uint16_t h0 = f2bf(v[2 * i]), h1 = f2bf(v[2 * i + 1]);
+    hw[i] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    lw[i] = (uint32_t)f2bf(v[2 * i] - bf2f(h0)) | ((uint32_t)f2bf(v[2 * i + 1] - bf2f(h1)) << 16);
+  }
+  f32x4* c32g = reinterpret_cast<f32x4*>(o.c32 + row * FP);
+  u32x4* chg = reinterpret_cast<u32x4*>(o.ch + row * FP);
+  u32x4* clg = reinterpret_cast<u32x4*>(o.cl + row * FP);
+#pragma unroll
+  for (int i = 0; i < FP / 4; ++i) c32g[i] = f32x4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
+#pragma unroll
+  for (int i = 0; i < FP / 8; ++i) {
+    chg[i] = u32x4{hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]};
+    clg[i] = u32x4{lw[4 * i], lw[4 * i + 1], lw[4 * i + 2], lw[4 * i + 3]};
+  }
+  const float ncr = (float)(sqrt(nn) * (1.0 + 1e-6));
+  o.nc[row] = ncr;
   if (o.rowb) {
     RowBound rb{};
     rb.G = f_up(T[0]);
     rb.Lam = lam;
     for (int i = 0; i < ns; ++i) rb.m[i] = (float)m[i];
-    rb.nc = o.nc[row];
+    rb.nc = ncr;
     o.rowb[row] = rb;
   }
   }
@@ -525,11 +555,19 @@ __global__ __launch_bounds__(128) void k_kl(const double* __restrict__ prior, co
   kl[k] = klnw + kd;
 }
 
-hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv) {
-  const Layout& L = *d.L;
-  double* apart = d.at<double>(L.mom_part);  // free again once the frame moments are final
+hipError_t launch_alpha(const DevPtrs& d, hipStream_t s) {
+  double* apart = d.at<double>(d.L->mom_part);  // free again once the frame moments are final
   hipLaunchKernelGGL(k_alpha_part, dim3(ALPHA_BLOCKS), dim3(256), 0, s, d.prior(), d.post(), d.K, apart);
   hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(256), 0, s, apart, d.frame());
+  return hipGetLastError();
+}
+
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv, bool alpha) {
+  const Layout& L = *d.L;
+  if (alpha) {
+    const hipError_t e = launch_alpha(d, s);
+    if (e != hipSuccess) return e;
+  }
   CoefOut o{d.K, cinv, cinv ? d.at<RowBound>(L.rowb) : nullptr, d.at<float>(L.lam), d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch),
             d.at<uint16_t>(L.cl), d.at<float>(L.nc)};
   const dim3 grid((unsigned)((L.Kpad + 127) / 128)), blk(128);

@@ -353,7 +353,8 @@ hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
   unsigned long long* keys = d.at<unsigned long long>(L.ckeys);
   int* hist = d.at<int>(L.lhist);
   hipLaunchKernelGGL(k_zero_hist, dim3(1), dim3(LAM_BINS), 0, s, hist);
-  hipLaunchKernelGGL(k_lam_hist, dim3(64), dim3(256), 0, s, d.post(), d.K, d.D, d.split, d.nsp, hist);
+  hipLaunchKernelGGL(k_lam_hist, dim3((unsigned)min((d.K + 255) / 256, (int64_t)1024)), dim3(256), 0, s, d.post(), d.K, d.D,
+                     d.split, d.nsp, hist);
   hipLaunchKernelGGL(k_lam_anchor, dim3(1), dim3(64), 0, s, hist, d.K, d.frame());
   hipLaunchKernelGGL(k_comp_keys, dim3((unsigned)((d.K + 255) / 256)), dim3(256), 0, s, d.post(), d.K, d.K, d.D,
                      d.split, d.nsp, d.frame(), keys);

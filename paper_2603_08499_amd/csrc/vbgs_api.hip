@@ -592,14 +592,15 @@ static hipError_t settle(vbgs_ctx* c, hipStream_t s) {
 // expectations and coefficient rows; with culling the MFMA rows are written in spatial order and
 // per-tile bounds are built
 // (with_kl = false: the caller launches the KL terms itself, after what the sweep needs)
-static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s, bool with_kl = true) {
+// (alpha = false: launch_alpha has run before, on s or a stream s waited for)
+static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s, bool with_kl = true, bool alpha = true) {
   const DevPtrs d = c->dev();
   hipError_t e;
   if (!use_cull(c)) {
-    e = launch_coeffs(d, s);
+    e = launch_coeffs(d, s, nullptr, alpha);
   } else {
     e = launch_sort_comps(d, s);
-    if (e == hipSuccess) e = launch_coeffs(d, s, d.at<int32_t>(c->L.cinv));
+    if (e == hipSuccess) e = launch_coeffs(d, s, d.at<int32_t>(c->L.cinv), alpha);
     if (e == hipSuccess) e = launch_tile_info(d, s);
   }
   if (e == hipSuccess && with_kl) e = launch_kl(d, s);
@@ -616,19 +617,20 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   const hipStream_t s = S(stream);
   hipError_t e;
   if (cull) {
-    // frame moments first (the components are centred and Morton-coded with them); then the
-    // components (sort, coefficient rows, tile bounds) on the side stream while the points
-    // (features, sort) go on; the sweep waits for both
+    // frame moments and the alpha sum first (the components are centred and Morton-coded with
+    // the moments); then the components (sort, coefficient rows, tile bounds) on the side stream
+    // while the points (features, sort) go on; the sweep waits for both
     e = c->side ? hipSuccess : hipErrorInvalidResourceHandle;  // made with the context
     if (e == hipSuccess) {
       Phase ph(c, 0, s);
       e = launch_frame_prep(d, X, N, s, 0);
+      if (e == hipSuccess) e = launch_alpha(d, s);
     }
     if (e == hipSuccess) e = hipEventRecord(c->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
     if (e == hipSuccess) {
       Phase ph(c, 1, c->side);
-      e = prepare_components(c, c->side, false);
+      e = prepare_components(c, c->side, false, false);
     }
     if (e == hipSuccess) e = hipEventRecord(c->join, c->side);
     // the KL terms (ELBO only) beside the sweep; the caller's stream waits for them after pass 1

@@ -151,6 +151,8 @@ constexpr int64_t STATE_MAGIC = 0x5342474256ll;  // "VBGBS"
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // float -> bfloat16, round to nearest even (finite inputs)
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -291,7 +293,10 @@ struct Init0 {
 hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& init, hipStream_t s);
 // part: 0 frame moments, 1 features, 2 both
 hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s, int part = 2);
-hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv = nullptr);
+// the sum of alpha over the posterior (FrameInfo::sum_alpha_q), which the coefficient rows need
+hipError_t launch_alpha(const DevPtrs& d, hipStream_t s);
+// alpha = false: launch_alpha has already run on this stream or one it waited for
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv = nullptr, bool alpha = true);
 // per-component KL terms of the ELBO (after launch_coeffs: it reads the frame's alpha sum)
 hipError_t launch_kl(const DevPtrs& d, hipStream_t s);
 hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s);
