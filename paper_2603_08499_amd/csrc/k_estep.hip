@@ -1150,15 +1150,29 @@ __global__ __launch_bounds__(256) void k_pass2(const EArgs a) {
 // v * 2^64 as a two's-complement 128-bit integer {lo, hi} added with integer atomics: the sum is
 // exact (to 2^-64 per term) and independent of the order of the additions, so the statistics
 // are bitwise reproducible without sorting the contributions by component.
-__device__ __forceinline__ void fx_add(unsigned long long* cell, double v) {
-#pragma clang fp contract(off)  // (as in fx_acc)
+// The 128-bit fixed-point image of v: v = hi + lo 2^-64 up to the bits below 2^-64, which are
+// dropped (hi = floor(v), returned as an integer-valued double; 0 <= lo < 2^64). Every step is
+// exact in FP64 (a power-of-two scaling, the difference of a number and its floor), and the
+// fraction's two 32-bit halves are converted separately.
+__device__ __forceinline__ double fx_split(double v, unsigned long long& lo) {
+  // no fusion of v - hi_d with the product that made v: every path converts the same rounded v
+#pragma clang fp contract(off)
   double hi_d = floor(v);
   double frac = v - hi_d;  // exact, in [0, 1]
-  if (frac >= 1.0) {
+  if (frac >= 1.0) {  // (v a tiny negative number)
     frac = 0.0;
     hi_d += 1.0;
   }
-  const unsigned long long lo = (unsigned long long)(frac * 18446744073709551616.0);
+  const double f1 = ldexp(frac, 32);     // [0, 2^32)
+  const double a1 = floor(f1);
+  const double f2 = ldexp(f1 - a1, 32);  // exact, [0, 2^32)
+  lo = ((unsigned long long)(uint32_t)a1 << 32) | (unsigned long long)(uint32_t)f2;
+  return hi_d;
+}
+
+__device__ __forceinline__ void fx_add(unsigned long long* cell, double v) {
+  unsigned long long lo;
+  const double hi_d = fx_split(v, lo);
   const unsigned long long old = atomicAdd(&cell[0], lo);
   const long long h = (long long)hi_d + ((old + lo < old) ? 1 : 0);
   if (h != 0) atomicAdd(&cell[1], (unsigned long long)h);
@@ -1695,23 +1709,24 @@ hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t
   return hipGetLastError();
 }
 
+// one thread per candidate list (point i / 4, list i % 4), so that a point's four lists are
+// placed in parallel; eight pairs at a time, so that their cursor atomics are in flight together
 __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= a.N || a.cand_n[p * 4] < 0) return;
-  // eight pairs at a time, so that their cursor atomics are in flight together
-  for (int g = 0; g < 4; ++g) {
-    const int cnt = a.cand_n[p * 4 + g];
-    const int32_t* ck = a.cand_k + (p * 4 + g) * CS;
-    for (int j0 = 0; j0 < cnt; j0 += 8) {
-      int32_t k[8], pos[8];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.N * 4) return;
+  const int64_t p = i >> 2;
+  const int cnt = a.cand_n[i];
+  if (cnt <= 0 || a.cand_n[p * 4] < 0) return;  // (an overflowed point: the rescan's statistics)
+  const int32_t* ck = a.cand_k + i * CS;
+  for (int j0 = 0; j0 < cnt; j0 += 8) {
+    int32_t k[8], pos[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) k[u] = j0 + u < cnt ? ck[j0 + u] : -1;
+    for (int u = 0; u < 8; ++u) k[u] = j0 + u < cnt ? ck[j0 + u] : -1;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) pos[u] = k[u] >= 0 ? a.coffset[k[u]] + atomicAdd(&a.ccursor[k[u]], 1) : -1;
+    for (int u = 0; u < 8; ++u) pos[u] = k[u] >= 0 ? a.coffset[k[u]] + atomicAdd(&a.ccursor[k[u]], 1) : -1;
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (k[u] >= 0) a.ent_n[pos[u]] = (int32_t)p;
-    }
+    for (int u = 0; u < 8; ++u)
+      if (k[u] >= 0) a.ent_n[pos[u]] = (int32_t)p;
   }
 }
 
@@ -1721,20 +1736,38 @@ __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
 struct Fx128 {
   unsigned long long lo;
   long long hi;
+  double hd;  // more of hi, summed in FP64 by fx_acc_small
 };
 
 __device__ __forceinline__ void fx_acc(Fx128& a, double v) {
-  // no fusion of v - hi_d with the product that made v: every path converts the same rounded v
-#pragma clang fp contract(off)
-  double hi_d = floor(v);
-  double frac = v - hi_d;
-  if (frac >= 1.0) {
-    frac = 0.0;
-    hi_d += 1.0;
-  }
-  const unsigned long long lo = (unsigned long long)(frac * 18446744073709551616.0);
+  unsigned long long lo;
+  const double hi_d = fx_split(v, lo);
   a.lo += lo;
   a.hi += (long long)hi_d + (a.lo < lo ? 1 : 0);
+}
+
+// fx_acc for |v| < 2^26: the integer parts are summed in FP64, exactly (fewer than 2^25 terms per
+// sum, since N < 2^25, so every partial sum stays below 2^52)
+__device__ __forceinline__ void fx_acc_small(Fx128& a, double v) {
+  unsigned long long lo;
+  const double hi_d = fx_split(v, lo);
+  a.lo += lo;
+  a.hd += hi_d + (a.lo < lo ? 1.0 : 0.0);
+}
+
+// hi with the FP64 part folded in
+__device__ __forceinline__ void fx_fold(Fx128& a) {
+  a.hi += (long long)a.hd;
+  a.hd = 0.0;
+}
+
+// the record of one pair keeps every product r u_i u_j below 2^26 (r <= 1): all |u_i| < 2^13
+template <int DT>
+__device__ __forceinline__ bool small_offsets(const double* u) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < DT; ++i) ok = ok && fabs(u[i]) < 8192.0;
+  return ok;
 }
 
 // A component with more than HEAVY kept pairs is summed by a whole workgroup (k_comp_stats_heavy),
@@ -1776,7 +1809,7 @@ __device__ __forceinline__ void comp_stats_emit(const EArgs& a, int64_t k, int f
 template <int DT>
 __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
   constexpr int F = 1 + DT + DT * (DT + 1) / 2;
-  constexpr int R = 1 + DT, NG = 256 / SG;
+  constexpr int R = 2 + DT, NG = 256 / SG;  // per pair: r, u[DT], 1
   __shared__ double buf[256 * R];
   __shared__ Fx128 part[NG][SG];
   __shared__ int32_t heavy[64];
@@ -1803,6 +1836,8 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
           fj = j;
         }
   }
+  // the slots this lane multiplies: r u_i u_j as (r u_i) u_j, an absent factor reading the 1
+  const int ia = fi >= 0 ? 1 + fi : R - 1, ib = fj >= 0 ? 1 + fj : R - 1;
   double is[DT];
 #pragma unroll
   for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
@@ -1811,10 +1846,12 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
     Fx128 acc;  // group 0 starts from the overflowed points' contributions
     acc.lo = grp == 0 && l < F ? a.fx[(k * FP + l) * 2] : 0ull;
     acc.hi = grp == 0 && l < F ? (long long)a.fx[(k * FP + l) * 2 + 1] : 0ll;
+    acc.hd = 0.0;
     const double* row = a.direct + k * a.dts;
     const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
     for (int32_t c0 = e0; c0 < e1; c0 += 256) {
       const int m = min(256, e1 - c0);
+      bool small = true;
       if (tid < m) {
         const int64_t n = a.ent_n[c0 + tid];
         double d[DT];
@@ -1822,20 +1859,27 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
         buf[tid * R] = exp2(s2 - a.lse2[n]);
 #pragma unroll
         for (int i = 0; i < DT; ++i) buf[tid * R + 1 + i] = d[i] * is[i];
+        buf[tid * R + R - 1] = 1.0;
+        small = small_offsets<DT>(buf + tid * R + 1);
       }
-      __syncthreads();
+      const bool all_small = __syncthreads_and(small ? 1 : 0);
       if (l < F) {
         const int q1 = min(m, grp * SG + SG);
-        for (int q = grp * SG; q < q1; ++q) {
-          const double* rq = buf + q * R;
-          double v = rq[0];
-          if (fi >= 0) v = v * rq[1 + fi];
-          if (fj >= 0) v = v * rq[1 + fj];
-          fx_acc(acc, v);
+        if (all_small) {
+          for (int q = grp * SG; q < q1; ++q) {
+            const double* rq = buf + q * R;
+            fx_acc_small(acc, (rq[0] * rq[ia]) * rq[ib]);
+          }
+        } else {
+          for (int q = grp * SG; q < q1; ++q) {
+            const double* rq = buf + q * R;
+            fx_acc(acc, (rq[0] * rq[ia]) * rq[ib]);
+          }
         }
       }
       __syncthreads();
     }
+    fx_fold(acc);
     part[grp][l] = acc;
     __syncthreads();
     const bool own = grp == 0 && l < F;
@@ -1864,7 +1908,7 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
 template <int DT>
 __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
   constexpr int F = 1 + DT + DT * (DT + 1) / 2;
-  constexpr int R = 1 + DT;  // per pair: r, u[DT]
+  constexpr int R = 2 + DT;  // per pair: r, u[DT], 1
   __shared__ double buf[256 / SG][SG * R];
   const int grp = threadIdx.x / SG, l = threadIdx.x % SG;
   const int64_t k = (int64_t)blockIdx.x * (256 / SG) + grp;
@@ -1882,10 +1926,13 @@ __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
           fj = j;
         }
   }
+  // the slots this lane multiplies: r u_i u_j as (r u_i) u_j, an absent factor reading the 1
+  const int ia = fi >= 0 ? 1 + fi : R - 1, ib = fj >= 0 ? 1 + fj : R - 1;
   const bool mine = val && l < F;
   Fx128 acc;  // starts from the overflowed points' contributions
   acc.lo = mine ? a.fx[(k * FP + l) * 2] : 0ull;
   acc.hi = mine ? (long long)a.fx[(k * FP + l) * 2 + 1] : 0ll;
+  acc.hd = 0.0;
   if (val) {
     double is[DT];
 #pragma unroll
@@ -1895,6 +1942,7 @@ __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
     const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
     for (int32_t c0 = e0; c0 < e1; c0 += SG) {
       const int m = min(SG, e1 - c0);
+      bool small = true;
       if (l < m) {
         const int64_t n = a.ent_n[c0 + l];
         double d[DT];
@@ -1902,18 +1950,26 @@ __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
         rec[l * R] = exp2(s2 - a.lse2[n]);
 #pragma unroll
         for (int i = 0; i < DT; ++i) rec[l * R + 1 + i] = d[i] * is[i];
+        rec[l * R + R - 1] = 1.0;
+        small = small_offsets<DT>(rec + l * R + 1);
       }
+      const bool all_small = __ballot(!small) == 0ull;  // (both groups of the wave)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (l < F)
-        for (int q = 0; q < m; ++q) {
-          const double* rq = rec + q * R;
-          double v = rq[0];
-          if (fi >= 0) v = v * rq[1 + fi];
-          if (fj >= 0) v = v * rq[1 + fj];
-          fx_acc(acc, v);
+      if (l < F) {
+        if (all_small) {
+          for (int q = 0; q < m; ++q) {
+            const double* rq = rec + q * R;
+            fx_acc_small(acc, (rq[0] * rq[ia]) * rq[ib]);
+          }
+        } else {
+          for (int q = 0; q < m; ++q) {
+            const double* rq = rec + q * R;
+            fx_acc(acc, (rq[0] * rq[ia]) * rq[ib]);
+          }
         }
+      }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1921,6 +1977,7 @@ __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
   }
   double v = 0.0;
   if (mine) {  // fixed point -> FP64, undo the scaling; raw coordinates centred at m_k
+    fx_fold(acc);
     v = (double)acc.hi + (double)acc.lo * 5.42101086242752217e-20;
     if (fi >= 0) v = v * a.frame->s[fi];
     if (fj >= 0) v = v * a.frame->s[fj];
@@ -2168,7 +2225,7 @@ hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s) {
 // statistics of the kept candidates: overflowed points (atomics), transpose, per-component sums
 hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) {
   if (N > 0) {
-    const dim3 gp((unsigned)((N + 255) / 256));
+    const dim3 gp((unsigned)((4 * N + 255) / 256));  // k_scatter_pairs: one thread per candidate list
     const int64_t nsb = (a.K + SCAN_B - 1) / SCAN_B;
     switch (D) {
 #define VB_ST(DD)                                                                         \
