@@ -88,7 +88,7 @@ def run_c4(args):
     data = []
     for t in range(n_ex):  # targets at the final prior of the exact frames
         m.estep_stats(Xs[t], lse=False, stats=False)
-        data.append((Xs[t], *m.export_targets(N)))
+        data.append((Xs[t], *m.export_targets(Xs[t])))
     torch.cuda.synchronize()
     steps = args.c4_train_steps
     print("bench c4: training %d steps" % steps, file=sys.stderr, flush=True)
@@ -118,7 +118,7 @@ def run_c4(args):
         reps.append(r)
         if r[0] and args.c4_retrain > 0:  # the fallback ran the exact E-step: its pairs are targets
             r0 = time.perf_counter()
-            data.append((X, *m.export_targets(N)))
+            data.append((X, *m.export_targets(X)))
             driver.train_on_targets(m, data, args.c4_retrain, 4096, 1e-3, 100 + i)
             torch.cuda.synchronize()
             t_re += time.perf_counter() - r0

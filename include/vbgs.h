@@ -317,8 +317,11 @@ vbgs_status vbgs_proposal_candidates(vbgs_ctx* ctx, const float* X, int64_t N, i
 
 /* After a vbgs_estep_stats (exact mode): training targets per point, the kept pairs of the
  * exact E-step (at most 64), tk (device, N x 64 int32, -1 = empty) and their responsibilities
- * tr (device, N x 64 FP32). N must equal the N of that E-step. */
-vbgs_status vbgs_export_targets(vbgs_ctx* ctx, int64_t N, int32_t* tk, float* tr, void* stream);
+ * tr (device, N x 64 FP32, each pair's FP64 score computed again from X, rounded once).
+ * X (device, N x D FP32) must hold the points of that E-step and N its N (the points are not
+ * kept by the library; other points give the responsibilities of the kept pairs at those
+ * points). VBGS_ERR_ARG for a null pointer; VBGS_ERR_STATE when N differs from that E-step's. */
+vbgs_status vbgs_export_targets(vbgs_ctx* ctx, const float* X, int64_t N, int32_t* tk, float* tr, void* stream);
 
 /* One training step of the proposal on a minibatch: rows batch_idx (device int32, B of them) of
  * the points X and of the targets (tk, tr as exported). Loss: mean over the batch of

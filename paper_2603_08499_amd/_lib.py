@@ -63,7 +63,7 @@ def load():
         "vbgs_proposal_set": (i32, [vp] + [vp] * 8 + [vp]),
         "vbgs_proposal_get": (i32, [vp] + [vp] * 6 + [vp]),
         "vbgs_estep_stats_pruned": (i32, [vp, vp, i64, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp]),
-        "vbgs_export_targets": (i32, [vp, i64, vp, vp, vp]),
+        "vbgs_export_targets": (i32, [vp, vp, i64, vp, vp, vp]),
         "vbgs_proposal_candidates": (i32, [vp, vp, i64, vp, vp]),
         "vbgs_proposal_train_step": (i32, [vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, vp, vp, vp]),
         "vbgs_timing": (i32, [vp, i32]),

@@ -253,6 +253,38 @@ __device__ __forceinline__ void record_candidate(const EArgs& a, int64_t p, int 
   }
 }
 
+// The pairs of one candidate list that can carry mass (score >= thr) are counted per component;
+// the count before this pair's increment, its rank among the component's pairs, replaces its score
+// (cs, as the bits of an int32) and places it in the transpose (k_scatter_pairs). The others
+// leave the list (ck = -1). Eight at a time, so that the loads and the atomics of a chunk are in
+// flight together.
+__device__ __forceinline__ void keep_pairs(const EArgs& a, int32_t* __restrict__ ck, float* __restrict__ cs, int cn,
+                                           float thr, unsigned& kept) {
+  for (int j0 = 0; j0 < cn; j0 += 8) {
+    float sv[8];
+    int32_t kv[8], rk[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = j0 + u < cn;
+      sv[u] = in ? cs[j0 + u] : -INFINITY;
+      kv[u] = in ? ck[j0 + u] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rk[u] = kv[u] >= 0 && sv[u] >= thr ? atomicAdd(&a.ccount[kv[u]], 1) : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j0 + u < cn) {
+        if (rk[u] >= 0) {
+          cs[j0 + u] = __int_as_float(rk[u]);
+          ++kept;
+        } else {
+          ck[j0 + u] = -1;
+        }
+      }
+    }
+  }
+}
+
 template <int P, bool EXACT>
 __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
   __shared__ CTile<P> T[2];
@@ -609,19 +641,6 @@ __device__ __forceinline__ void screen_tile(const EArgs& a, SweepWave<P>& S, int
         }
       }
     }
-  }
-}
-
-// FP64 score (log2 units) of one pair in direct form, for the run-time D of the wave
-__device__ __forceinline__ double direct_score2_rt(const double* __restrict__ row, const float* __restrict__ x, int D) {
-  double d[MAXD];
-  switch (D) {
-    case 1: return direct_score2_dt<1>(row, x, d);
-    case 2: return direct_score2_dt<2>(row, x, d);
-    case 3: return direct_score2_dt<3>(row, x, d);
-    case 4: return direct_score2_dt<4>(row, x, d);
-    case 5: return direct_score2_dt<5>(row, x, d);
-    default: return direct_score2_dt<6>(row, x, d);
   }
 }
 
@@ -1008,14 +1027,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       const double L2 = mm + log2(ll);
       if (g == 0) a.lse2[p] = L2;
       const float thr = (float)(L2 - (double)a.T2);  // FP32 rounding is monotone (see evict_candidates)
-      for (int j = 0; j < S.cn[b]; ++j) {
-        if (cs[j] >= thr) {
-          atomicAdd(&a.ccount[ck[j]], 1);
-          ++kept;
-        } else {
-          ck[j] = -1;
-        }
-      }
+      keep_pairs(a, ck, cs, S.cn[b], thr, kept);
     }
   }
   count_refined(&a.frame->refined2, kept);
@@ -1382,18 +1394,8 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
       a.lse2[p] = L2;
       // keep the pairs that can carry mass (FP32 rounding is monotone, see evict_candidates)
       const float thr = (float)(L2 - (double)a.T2);
-      for (int g = 0; g < 4; ++g) {
-        const int cnt = a.cand_n[p * 4 + g];
-        for (int j = 0; j < cnt; ++j) {
-          const int64_t e = (p * 4 + g) * CS + j;
-          if (a.cand_s[e] >= thr) {
-            atomicAdd(&a.ccount[a.cand_k[e]], 1);
-            ++kept;
-          } else {
-            a.cand_k[e] = -1;
-          }
-        }
-      }
+      for (int g = 0; g < 4; ++g)
+        keep_pairs(a, a.cand_k + (p * 4 + g) * CS, a.cand_s + (p * 4 + g) * CS, a.cand_n[p * 4 + g], thr, kept);
     }
     if (a.lse_out) a.lse_out[p] = L2 * LN2;
   }
@@ -1709,8 +1711,8 @@ hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t
   return hipGetLastError();
 }
 
-// one thread per candidate list (point i / 4, list i % 4), so that a point's four lists are
-// placed in parallel; eight pairs at a time, so that their cursor atomics are in flight together
+// one thread per candidate list (point i / 4, list i % 4): each kept pair goes to its component's
+// segment at the rank it drew when it was kept (keep_pairs)
 __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= a.N * 4) return;
@@ -1718,15 +1720,17 @@ __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
   const int cnt = a.cand_n[i];
   if (cnt <= 0 || a.cand_n[p * 4] < 0) return;  // (an overflowed point: the rescan's statistics)
   const int32_t* ck = a.cand_k + i * CS;
+  const float* cs = a.cand_s + i * CS;
   for (int j0 = 0; j0 < cnt; j0 += 8) {
-    int32_t k[8], pos[8];
+    int32_t k[8], r[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) k[u] = j0 + u < cnt ? ck[j0 + u] : -1;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) pos[u] = k[u] >= 0 ? a.coffset[k[u]] + atomicAdd(&a.ccursor[k[u]], 1) : -1;
+    for (int u = 0; u < 8; ++u) {
+      k[u] = j0 + u < cnt ? ck[j0 + u] : -1;
+      r[u] = j0 + u < cnt ? __float_as_int(cs[j0 + u]) : 0;
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (k[u] >= 0) a.ent_n[pos[u]] = (int32_t)p;
+      if (k[u] >= 0) a.ent_n[a.coffset[k[u]] + r[u]] = (int32_t)p;
   }
 }
 
@@ -2145,7 +2149,6 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
   if (stage == 0) {
     const int64_t Kp1 = a.Kpad + 1;
     hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, a.gate);
-    hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1, a.gate);
     hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, a.gate);
   } else if (stage == 1) {  // the screen's choice and, with culling, the blocks' dispatch order
     hipLaunchKernelGGL(k_screen_part, dim3(SCR_BLOCKS), dim3(256), 0, s, a.nc, a.Kpad, a.nphi, N, a.scr_part);
@@ -2204,7 +2207,6 @@ hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStr
 hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s) {
   const int64_t Kp1 = a.Kpad + 1;
   hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, nullptr);
-  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccursor, Kp1, nullptr);
   hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, nullptr);
   if (N <= 0) return hipGetLastError();
   EArgs u = a;
@@ -2284,7 +2286,6 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.fx = d.at<unsigned long long>(L.fx);
   a.ccount = d.at<int32_t>(L.ccount);
   a.coffset = d.at<int32_t>(L.coffset);
-  a.ccursor = d.at<int32_t>(L.ccursor);
   a.ent_n = d.at<int32_t>(L.ent_n);
   a.frame = d.frame();
   a.gate = c.gate;

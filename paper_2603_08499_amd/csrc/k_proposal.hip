@@ -649,6 +649,21 @@ __global__ void k_no_audit(int32_t* gate, double* report) {
 // ---------------------------------------------------------------------------
 // training targets from an exact E-step: the kept pairs with r = 2^(s - LSE)
 // ---------------------------------------------------------------------------
+// FP64 score (log2 units) of one pair in direct form, any supported D
+__device__ double score2_anyd(const double* __restrict__ row, const float* __restrict__ x, int D) {
+  double d[MAXD];
+  switch (D) {
+    case 1: return direct_score2_dt<1>(row, x, d);
+    case 2: return direct_score2_dt<2>(row, x, d);
+    case 3: return direct_score2_dt<3>(row, x, d);
+    case 4: return direct_score2_dt<4>(row, x, d);
+    case 5: return direct_score2_dt<5>(row, x, d);
+    case 6: return direct_score2_dt<6>(row, x, d);
+    case 7: return direct_score2_dt<7>(row, x, d);
+    default: return direct_score2_dt<8>(row, x, d);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_export_targets(const EArgsLite e, int64_t N, int32_t* __restrict__ tk,
                                                         float* __restrict__ tr) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -662,8 +677,10 @@ __global__ __launch_bounds__(256) void k_export_targets(const EArgsLite e, int64
         const int64_t q = (p * 4 + g) * CS + j;
         const int32_t k = e.cand_k[q];
         if (k < 0) continue;
+        // (the E-step keeps a kept pair's rank in its score slot: the score is computed again)
+        const double s2 = score2_anyd(e.direct + (int64_t)k * e.dts, e.X + p * e.D, e.D);
         tk[p * 64 + m] = k;
-        tr[p * 64 + m] = (float)exp2((double)e.cand_s[q] - L2);
+        tr[p * 64 + m] = (float)exp2(s2 - L2);
         ++m;
       }
     }

@@ -280,7 +280,6 @@ Layout make_layout(const vbgs_params& p) {
   L.fx = take(sparse ? (size_t)L.Kpad * FP * 16 : 0);
   L.ccount = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
   L.coffset = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
-  L.ccursor = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
   L.ent_n = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
   int64_t npow = 2048, kpow = 2048;
   while (npow < n) npow <<= 1;
@@ -1081,13 +1080,13 @@ vbgs_status vbgs_proposal_candidates(vbgs_ctx* c, const float* X, int64_t N, int
   return hipfail(c, e, "proposal_candidates");
 }
 
-vbgs_status vbgs_export_targets(vbgs_ctx* c, int64_t N, int32_t* tk, float* tr, void* stream) {
-  if (!c || !tk || !tr) return VBGS_ERR_ARG;
+vbgs_status vbgs_export_targets(vbgs_ctx* c, const float* X, int64_t N, int32_t* tk, float* tr, void* stream) {
+  if (!c || !X || !tk || !tr) return VBGS_ERR_ARG;
   if (c->p.score_prec == VBGS_FP64 || !c->p.exact) return fail(c, VBGS_ERR_UNSUPPORTED, "needs the exact MFMA mode");
   if (!c->have_stats || N != c->last_N) return fail(c, VBGS_ERR_STATE, "N must match the last E-step");
   VBGS_SETTLE(c, stream);
   EstepCfg cfg{c->p.score_prec, 1, c->T2, 1};
-  const EArgs ea = make_eargs(c->dev(), cfg, nullptr, N, nullptr);
+  const EArgs ea = make_eargs(c->dev(), cfg, X, N, nullptr);
   return hipfail(c, launch_export_targets(ea, N, tk, tr, S(stream)), "export_targets");
 }
 

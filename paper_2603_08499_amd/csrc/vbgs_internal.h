@@ -115,7 +115,7 @@ struct Layout {
   size_t phi8, phis, c8, cs8;  // FP8 tier: e4m3 rows and the factors that undo their scaling
   int fp8;
   size_t frame, mom_part, phi32, phih, phil, nphi, lse2, lse_part, direct, c32, ch, cl, nc, kl,
-      spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ccursor, ent_n, total;
+      spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ent_n, total;
   int64_t Kpad, n_lse_part;
   int nsplit_max;
   // spatial ordering (culled exact sweep)
@@ -245,6 +245,19 @@ __device__ __forceinline__ double direct_score2_dt(const double* __restrict__ T,
   return T[0] - q;
 }
 
+// FP64 score (log2 units) of one pair in direct form, for a run-time D <= 6 (the MFMA paths)
+__device__ __forceinline__ double direct_score2_rt(const double* __restrict__ row, const float* __restrict__ x, int D) {
+  double d[MAXD];
+  switch (D) {
+    case 1: return direct_score2_dt<1>(row, x, d);
+    case 2: return direct_score2_dt<2>(row, x, d);
+    case 3: return direct_score2_dt<3>(row, x, d);
+    case 4: return direct_score2_dt<4>(row, x, d);
+    case 5: return direct_score2_dt<5>(row, x, d);
+    default: return direct_score2_dt<6>(row, x, d);
+  }
+}
+
 template <int D>
 __device__ __forceinline__ double direct_score2_t(const double* __restrict__ T, const double* __restrict__ x) {
   double d[D];
@@ -354,9 +367,8 @@ struct EArgs {
   int32_t* cand_n;            // N x 4 list lengths, -1 = overflowed point
   int32_t* over_list;         // overflowed points
   unsigned long long* fx;     // Kpad x 32 x {lo, hi}: 128-bit fixed-point statistics (overflowed points)
-  int32_t* ccount;            // Kpad + 1: kept pairs per component
+  int32_t* ccount;            // Kpad + 1: kept pairs per component (their ranks: keep_pairs)
   int32_t* coffset;           // Kpad + 1: exclusive scan of ccount
-  int32_t* ccursor;           // Kpad + 1: scatter cursors
   int32_t* ent_n;             // kept pairs grouped by component: point index
   FrameInfo* frame;
   const int32_t* gate;        // when set, the exact dense kernels run only if gate[0] != 0

@@ -72,7 +72,7 @@ def run_stream(model: VBGS, frames: List[torch.Tensor], n_exact: int, train_step
                 model.estep_stats(X, lse=False, stats=False)
                 F = model.elbo()
                 if last and model.params.proposal:
-                    tk, tr = model.export_targets(N)
+                    tk, tr = model.export_targets(X)
                     data.append((X, tk, tr))
                 model.update(commit=last)
                 logs.append(FrameLog(t, "exact", float(F.item())))
@@ -87,7 +87,7 @@ def run_stream(model: VBGS, frames: List[torch.Tensor], n_exact: int, train_step
                 logs.append(FrameLog(t, "pruned", float(F.item()), bool(r[0]), float(r[1]), float(r[2])))
                 if last and r[0] and retrain_steps > 0:
                     model.estep_stats(X, lse=False, stats=False)  # exact targets of the failed frame
-                    data.append((X, *model.export_targets(N)))
+                    data.append((X, *model.export_targets(X)))
                     train_on_targets(model, data, retrain_steps, batch, lr, seed + t)
         if t == n_exact - 1 and model.params.proposal and train_steps > 0:
             train_on_targets(model, data, train_steps, batch, lr, seed)

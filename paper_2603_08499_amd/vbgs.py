@@ -288,10 +288,13 @@ class VBGS:
         self._check(self.lib.vbgs_proposal_candidates(self.ctx, _ptr(X), X.shape[0], _ptr(out), _stream()))
         return out
 
-    def export_targets(self, N):
+    def export_targets(self, X):
+        """Training targets of the last exact E-step, whose points X must be."""
+        X = self._points(X)
+        N = X.shape[0]
         tk = torch.empty((N, 64), dtype=torch.int32, device=self.device)
         tr = torch.empty((N, 64), dtype=torch.float32, device=self.device)
-        self._check(self.lib.vbgs_export_targets(self.ctx, int(N), _ptr(tk), _ptr(tr), _stream()))
+        self._check(self.lib.vbgs_export_targets(self.ctx, _ptr(X), int(N), _ptr(tk), _ptr(tr), _stream()))
         return tk, tr
 
     def n_train(self):

@@ -212,14 +212,15 @@ def test_forced_fallback_and_audit_report(dev, bound, expect_fallback):
 def test_exported_targets_are_the_exact_responsibilities(dev):
     X, pr = scenes.random_problem(1500, 250, 6, seed=49)
     m = _model(dev, pr, X.shape[0])
-    m.estep_stats(torch.from_numpy(X).to(dev), lse=False, stats=False)
-    tk, tr = m.export_targets(X.shape[0])
+    Xg = torch.from_numpy(X).to(dev)
+    m.estep_stats(Xg, lse=False, stats=False)
+    tk, tr = m.export_targets(Xg)
     torch.cuda.synchronize()
     tk, tr = tk.cpu().numpy(), tr.cpu().numpy()
     Rr = R.responsibilities(X, R.NW.from_prior(pr))
     for n in range(0, X.shape[0], 7):
         ks = tk[n][tk[n] >= 0]
-        # the exported r come from exact scores stored as FP32 (about 1e-6 relative)
+        # the exported r are exact FP64 responsibilities rounded to FP32
         assert np.allclose(tr[n][:ks.size], Rr[n, ks], rtol=1e-5, atol=1e-30)
         assert Rr[n, ks].sum() > 1 - 1e-9
         assert len(set(ks.tolist())) == ks.size
