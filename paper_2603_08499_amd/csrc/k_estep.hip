@@ -1229,6 +1229,7 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n, const int32_t* gate
 // BO_MAX, or a reset, keeps the Morton order. Any order gives the same results.
 constexpr int BO_SPAN = 32;  // previous blocks looked at per block
 constexpr int BO_MAX = 4096;
+constexpr int BO_LDS = 8192;  // previous blocks whose codes are searched in LDS
 
 __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost, const uint32_t* __restrict__ bcode,
                                                       const uint32_t* __restrict__ pcode, int64_t N, int64_t nb,
@@ -1247,6 +1248,12 @@ __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost,
     for (int64_t i = tid; i < len; i += 1024) border[start + i] = (int32_t)(start + i);
     return;
   }
+  // the previous launch's block codes in LDS for the searches below (when they fit)
+  __shared__ uint32_t bcs[BO_LDS];
+  const bool in_lds = np <= BO_LDS;
+  if (in_lds)
+    for (int64_t i = tid; i < np; i += 1024) bcs[i] = bcode[i];
+  __syncthreads();
   int n2 = 1;
   while (n2 < len) n2 <<= 1;
   for (int i = tid; i < n2; i += 1024) {
@@ -1257,7 +1264,7 @@ __global__ __launch_bounds__(1024) void k_block_order(float* __restrict__ bcost,
         int64_t lo = 0, hi = np - 1;
         while (lo < hi) {
           const int64_t mid = (lo + hi + 1) >> 1;
-          if (bcode[mid] <= code) lo = mid;
+          if ((in_lds ? bcs[mid] : bcode[mid]) <= code) lo = mid;
           else hi = mid - 1;
         }
         return lo;
@@ -2150,9 +2157,10 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
     const int64_t Kp1 = a.Kpad + 1;
     hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a.ccount, Kp1, a.gate);
     hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, s, a.fx, a.Kpad * FP * 2, a.gate);
-  } else if (stage == 1) {  // the screen's choice and, with culling, the blocks' dispatch order
+  } else if (stage == 1) {  // the screen's choice (needs the component rows)
     hipLaunchKernelGGL(k_screen_part, dim3(SCR_BLOCKS), dim3(256), 0, s, a.nc, a.Kpad, a.nphi, N, a.scr_part);
     hipLaunchKernelGGL(k_screen_pick, dim3(1), dim3(256), 0, s, a.scr_part, a.K, N, prec, a.frame, a.scr_gate);
+  } else if (stage == 4) {  // with culling, the blocks' dispatch order (needs the point order only)
     if (cull)
       hipLaunchKernelGGL(k_block_order, dim3(8), dim3(1024), 0, s, a.bcost, a.bcode, a.pcode, N, (int64_t)((N + 63) / 64),
                          a.nb_cap, a.bprev, a.border, a.order_reset);
@@ -2198,7 +2206,7 @@ static hipError_t exact_stage(const EArgs& a, int prec, int D, int64_t N, hipStr
 
 hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull) {
   hipError_t e = hipSuccess;
-  for (const int stage : {0, 1, 3, 2})
+  for (const int stage : {0, 4, 1, 3, 2})
     if (e == hipSuccess) e = exact_stage(a, prec, D, N, s, cull, stage);
   return e;
 }
@@ -2346,7 +2354,7 @@ hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int
     if (stage >= 0) return exact_stage(a, c.prec, d.D, N, s, c.cull, stage);
     return launch_exact_sweep(a, c.prec, d.D, N, s, c.cull);
   }
-  if (stage == 0 || stage == 1 || stage == 2) return hipSuccess;  // the whole pass is stage 3 (or -1)
+  if (stage == 0 || stage == 1 || stage == 2 || stage == 4) return hipSuccess;  // the whole pass is stage 3 (or -1)
   if (c.prec == VBGS_FP64) {
     const dim3 grid((unsigned)((N + 255) / 256));
     switch (d.D) {

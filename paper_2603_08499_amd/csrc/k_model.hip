@@ -609,13 +609,38 @@ hipError_t launch_kl(const DevPtrs& d, hipStream_t s) {
 // conjugate update through natural parameters (FP64, one thread per component)
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void k_update(double* prior, double* post, const double* __restrict__ st, int64_t K, int commit,
+__global__ __launch_bounds__(256) void k_update(double* prior, double* post, const double* __restrict__ st, int64_t K, int commit,
                          int split) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   constexpr int F = 1 + D + D * (D + 1) / 2;
-  const double* p = prior + k * REC;
-  const double* S = st + k * F;
+  // records are REC = 48 doubles (384 bytes) apart: their loads and stores go 16 bytes at a time;
+  // the prior record's doubles in use (through the second block's nu), rounded up to even
+  constexpr int PU = ((rec_kc(D) + 3) & ~1) < REC ? ((rec_kc(D) + 3) & ~1) : REC;
+  double p[PU + 2];
+  p[PU] = p[PU + 1] = 0.0;  // (past the record: a second block's kappa and nu, which D = 8 never has)
+  {
+    const f64x2* pv = reinterpret_cast<const f64x2*>(prior + k * REC);
+#pragma unroll
+    for (int i = 0; i < PU / 2; ++i) {
+      const f64x2 t = pv[i];
+      p[2 * i] = t.x;
+      p[2 * i + 1] = t.y;
+    }
+  }
+  double S[F];
+  if constexpr (F % 2 == 0) {
+    const f64x2* sv = reinterpret_cast<const f64x2*>(st + k * F);
+#pragma unroll
+    for (int i = 0; i < F / 2; ++i) {
+      const f64x2 t = sv[i];
+      S[2 * i] = t.x;
+      S[2 * i + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < F; ++i) S[i] = st[k * F + i];
+  }
   const double Nk = S[0];
   double r[REC];
 #pragma unroll
@@ -651,11 +676,13 @@ __global__ void k_update(double* prior, double* post, const double* __restrict__
                          ? p[3 + D + t] + S[o + t] + kp[b] * mp[i] * mp[j] - kappa[b] * m[i] * m[j]
                          : 0.0;
     }
+  f64x2* po = reinterpret_cast<f64x2*>(post + k * REC);
 #pragma unroll
-  for (int i = 0; i < REC; ++i) post[k * REC + i] = r[i];
+  for (int i = 0; i < REC / 2; ++i) po[i] = f64x2{r[2 * i], r[2 * i + 1]};
   if (commit) {
+    f64x2* pp = reinterpret_cast<f64x2*>(prior + k * REC);
 #pragma unroll
-    for (int i = 0; i < REC; ++i) prior[k * REC + i] = r[i];
+    for (int i = 0; i < REC / 2; ++i) pp[i] = f64x2{r[2 * i], r[2 * i + 1]};
   }
 }
 

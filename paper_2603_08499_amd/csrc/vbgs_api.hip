@@ -639,9 +639,12 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
       Phase ph(c, 8, s);
       e = launch_frame_prep(d, X, N, s, 1);
       if (e == hipSuccess) e = launch_sort_points(d, X, N, s);
+      // what needs no component work, while the side stream is still busy: the sweep's cleared
+      // counters and its blocks' dispatch order
+      if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, s, 0);
+      if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, s, 4);
     }
     if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join, 0);
-    if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, s, 0);
   } else {
     {
       Phase ph(c, 0, s);

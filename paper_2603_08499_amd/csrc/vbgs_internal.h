@@ -87,7 +87,7 @@ __device__ __forceinline__ float f_up(double v) {
 // and W (cross-block entries of W^-1 are zero). The record keeps block 0's kappa and nu at slots
 // 1 and 2 and block 1's at KC and KC + 1. With s = 0 all coordinates form one block.
 __host__ __device__ __forceinline__ int coord_block(int i, int split) { return (split > 0 && i >= split) ? 1 : 0; }
-__host__ __device__ __forceinline__ int rec_kc(int D) { return 3 + D + D * (D + 1) / 2; }
+__host__ __device__ constexpr int rec_kc(int D) { return 3 + D + D * (D + 1) / 2; }
 __device__ __forceinline__ double rec_kappa(const double* q, int D, int b) { return b ? q[rec_kc(D)] : q[1]; }
 __device__ __forceinline__ double rec_nu(const double* q, int D, int b) { return b ? q[rec_kc(D) + 1] : q[2]; }
 
@@ -397,8 +397,9 @@ struct EArgs {
 };
 EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out);
 // stage -1: the whole first pass; exact MFMA mode in stages 0 (clear the transpose counters),
-// 1 (screen choice and dispatch order), 3 (the screening sweep) and 2 (exact per-point LSE), in
-// that order; other modes run the whole pass in stage 3
+// 4 (with culling, the blocks' dispatch order), 1 (screen choice), 3 (the screening sweep) and 2
+// (exact per-point LSE), in that order (0 and 4 need no component work); other modes run the
+// whole pass in stage 3
 hipError_t launch_pass1(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, double* lse_out,
                         hipStream_t s, int stage = -1);
 // stats_out (or null): the caller's statistics; the exact mode writes them in pass 2 (fold is then empty)
