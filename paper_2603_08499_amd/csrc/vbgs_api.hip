@@ -40,9 +40,10 @@ struct vbgs_ctx {
   bool have_stats;
   bool order_reset;  // the sweep's block costs are not measured yet
   bool pending_clear;  // attached to a state: the workspace's flags and counters are not cleared yet
-  // side stream (default priority) for the component preparation, which overlaps the point
-  // preparation of the culled path; made on first use
-  hipStream_t side = nullptr;
+  // side streams (default priority) of the culled path: the component preparation, which overlaps
+  // the point preparation, and the KL terms of the ELBO, which overlap both (not the sweep: their
+  // waves hold most of a SIMD's registers and would keep the sweep's first blocks waiting)
+  hipStream_t side = nullptr, side2 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr;
   int nsplit;
   float T2;
@@ -403,11 +404,12 @@ static bool use_cull(const vbgs_ctx* c) {
   return c->p.score_prec != VBGS_FP64 && c->p.exact == 1 && c->p.cull == 1;
 }
 
-// the side stream and its two events (culled path only), made with the context so that no stream
+// the side streams and their events (culled path only), made with the context so that no stream
 // is created while a caller's stream may be capturing; on failure nothing is left behind
 static hipError_t make_side(vbgs_ctx* c) {
   if (c->side || !use_cull(c)) return hipSuccess;
   hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->kl_done, hipEventDisableTiming);
@@ -415,8 +417,9 @@ static hipError_t make_side(vbgs_ctx* c) {
     if (c->kl_done) hipEventDestroy(c->kl_done);
     if (c->join) hipEventDestroy(c->join);
     if (c->fork) hipEventDestroy(c->fork);
+    if (c->side2) hipStreamDestroy(c->side2);
     if (c->side) hipStreamDestroy(c->side);
-    c->side = nullptr;
+    c->side = c->side2 = nullptr;
     c->fork = c->join = c->kl_done = nullptr;
   }
   return e;
@@ -627,14 +630,16 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     }
     if (e == hipSuccess) e = hipEventRecord(c->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
+    // the KL terms (ELBO only) on a stream of their own; the caller's stream waits for them after
+    // pass 1
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side2, c->fork, 0);
+    if (e == hipSuccess) e = launch_kl(d, c->side2);
+    if (e == hipSuccess) e = hipEventRecord(c->kl_done, c->side2);
     if (e == hipSuccess) {
       Phase ph(c, 1, c->side);
       e = prepare_components(c, c->side, false, false);
     }
     if (e == hipSuccess) e = hipEventRecord(c->join, c->side);
-    // the KL terms (ELBO only) beside the sweep; the caller's stream waits for them after pass 1
-    if (e == hipSuccess) e = launch_kl(d, c->side);
-    if (e == hipSuccess) e = hipEventRecord(c->kl_done, c->side);
     if (e == hipSuccess) {
       Phase ph(c, 8, s);
       e = launch_frame_prep(d, X, N, s, 1);
@@ -1157,11 +1162,13 @@ const char* vbgs_last_error(const vbgs_ctx* c) { return c ? c->err.c_str() : "nu
 
 void vbgs_destroy(vbgs_ctx* c) {
   if (!c) return;
-  if (c->side) {  // its work precedes the join event that the caller's stream waited on
+  if (c->side) {  // their work precedes the events that the caller's stream waited on
     hipStreamSynchronize(c->side);
+    hipStreamSynchronize(c->side2);
     hipEventDestroy(c->fork);
     hipEventDestroy(c->join);
     hipEventDestroy(c->kl_done);
+    hipStreamDestroy(c->side2);
     hipStreamDestroy(c->side);
   }
   if (c->timers_made)
