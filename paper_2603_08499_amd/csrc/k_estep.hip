@@ -1917,10 +1917,11 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
 // offset u) into LDS, then lane f < F adds feature f (r, r u_i or r u_i u_j) of every pair of the
 // chunk into its own 128-bit sum, so no lane holds more than one sum.
 template <int DT>
-__global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_comp_stats(const EArgs a) {
   constexpr int F = 1 + DT + DT * (DT + 1) / 2;
   constexpr int R = 2 + DT;  // per pair: r, u[DT], 1
   __shared__ double buf[256 / SG][SG * R];
+  __shared__ f64x2 rows[256 / SG][16];  // each group's component row (direct form, 32 doubles)
   const int grp = threadIdx.x / SG, l = threadIdx.x % SG;
   const int64_t k = (int64_t)blockIdx.x * (256 / SG) + grp;
   const bool val = k < a.K && a.coffset[k + 1] - a.coffset[k] <= HEAVY;  // uniform over the group
@@ -1948,7 +1949,13 @@ __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
     double is[DT];
 #pragma unroll
     for (int i = 0; i < DT; ++i) is[i] = 1.0 / a.frame->s[i];
-    const double* row = a.direct + k * a.dts;
+    // the row once per group in LDS, read by every pair's score (instead of 28 registers per lane)
+    static_assert(SG >= 16, "row copy");
+    if (l < 16) rows[grp][l] = reinterpret_cast<const f64x2*>(a.direct + k * a.dts)[l];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double* row = reinterpret_cast<const double*>(rows[grp]);
     double* rec = buf[grp];
     const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
     for (int32_t c0 = e0; c0 < e1; c0 += SG) {
@@ -1970,11 +1977,13 @@ __global__ __launch_bounds__(256) void k_comp_stats(const EArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (l < F) {
         if (all_small) {
+#pragma unroll 2
           for (int q = 0; q < m; ++q) {
             const double* rq = rec + q * R;
             fx_acc_small(acc, (rq[0] * rq[ia]) * rq[ib]);
           }
         } else {
+#pragma unroll 2
           for (int q = 0; q < m; ++q) {
             const double* rq = rec + q * R;
             fx_acc(acc, (rq[0] * rq[ia]) * rq[ib]);
