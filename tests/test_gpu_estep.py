@@ -200,6 +200,35 @@ def test_edge_cases(dev):
 
 
 @gpu
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64_culled"])
+def test_large_scaled_offsets(dev, prec):
+    """Points within 1e-3 of each other (frame scale 2^-12) and components ~4 away: every kept
+    pair's scaled offset exceeds 2^13, so the per-component fixed-point sums take the path that
+    converts each integer part to 64 bits (the other path sums them in FP64)."""
+    print("case", prec, flush=True)
+    X0, pr = scenes.random_problem(1500, 40, 6, seed=88)
+    X = (X0 * 1e-3).astype(np.float32)
+    g = np.random.default_rng(88)
+    pr.m0 = 4.0 + g.normal(0.0, 0.002, pr.m0.shape)  # several components share the mass
+    p = R.NW.from_prior(pr)
+    m = _model(dev, pr, X.shape[0], prec)
+    lse, st = m.estep_stats(torch.from_numpy(X).to(dev))
+    torch.cuda.synchronize()
+    assert m.sync_status() == 0
+    e = R.expectations(p)
+    ls = R.lse(X, p, e)
+    ref = R.stats(X, p, ls, e).packed()
+    dl = np.abs(lse.cpu().numpy() - ls).max()
+    es = _stat_err(ref, st.cpu().numpy(), 6)
+    # the scaled offsets really are beyond 2^13 (s: the frame's power-of-two scale)
+    s = 2.0 ** np.rint(np.log2(X.astype(np.float64).std(axis=0)))
+    assert np.abs((X[:, None, :] - p.m[None, :, :]) / s).min() > 8192
+    print("  max|dLSE| %.2e stats relerr %.2e" % (dl, es), flush=True)
+    assert dl < 2e-6 * max(1.0, np.abs(ls).max() / 1e3)
+    assert es < 1e-5
+
+
+@gpu
 @pytest.mark.parametrize("K", [1, 70])
 def test_fp8_tier_edges(dev, K):
     """FP8 plain tier on empty, single and ragged batches and on K = 1: the device flags stay clear,
