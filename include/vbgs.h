@@ -29,7 +29,10 @@
  *    (NULL = the legacy default stream).
  *  - Calls only enqueue work on `stream`: they never synchronise (except
  *    vbgs_sync_status) and never allocate device memory. State and workspace
- *    are caller-provided buffers sized by vbgs_query_sizes.
+ *    are caller-provided buffers sized by vbgs_query_sizes. (The culled exact
+ *    E-step forks part of its work onto two streams the context made at init,
+ *    after an event on `stream`, and `stream` waits on their events before
+ *    the call's later work, so `stream` still orders every call.)
  *  - Every call returns a vbgs_status; no C++ exception crosses the ABI.
  *    Argument and shape errors are returned synchronously and leave the
  *    context unchanged. Numeric faults found on the device (a W^{-1} that is
