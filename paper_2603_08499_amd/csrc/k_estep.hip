@@ -440,14 +440,14 @@ __global__ __launch_bounds__(256) void k_pass1(const EArgs a) {
 // ---------------------------------------------------------------------------
 // exact mode, culled sweep over spatially sorted points and components
 // ---------------------------------------------------------------------------
-// Points are taken in Morton order (a wave holds 64 spatially close points) and the coefficient
-// rows in the order of (curvature class, Morton code of the mean), 64 rows per tile. Bounds on
+// Points are taken in curve order (a wave holds 64 spatially close points) and the coefficient
+// rows in the order of (curvature class, Hilbert code of the mean), 64 rows per tile. Bounds on
 // the score of a pair with a point x (first min(D, 3) raw coordinates S):
 //   tile t:  G_t - Lam_t dist^2(x_S, box_t)       (TileInfo: max G, min lambda, box of the means)
 //   row k:   G_k - lambda_k |x_S - m_k,S|^2       (RowBound)
 // A pair whose bound lies below the point's running lower bound M minus the margin T is one the
 // per-pair screen would drop, so it is never screened. Each wave works on its own:
-//   1. pilot: the centre tiles (in each curvature class, the tiles at the Morton positions of its
+//   1. pilot: the centre tiles (in each curvature class, the tiles at the Hilbert positions of its
 //      first and last point) are screened without recording, which brings every M close to its
 //      final value;
 //   2. the seed tiles (the centres and their two neighbours), now recording candidates;
@@ -498,7 +498,7 @@ __device__ __forceinline__ int64_t find_tiles8(const TileInfo* __restrict__ ti, 
 constexpr int DIRECT_MAX = 2;
 
 // Workgroups are dealt to the eight XCDs in turn; renumber them so that each XCD takes one
-// contiguous range of the Morton order, whose component tiles then stay in that XCD's L2.
+// contiguous range of the curve order, whose component tiles then stay in that XCD's L2.
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
   const int64_t x = b % 8, q = b / 8, per = nb / 8, rem = nb % 8;
   return x * per + (x < rem ? x : rem) + q;
@@ -815,7 +815,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __builtin_amdgcn_wave_barrier();
   if (j0 < a.N) {
     const int64_t ntiles = a.Kpad / CT;
-    // seeds: in each curvature class, the tiles around the Morton positions of the wave's first
+    // seeds: in each curvature class, the tiles around the Hilbert positions of the wave's first
     // and last point (eight centres c_q, q = 2 class + end)
     const int64_t jl = min(j0 + 63, a.N - 1);
     const int qq = lane >> 3;
@@ -1221,12 +1221,12 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n, const int32_t* gate
 // blocks (xcd_block). Within its range, an XCD starts the blocks predicted to take longest first
 // (longest processing time first), so that the long blocks do not form the tail. A block's
 // predicted cost is the longest time the previous launch on the same context measured for the
-// blocks that covered the same stretch of the Morton order: the previous blocks are in Morton
+// blocks that covered the same stretch of the curve order: the previous blocks are in Hilbert
 // order, so those from the one whose first code is the largest not above this block's first code
 // to the one whose first code is the largest not above its last code (the same block when the
 // points are the same, as in coordinate-ascent steps on one frame; its neighbours in space on a
 // new frame, where a block that straddles a costly one is likely costly too). A range longer than
-// BO_MAX, or a reset, keeps the Morton order. Any order gives the same results.
+// BO_MAX, or a reset, keeps the curve order. Any order gives the same results.
 constexpr int BO_SPAN = 32;  // previous blocks looked at per block
 constexpr int BO_MAX = 4096;
 constexpr int BO_LDS = 8192;  // previous blocks whose codes are searched in LDS

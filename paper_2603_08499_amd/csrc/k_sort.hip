@@ -1,4 +1,4 @@
-// Spatial ordering for the culled exact sweep: 3-D Morton keys of points and component means,
+// Spatial ordering for the culled exact sweep: 3-D Hilbert-curve keys of points and component means,
 // a stable radix sort of 64-bit keys on their code (key = code << 32 | index, so every key is
 // unique and the order is deterministic; the reassignment step sorts with a bitonic network), and
 // per-tile bounds of the sorted component rows.
@@ -16,17 +16,42 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
   return v;
 }
 
-// Morton code of the first ns (<= 3) coordinates, each quantised to 10 bits over the frame's
-// window mu +- 4 s (clamped): the same map for points and component means
-__device__ __forceinline__ uint32_t morton_code(const float* x, const double* xd, int ns, const FrameInfo* fr) {
-  uint32_t code = 0;
+// Hilbert-curve code of the first ns (<= 3) coordinates, each quantised to 10 bits over the
+// frame's window mu +- 4 s (clamped): the same map for points and component means. Unlike the
+// Morton order, consecutive cells of the Hilbert order are always neighbours, so a run of
+// consecutive points (a sweep block) or components (a tile) has a tighter box. The index comes
+// from Skilling's transform of the coordinates ("Programming the Hilbert curve", 2004): undo the
+// per-level reflections and exchanges, Gray-encode, and interleave the bits, most significant
+// level first, coordinate 0 first within a level.
+__device__ __forceinline__ uint32_t curve_code(const float* x, const double* xd, int ns, const FrameInfo* fr) {
+  uint32_t q[3] = {0u, 0u, 0u};
   for (int i = 0; i < ns; ++i) {
     const double v = x ? (double)x[i] : xd[i];
     double u = (v - (double)fr->mu[i]) / (8.0 * fr->s[i]) + 0.5;
     u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
-    const uint32_t q = (uint32_t)(u * 1023.0);
-    code |= spread3(q) << i;
+    q[i] = (uint32_t)(u * 1023.0);
   }
+  if (ns > 1) {
+    for (uint32_t b = 1u << 9; b > 1u; b >>= 1) {
+      const uint32_t low = b - 1u;
+      for (int i = 0; i < ns; ++i) {
+        if (q[i] & b) {
+          q[0] ^= low;
+        } else {
+          const uint32_t t = (q[0] ^ q[i]) & low;
+          q[0] ^= t;
+          q[i] ^= t;
+        }
+      }
+    }
+    for (int i = 1; i < ns; ++i) q[i] ^= q[i - 1];
+    uint32_t t = 0u;
+    for (uint32_t b = 1u << 9; b > 1u; b >>= 1)
+      if (q[ns - 1] & b) t ^= b - 1u;
+    for (int i = 0; i < ns; ++i) q[i] ^= t;
+  }
+  uint32_t code = 0;
+  for (int i = 0; i < ns; ++i) code |= spread3(q[i]) << (ns - 1 - i);
   return code;
 }
 
@@ -34,11 +59,11 @@ __global__ void k_point_keys(const float* __restrict__ X, int64_t N, int64_t Npo
                              unsigned long long* __restrict__ keys) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= Npow) return;
-  keys[n] = n < N ? ((unsigned long long)morton_code(X + n * D, nullptr, ns, fr) << 32) | (unsigned long long)n
+  keys[n] = n < N ? ((unsigned long long)curve_code(X + n * D, nullptr, ns, fr) << 32) | (unsigned long long)n
                   : ~0ull;
 }
 
-// Components are sorted by (curvature class, Morton code of the mean): a tile bound uses the
+// Components are sorted by (curvature class, Hilbert code of the mean): a tile bound uses the
 // smallest curvature lambda of its rows, so rows of very different lambda are kept apart. The
 // classes are octave pairs (factor 4 in lambda) below an anchor, the half-octave bin of the 90th
 // percentile of lambda over the components: class 0 holds lambda >= anchor / 4, class 3 the
@@ -82,7 +107,7 @@ __global__ void k_comp_keys(const double* __restrict__ post, int64_t K, int64_t 
   const int b = lam_bin(comp_lambda(q, D, split, ns));
   const int gap = fr->lam_anchor - b;
   const uint32_t cls = b == 0 ? 3u : (gap < 4 ? 0u : (uint32_t)min(gap / 4, 3));
-  const uint32_t code = (cls << 30) | morton_code(nullptr, q + 3, ns, fr);
+  const uint32_t code = (cls << 30) | curve_code(nullptr, q + 3, ns, fr);
   keys[k] = ((unsigned long long)code << 32) | (unsigned long long)k;
 }
 
@@ -175,7 +200,7 @@ __global__ void k_unpack_order(const unsigned long long* __restrict__ keys, int6
 
 // Per 64-row tile of the sorted component table: G = max g2, Lambda = min lambda (a lower bound on
 // the curvature of the score in the first three raw coordinates), box of those coordinates of the
-// means, and the Morton code of the first row. G and the box are rounded outward, so the bound
+// means, and the Hilbert code of the first row. G and the box are rounded outward, so the bound
 // formed from them in FP32 stays above every score of the tile. Empty (padding) tiles get G = -inf.
 __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ corder,
                                                    const uint32_t* __restrict__ ccode, int64_t K, int64_t ntiles,

@@ -619,7 +619,7 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   const hipStream_t s = S(stream);
   hipError_t e;
   if (cull) {
-    // frame moments and the alpha sum first (the components are centred and Morton-coded with
+    // frame moments and the alpha sum first (the components are centred and Hilbert-coded with
     // the moments); then the components (sort, coefficient rows, tile bounds) on the side stream
     // while the points (features, sort) go on; the sweep waits for both
     e = c->side ? hipSuccess : hipErrorInvalidResourceHandle;  // made with the context

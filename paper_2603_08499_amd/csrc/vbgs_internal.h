@@ -59,7 +59,7 @@ struct TileInfo {
   float G;          // max over the tile of the score constant g2 (log2 units)
   float Lam;        // min over the tile of lambda_k: s2 <= g2 - lambda_k |x_S - m_k,S|^2
   float lo[3], hi[3];  // box of the means in the culling coordinates (the others read 0)
-  uint32_t code;    // Morton code of the tile's first row
+  uint32_t code;    // Hilbert code of the tile's first row
   uint32_t pad;
 };
 
@@ -120,7 +120,7 @@ struct Layout {
   int nsplit_max;
   // spatial ordering (culled exact sweep)
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
-  size_t bcost, bcode, border;  // per 64-point block of the culled sweep: measured time, Morton code
+  size_t bcost, bcode, border;  // per 64-point block of the culled sweep: measured time, Hilbert code
                                 // of its first point, dispatch order
   size_t bprev;                 // number of blocks of the last sweep (int64)
   size_t slist;                 // per block, the tiles it scores directly (uint32, Kpad / 64 per block)
@@ -373,7 +373,7 @@ struct EArgs {
   FrameInfo* frame;
   const int32_t* gate;        // when set, the exact dense kernels run only if gate[0] != 0
   const int32_t* porder;      // culled sweep: sorted position -> point index
-  const uint32_t* pcode;      // Morton codes of the sorted points
+  const uint32_t* pcode;      // Hilbert codes of the sorted points
   const int32_t* corder;      // sorted row -> component index
   const TileInfo* tinfo;      // per-tile bounds of the sorted component table
   const RowBound* rowb;       // per-row bounds of the sorted component table
@@ -381,7 +381,7 @@ struct EArgs {
                               // coefficient norm of rows 16 cb + 4 g .. 16 cb + 4 g + 3
   int32_t* scan_part;         // block sums of the pair-count scan
   float* bcost;               // culled sweep: per 64-point block, the duration of its last sweep
-  uint32_t* bcode;            // and the Morton code of its first point then
+  uint32_t* bcode;            // and the Hilbert code of its first point then
   int32_t* border;            // culled sweep: dispatch position -> block (costliest first per XCD)
   int64_t* bprev;             // culled sweep: blocks of the last launch (their bcost / bcode entries)
   uint32_t* slist;            // culled sweep: per 64-point block, its tiles scored directly (Kpad / 64 each)
