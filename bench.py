@@ -283,7 +283,8 @@ def run_c5(args):
 
 def sweep_traffic(args):
     """HBM bytes per launch of the screening sweep from the committed counter summary, or None when
-    the summary was taken on another workload or precision or the kernel source has changed since."""
+    the summary was taken on another workload or precision or the kernel source, or the source of
+    the point and component order the sweep runs over, has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "c3_sweep_traffic.json")
     src = os.path.join(ROOT, "paper_2603_08499_amd", "csrc", "k_estep.hip")
@@ -292,6 +293,9 @@ def sweep_traffic(args):
         return None
     rec = json.load(open(path))
     if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    order = os.path.join(ROOT, "paper_2603_08499_amd", "csrc", "k_sort.hip")  # the points' and tiles' order
+    if rec.get("order_source_sha256") != hashlib.sha256(open(order, "rb").read()).hexdigest():
         return None
     return rec["hbm_bytes_per_launch"]
 
