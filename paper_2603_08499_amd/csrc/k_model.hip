@@ -141,8 +141,10 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ X, i
   }
   double nn = 0.0;
   for (int i = 0; i < FP; ++i) nn += (double)f[i] * (double)f[i];
-  f32x4* p32 = reinterpret_cast<f32x4*>(phi32 + n * FP);
-  for (int q = 0; q < FP / 4; ++q) p32[q] = f32x4{f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]};
+  if (phi32) {  // (null: no kernel of this context's precision reads the FP32 rows)
+    f32x4* p32 = reinterpret_cast<f32x4*>(phi32 + n * FP);
+    for (int q = 0; q < FP / 4; ++q) p32[q] = f32x4{f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]};
+  }
   uint32_t hw[FP / 2], lw[FP / 2];
 #pragma unroll
   for (int q = 0; q < FP / 2; ++q) {
@@ -257,7 +259,8 @@ hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStr
   if (part_sel == 0) return hipGetLastError();
   if (N > 0 && d.D <= 6)  // quadratic features fill 1 + D + D(D+1)/2 <= 32 slots only for D <= 6
     hipLaunchKernelGGL(k_features, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, N, d.D, d.frame(),
-                       d.at<float>(L.phi32), d.at<uint16_t>(L.phih), d.at<uint16_t>(L.phil), d.at<float>(L.nphi),
+                       L.f32rows || L.fp8 ? d.at<float>(L.phi32) : nullptr, d.at<uint16_t>(L.phih), d.at<uint16_t>(L.phil),
+                       d.at<float>(L.nphi),
                        &d.frame()->flags);
   if (N > 0 && L.fp8)
     hipLaunchKernelGGL(k_fp8_rows, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, d.at<float>(L.phi32), N,

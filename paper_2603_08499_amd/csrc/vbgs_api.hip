@@ -264,6 +264,7 @@ Layout make_layout(const vbgs_params& p) {
   L.cl = take((size_t)L.Kpad * FP * 2);
   L.nc = take((size_t)L.Kpad * 4);
   L.fp8 = p.score_prec == VBGS_FP8 ? 1 : 0;
+  L.f32rows = (p.exact && (p.score_prec == VBGS_BF16X3 || p.score_prec == VBGS_BF16)) ? 0 : 1;
   L.phi8 = take(L.fp8 ? (size_t)n * FP : 0);
   L.phis = take(L.fp8 ? (size_t)n * 4 : 0);
   L.c8 = take(L.fp8 ? (size_t)L.Kpad * FP : 0);

@@ -114,6 +114,7 @@ __device__ __forceinline__ int lam_bin(float lam) {
 struct Layout {
   size_t phi8, phis, c8, cs8;  // FP8 tier: e4m3 rows and the factors that undo their scaling
   int fp8;
+  int f32rows;  // the points' FP32 feature rows are read (FP32, automatic and FP8 screens; plain tiers)
   size_t frame, mom_part, phi32, phih, phil, nphi, lse2, lse_part, direct, c32, ch, cl, nc, kl,
       spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ent_n, total;
   int64_t Kpad, n_lse_part;
