@@ -44,7 +44,7 @@ struct vbgs_ctx {
   // the point preparation, and the KL terms of the ELBO, which overlap both (not the sweep: their
   // waves hold most of a SIMD's registers and would keep the sweep's first blocks waiting)
   hipStream_t side = nullptr, side2 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr, zeroed = nullptr;
   int nsplit;
   float T2;
   void* scratch = nullptr;  // device address of this device's static scratch (vbgs_estep_stats_scratch)
@@ -414,14 +414,16 @@ static hipError_t make_side(vbgs_ctx* c) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->kl_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->zeroed, hipEventDisableTiming);
   if (e != hipSuccess) {
+    if (c->zeroed) hipEventDestroy(c->zeroed);
     if (c->kl_done) hipEventDestroy(c->kl_done);
     if (c->join) hipEventDestroy(c->join);
     if (c->fork) hipEventDestroy(c->fork);
     if (c->side2) hipStreamDestroy(c->side2);
     if (c->side) hipStreamDestroy(c->side);
     c->side = c->side2 = nullptr;
-    c->fork = c->join = c->kl_done = nullptr;
+    c->fork = c->join = c->kl_done = c->zeroed = nullptr;
   }
   return e;
 }
@@ -631,9 +633,11 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     }
     if (e == hipSuccess) e = hipEventRecord(c->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
-    // the KL terms (ELBO only) on a stream of their own; the caller's stream waits for them after
-    // pass 1
+    // the sweep's cleared counters, then the KL terms (ELBO only), on a stream of their own; the
+    // caller's stream waits for the first before the sweep and for the second after pass 1
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side2, c->fork, 0);
+    if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, c->side2, 0);
+    if (e == hipSuccess) e = hipEventRecord(c->zeroed, c->side2);
     if (e == hipSuccess) e = launch_kl(d, c->side2);
     if (e == hipSuccess) e = hipEventRecord(c->kl_done, c->side2);
     if (e == hipSuccess) {
@@ -645,12 +649,12 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
       Phase ph(c, 8, s);
       e = launch_frame_prep(d, X, N, s, 1);
       if (e == hipSuccess) e = launch_sort_points(d, X, N, s);
-      // what needs no component work, while the side stream is still busy: the sweep's cleared
-      // counters and its blocks' dispatch order
-      if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, s, 0);
+      // what needs no component work, while the side stream is still busy: the blocks' dispatch
+      // order
       if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, s, 4);
     }
     if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->zeroed, 0);
   } else {
     {
       Phase ph(c, 0, s);
@@ -1169,6 +1173,7 @@ void vbgs_destroy(vbgs_ctx* c) {
     hipEventDestroy(c->fork);
     hipEventDestroy(c->join);
     hipEventDestroy(c->kl_done);
+    hipEventDestroy(c->zeroed);
     hipStreamDestroy(c->side2);
     hipStreamDestroy(c->side);
   }
