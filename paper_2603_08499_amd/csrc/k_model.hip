@@ -294,33 +294,25 @@ __device__ void load_winv(const double* r, double A[D][D]) {
     for (int j = i; j < D; ++j) A[i][j] = A[j][i] = r[3 + D + tri_up(i, j, D)];
 }
 
-struct CoefOut {
+struct CoefOut {  // rows in component order
   int64_t K;
-  const int32_t* cinv;  // component -> row of the expanded tables (null: identity)
-  RowBound* rowb;       // per-row bounds in the order of cinv (only with cinv)
   float* lam;           // lower bound on the score curvature in the first min(D, 3) coordinates
   double* direct;
-  float* c32;
+  float* c32;  // (may be null: no FP32 rows)
   uint16_t* ch;
   uint16_t* cl;
   float* nc;
 };
 
 __device__ void write_dead_row(const CoefOut& o, int64_t k, int dts, bool expanded) {
-  const int64_t row = (o.cinv && k < o.K) ? (int64_t)o.cinv[k] : k;
   for (int i = 0; i < (expanded ? FP : 0); ++i) {
     const float v = i == 0 ? DEAD_C0 : 0.0f;
-    o.c32[row * FP + i] = v;
+    if (o.c32) o.c32[k * FP + i] = v;
     const uint16_t h = f2bf(v);
-    o.ch[row * FP + i] = h;
-    o.cl[row * FP + i] = f2bf(v - bf2f(h));
+    o.ch[k * FP + i] = h;
+    o.cl[k * FP + i] = f2bf(v - bf2f(h));
   }
-  if (expanded) o.nc[row] = 0.0f;
-  if (o.rowb) {
-    RowBound rb{};
-    rb.G = -FLT_MAX;
-    o.rowb[row] = rb;
-  }
+  if (expanded) o.nc[k] = 0.0f;
   for (int i = 0; i < dts; ++i) o.direct[k * dts + i] = i == 0 ? -1.0e300 : 0.0;
 }
 
@@ -429,7 +421,6 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
       c[oo++] = (a == b ? -0.5 : -1.0) * LOG2E * nuv[coord_block(a, split)] * wab;
     }
   double nn = 0.0;
-  const int64_t row = o.cinv ? (int64_t)o.cinv[k] : k;
   // the row's three formats, written 16 bytes at a time
   float v[FP];
   uint32_t hw[FP / 2], lw[FP / 2];
@@ -444,26 +435,19 @@ __global__ __launch_bounds__(128) void k_coeffs(const double* __restrict__ prior
     hw[i] = (uint32_t)h0 | ((uint32_t)h1 << 16);
     lw[i] = (uint32_t)f2bf(v[2 * i] - bf2f(h0)) | ((uint32_t)f2bf(v[2 * i + 1] - bf2f(h1)) << 16);
   }
-  f32x4* c32g = reinterpret_cast<f32x4*>(o.c32 + row * FP);
-  u32x4* chg = reinterpret_cast<u32x4*>(o.ch + row * FP);
-  u32x4* clg = reinterpret_cast<u32x4*>(o.cl + row * FP);
+  u32x4* chg = reinterpret_cast<u32x4*>(o.ch + k * FP);
+  u32x4* clg = reinterpret_cast<u32x4*>(o.cl + k * FP);
+  if (o.c32) {
+    f32x4* c32g = reinterpret_cast<f32x4*>(o.c32 + k * FP);
 #pragma unroll
-  for (int i = 0; i < FP / 4; ++i) c32g[i] = f32x4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
+    for (int i = 0; i < FP / 4; ++i) c32g[i] = f32x4{v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]};
+  }
 #pragma unroll
   for (int i = 0; i < FP / 8; ++i) {
     chg[i] = u32x4{hw[4 * i], hw[4 * i + 1], hw[4 * i + 2], hw[4 * i + 3]};
     clg[i] = u32x4{lw[4 * i], lw[4 * i + 1], lw[4 * i + 2], lw[4 * i + 3]};
   }
-  const float ncr = (float)(sqrt(nn) * (1.0 + 1e-6));
-  o.nc[row] = ncr;
-  if (o.rowb) {
-    RowBound rb{};
-    rb.G = f_up(T[0]);
-    rb.Lam = lam;
-    for (int i = 0; i < ns; ++i) rb.m[i] = (float)m[i];
-    rb.nc = ncr;
-    o.rowb[row] = rb;
-  }
+  o.nc[k] = (float)(sqrt(nn) * (1.0 + 1e-6));
   }
 
 }
@@ -565,14 +549,21 @@ hipError_t launch_alpha(const DevPtrs& d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv, bool alpha) {
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, bool alpha, bool staged) {
   const Layout& L = *d.L;
+  if (staged && L.fp8) return hipErrorInvalidValue;  // (the FP8 tier is never culled)
   if (alpha) {
     const hipError_t e = launch_alpha(d, s);
     if (e != hipSuccess) return e;
   }
-  CoefOut o{d.K, cinv, cinv ? d.at<RowBound>(L.rowb) : nullptr, d.at<float>(L.lam), d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch),
+  CoefOut o{d.K, d.at<float>(L.lam), d.at<double>(L.direct), d.at<float>(L.c32), d.at<uint16_t>(L.ch),
             d.at<uint16_t>(L.cl), d.at<float>(L.nc)};
+  if (staged) {
+    o.c32 = L.stage_c32 ? d.at<float>(L.c32u) : nullptr;
+    o.ch = d.at<uint16_t>(L.chu);
+    o.cl = d.at<uint16_t>(L.clu);
+    o.nc = d.at<float>(L.ncu);
+  }
   const dim3 grid((unsigned)((L.Kpad + 127) / 128)), blk(128);
   int* fl = &d.frame()->flags;
   switch (d.D) {

@@ -198,38 +198,80 @@ __global__ void k_unpack_order(const unsigned long long* __restrict__ keys, int6
   if (codes) codes[j] = (uint32_t)(v >> 32);
 }
 
-// Per 64-row tile of the sorted component table: G = max g2, Lambda = min lambda (a lower bound on
-// the curvature of the score in the first three raw coordinates), box of those coordinates of the
-// means, and the Hilbert code of the first row. G and the box are rounded outward, so the bound
-// formed from them in FP32 stays above every score of the tile. Empty (padding) tiles get G = -inf.
+// 16-byte chunks of the tile's rows from the component-order table (consecutive lanes on
+// consecutive chunks of a row, so reads and writes are whole rows); k: the component of row `lane`
+template <int C>
+__device__ __forceinline__ void gather_rows(const void* __restrict__ src, void* __restrict__ dst, int64_t t, int k,
+                                            int lane) {
+  const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+  u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    const int i = q * 64 + lane, r = i / C, c = i % C;
+    const int kr = __shfl(k, r);
+    d4[(t * CT + r) * C + c] = s4[(int64_t)kr * C + c];
+  }
+}
+
+struct TileRows {  // component-order rows (c32u may be null) -> their sorted tables
+  const float* c32u;
+  const uint16_t* chu;
+  const uint16_t* clu;
+  const float* ncu;
+  float* c32;
+  uint16_t* ch;
+  uint16_t* cl;
+  float* nc;
+  RowBound* rowb;
+};
+
+// Per 64-row tile of the sorted component table: the rows gathered from component order, each
+// row's bound record (G = g2 rounded up, its lambda, the first three coordinates of its mean, its
+// norm), and the tile's G = max g2, Lambda = min lambda (a lower bound on the curvature of the
+// score in the first three raw coordinates), box of those coordinates of the means, and the
+// Hilbert code of the first row. G and the box are rounded outward, so the bound formed from them
+// in FP32 stays above every score of the tile. Empty (padding) tiles get G = -inf. Dead rows
+// (padding, and components whose W^-1 is not positive definite) get G = -FLT_MAX.
 __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ corder,
                                                    const uint32_t* __restrict__ ccode, int64_t K, int64_t ntiles,
                                                    int D, int ns, const double* __restrict__ direct, int dts,
-                                                   const float* __restrict__ lam, const RowBound* __restrict__ rowb,
+                                                   const float* __restrict__ lam, TileRows g,
                                                    TileInfo* __restrict__ info, float* __restrict__ ncg) {
   // one wave per tile, lane = row
   const int lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   const int64_t j = t * CT + lane;
+  const int k = j < K ? corder[j] : (int)j;  // padding rows: their own (dead) rows
+  if (g.c32u) gather_rows<FP * 4 / 16>(g.c32u, g.c32, t, k, lane);
+  gather_rows<FP * 2 / 16>(g.chu, g.ch, t, k, lane);
+  gather_rows<FP * 2 / 16>(g.clu, g.cl, t, k, lane);
+  const float nc_row = g.ncu[k];
+  g.nc[j] = nc_row;
   float G = -INFINITY, Lm = INFINITY, lo[3], hi[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     lo[i] = INFINITY;
     hi[i] = -INFINITY;
   }
+  RowBound rb{};
+  rb.G = -FLT_MAX;
   if (j < K) {
-    const int64_t k = corder[j];
-    const double* T = direct + k * dts;
-    G = f_up(T[0]);
-    Lm = lam[k];
+    const double* T = direct + (int64_t)k * dts;
+    rb.G = f_up(T[0]);
+    rb.Lam = lam[k];
+    rb.nc = nc_row;
+    G = rb.G;
+    Lm = rb.Lam;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
       if (i < ns) {
+        rb.m[i] = (float)T[1 + i];
         lo[i] = f_down(T[1 + i]);
         hi[i] = f_up(T[1 + i]);
       }
   }
+  g.rowb[j] = rb;
   for (int o = 1; o < 64; o <<= 1) {
     G = fmaxf(G, __shfl_xor(G, o));
     Lm = fminf(Lm, __shfl_xor(Lm, o));
@@ -241,12 +283,12 @@ __global__ __launch_bounds__(256) void k_tile_info(const int32_t* __restrict__ c
   }
   // norms of the four-row groups, stored [tile][g][cb] (row 16 cb + 4 g + i): each lane of the
   // sweep reads its four values with one 16-byte load
-  float nc = rowb[t * CT + lane].nc;
+  float nc = nc_row;
   nc = fmaxf(nc, __shfl_xor(nc, 1));
   nc = fmaxf(nc, __shfl_xor(nc, 2));
   if ((lane & 3) == 0) {
-    const int cb = lane >> 4, g = (lane >> 2) & 3;
-    ncg[t * CT / 4 + g * 4 + cb] = nc;
+    const int cb = lane >> 4, gq = (lane >> 2) & 3;
+    ncg[t * CT / 4 + gq * 4 + cb] = nc;
   }
   if (lane == 0) {
     TileInfo ti;
@@ -394,9 +436,13 @@ hipError_t launch_sort_comps(const DevPtrs& d, hipStream_t s) {
 hipError_t launch_tile_info(const DevPtrs& d, hipStream_t s) {
   const Layout& L = *d.L;
   const int64_t ntiles = L.Kpad / CT;
+  if (d.D > 6) return hipErrorInvalidValue;  // (the MFMA rows exist for D <= 6 only)
+  TileRows g{L.stage_c32 ? d.at<float>(L.c32u) : nullptr, d.at<uint16_t>(L.chu), d.at<uint16_t>(L.clu),
+             d.at<float>(L.ncu), d.at<float>(L.c32), d.at<uint16_t>(L.ch), d.at<uint16_t>(L.cl), d.at<float>(L.nc),
+             d.at<RowBound>(L.rowb)};
   hipLaunchKernelGGL(k_tile_info, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, d.at<int32_t>(L.corder),
                      d.at<uint32_t>(L.ccode), d.K, ntiles, d.D, d.nsp, d.at<double>(L.direct), direct_stride(d.D),
-                     d.at<float>(L.lam), d.at<RowBound>(L.rowb), d.at<TileInfo>(L.tinfo), d.at<float>(L.ncg));
+                     d.at<float>(L.lam), g, d.at<TileInfo>(L.tinfo), d.at<float>(L.ncg));
   return hipGetLastError();
 }
 

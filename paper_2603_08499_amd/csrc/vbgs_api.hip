@@ -44,7 +44,7 @@ struct vbgs_ctx {
   // the point preparation, and the KL terms of the ELBO, which overlap both (not the sweep: their
   // waves hold most of a SIMD's registers and would keep the sweep's first blocks waiting)
   hipStream_t side = nullptr, side2 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr, zeroed = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr, rows_done = nullptr, feat_done = nullptr;
   int nsplit;
   float T2;
   void* scratch = nullptr;  // device address of this device's static scratch (vbgs_estep_stats_scratch)
@@ -275,6 +275,14 @@ Layout make_layout(const vbgs_params& p) {
   L.spart = take(exact_mfma ? 0 : (size_t)ns * L.Kpad * stat_stride(p.D) * 8);
   L.stats = take((size_t)K * nfeat(p.D) * 8);
   const bool sparse = p.score_prec != VBGS_FP64;  // exact MFMA mode: candidate lists + fixed-point sums
+  {  // the culled path's staging rows
+    const bool staged = sparse && p.exact == 1 && p.cull == 1;
+    L.stage_c32 = staged && !(p.score_prec == VBGS_BF16X3 || p.score_prec == VBGS_BF16) ? 1 : 0;
+    L.c32u = take(L.stage_c32 ? (size_t)L.Kpad * FP * 4 : 0);
+    L.chu = take(staged ? (size_t)L.Kpad * FP * 2 : 0);
+    L.clu = take(staged ? (size_t)L.Kpad * FP * 2 : 0);
+    L.ncu = take(staged ? (size_t)L.Kpad * 4 : 0);
+  }
   L.cand_k = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
   L.cand_s = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
   L.cand_n = take(sparse ? (size_t)n * 4 * 4 : 0);
@@ -414,16 +422,18 @@ static hipError_t make_side(vbgs_ctx* c) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->kl_done, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->zeroed, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->rows_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->feat_done, hipEventDisableTiming);
   if (e != hipSuccess) {
-    if (c->zeroed) hipEventDestroy(c->zeroed);
+    if (c->feat_done) hipEventDestroy(c->feat_done);
+    if (c->rows_done) hipEventDestroy(c->rows_done);
     if (c->kl_done) hipEventDestroy(c->kl_done);
     if (c->join) hipEventDestroy(c->join);
     if (c->fork) hipEventDestroy(c->fork);
     if (c->side2) hipStreamDestroy(c->side2);
     if (c->side) hipStreamDestroy(c->side);
     c->side = c->side2 = nullptr;
-    c->fork = c->join = c->kl_done = c->zeroed = nullptr;
+    c->fork = c->join = c->kl_done = c->rows_done = c->feat_done = nullptr;
   }
   return e;
 }
@@ -594,21 +604,19 @@ static hipError_t settle(vbgs_ctx* c, hipStream_t s) {
   } while (0)
 
 
-// expectations and coefficient rows; with culling the MFMA rows are written in spatial order and
-// per-tile bounds are built
-// (with_kl = false: the caller launches the KL terms itself, after what the sweep needs)
-// (alpha = false: launch_alpha has run before, on s or a stream s waited for)
-static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s, bool with_kl = true, bool alpha = true) {
+// expectations and coefficient rows, and the KL terms; with culling the MFMA rows are written in
+// component order, then gathered into spatial order with the per-row and per-tile bounds
+static hipError_t prepare_components(vbgs_ctx* c, hipStream_t s) {
   const DevPtrs d = c->dev();
   hipError_t e;
   if (!use_cull(c)) {
-    e = launch_coeffs(d, s, nullptr, alpha);
+    e = launch_coeffs(d, s);
   } else {
     e = launch_sort_comps(d, s);
-    if (e == hipSuccess) e = launch_coeffs(d, s, d.at<int32_t>(c->L.cinv), alpha);
+    if (e == hipSuccess) e = launch_coeffs(d, s, true, true);
     if (e == hipSuccess) e = launch_tile_info(d, s);
   }
-  if (e == hipSuccess && with_kl) e = launch_kl(d, s);
+  if (e == hipSuccess) e = launch_kl(d, s);
   return e;
 }
 
@@ -622,39 +630,42 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   const hipStream_t s = S(stream);
   hipError_t e;
   if (cull) {
-    // frame moments and the alpha sum first (the components are centred and Hilbert-coded with
-    // the moments); then the components (sort, coefficient rows, tile bounds) on the side stream
-    // while the points (features, sort) go on; the sweep waits for both
+    // the frame moments first (the components are centred and Hilbert-coded with them), then three
+    // streams: the component sort, then the gather of the rows into its order with the tile
+    // bounds (side); the sweep's cleared counters, the alpha sum, the coefficient rows in
+    // component order, the point features, and the KL terms (ELBO only) (side2); the point sort
+    // and the blocks' dispatch order (the caller's stream, which waits for the gather and the
+    // features before the sweep, and for the KL terms after pass 1)
     e = c->side ? hipSuccess : hipErrorInvalidResourceHandle;  // made with the context
     if (e == hipSuccess) {
       Phase ph(c, 0, s);
       e = launch_frame_prep(d, X, N, s, 0);
-      if (e == hipSuccess) e = launch_alpha(d, s);
     }
     if (e == hipSuccess) e = hipEventRecord(c->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
-    // the sweep's cleared counters, then the KL terms (ELBO only), on a stream of their own; the
-    // caller's stream waits for the first before the sweep and for the second after pass 1
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side2, c->fork, 0);
     if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, c->side2, 0);
-    if (e == hipSuccess) e = hipEventRecord(c->zeroed, c->side2);
+    if (e == hipSuccess) e = launch_coeffs(d, c->side2, true, true);
+    if (e == hipSuccess) e = hipEventRecord(c->rows_done, c->side2);
+    if (e == hipSuccess) e = launch_frame_prep(d, X, N, c->side2, 1);
+    if (e == hipSuccess) e = hipEventRecord(c->feat_done, c->side2);
     if (e == hipSuccess) e = launch_kl(d, c->side2);
     if (e == hipSuccess) e = hipEventRecord(c->kl_done, c->side2);
     if (e == hipSuccess) {
       Phase ph(c, 1, c->side);
-      e = prepare_components(c, c->side, false, false);
+      e = launch_sort_comps(d, c->side);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->rows_done, 0);
+      if (e == hipSuccess) e = launch_tile_info(d, c->side);
     }
     if (e == hipSuccess) e = hipEventRecord(c->join, c->side);
     if (e == hipSuccess) {
       Phase ph(c, 8, s);
-      e = launch_frame_prep(d, X, N, s, 1);
-      if (e == hipSuccess) e = launch_sort_points(d, X, N, s);
-      // what needs no component work, while the side stream is still busy: the blocks' dispatch
-      // order
+      e = launch_sort_points(d, X, N, s);
       if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, s, 4);
     }
+    // (the join follows rows_done, which follows the cleared counters)
     if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join, 0);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->zeroed, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->feat_done, 0);
   } else {
     {
       Phase ph(c, 0, s);
@@ -1173,7 +1184,8 @@ void vbgs_destroy(vbgs_ctx* c) {
     hipEventDestroy(c->fork);
     hipEventDestroy(c->join);
     hipEventDestroy(c->kl_done);
-    hipEventDestroy(c->zeroed);
+    hipEventDestroy(c->rows_done);
+    hipEventDestroy(c->feat_done);
     hipStreamDestroy(c->side2);
     hipStreamDestroy(c->side);
   }

@@ -121,6 +121,11 @@ struct Layout {
   int nsplit_max;
   // spatial ordering (culled exact sweep)
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
+  // the coefficient rows in component order (FP32, BF16 hi / lo, norms), written while the
+  // components are sorted and gathered into the sorted tables with the tile bounds; c32u only
+  // where a screen of the context's precision reads FP32 rows (stage_c32)
+  size_t c32u, chu, clu, ncu;
+  int stage_c32;
   size_t bcost, bcode, border;  // per 64-point block of the culled sweep: measured time, Hilbert code
                                 // of its first point, dispatch order
   size_t bprev;                 // number of blocks of the last sweep (int64)
@@ -309,8 +314,10 @@ hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& in
 hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStream_t s, int part = 2);
 // the sum of alpha over the posterior (FrameInfo::sum_alpha_q), which the coefficient rows need
 hipError_t launch_alpha(const DevPtrs& d, hipStream_t s);
-// alpha = false: launch_alpha has already run on this stream or one it waited for
-hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, const int32_t* cinv = nullptr, bool alpha = true);
+// alpha = false: launch_alpha has already run on this stream or one it waited for; staged = true
+// (culled path): the expanded rows go to the component-order staging tables (launch_tile_info
+// gathers them into the sorted order), else straight into the tables in component order
+hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, bool alpha = true, bool staged = false);
 // per-component KL terms of the ELBO (after launch_coeffs: it reads the frame's alpha sum)
 hipError_t launch_kl(const DevPtrs& d, hipStream_t s);
 hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s);
