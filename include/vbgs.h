@@ -266,8 +266,12 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
  * the blocks screened by all E-steps since vbgs_init or the last vbgs_clear_flags, out[7] = the
  * points whose candidate lists overflowed (their LSE and statistics come from a full rescan),
  * out[8] = the screen precision the sweep used (vbgs_prec), out[9] = the split-BF16 screen's
- * error bound for the mean coefficient-row and feature norms, in 1/1000 log2 units. */
-vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[10], void* stream);
+ * error bound for the mean coefficient-row and feature norms, in 1/1000 log2 units, out[10] =
+ * the culled sweep's pair segments: 0 = every kept pair was written into its component's segment
+ * (sized from the previous culled E-step's counts), 1 = a pair found no room and the statistics
+ * grouped the pairs by a scan of the counts instead (the results are the same either way), -1 =
+ * not the culled path. */
+vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[11], void* stream);
 
 /* Per-phase timing with HIP events recorded on the stream of each call.
  * Phases: 0 frame moments + features, 1 expectations + coefficient rows (with culling also the

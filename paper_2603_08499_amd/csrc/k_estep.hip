@@ -253,13 +253,15 @@ __device__ __forceinline__ void record_candidate(const EArgs& a, int64_t p, int 
   }
 }
 
-// The pairs of one candidate list that can carry mass (score >= thr) are counted per component;
-// the count before this pair's increment, its rank among the component's pairs, replaces its score
-// (cs, as the bits of an int32) and places it in the transpose (k_scatter_pairs). The others
+// The pairs of one candidate list (of point p) that can carry mass (score >= thr) are counted per
+// component; the count before this pair's increment, its rank among the component's pairs,
+// replaces its score (cs, as the bits of an int32) and places it in the transpose. With segments
+// (a.seg) the pair goes there at once, at seg[k].x + rank, if that is inside the component's
+// segment (else a.seg_miss is set and the transpose is redone by k_scatter_pairs). The others
 // leave the list (ck = -1). Eight at a time, so that the loads and the atomics of a chunk are in
 // flight together.
-__device__ __forceinline__ void keep_pairs(const EArgs& a, int32_t* __restrict__ ck, float* __restrict__ cs, int cn,
-                                           float thr, unsigned& kept) {
+__device__ __forceinline__ void keep_pairs(const EArgs& a, int32_t p, int32_t* __restrict__ ck, float* __restrict__ cs,
+                                           int cn, float thr, unsigned& kept) {
   for (int j0 = 0; j0 < cn; j0 += 8) {
     float sv[8];
     int32_t kv[8], rk[8];
@@ -269,8 +271,24 @@ __device__ __forceinline__ void keep_pairs(const EArgs& a, int32_t* __restrict__
       sv[u] = in ? cs[j0 + u] : -INFINITY;
       kv[u] = in ? ck[j0 + u] : -1;
     }
+    int2 sg[8];  // the segments, loaded with the atomics in flight
 #pragma unroll
-    for (int u = 0; u < 8; ++u) rk[u] = kv[u] >= 0 && sv[u] >= thr ? atomicAdd(&a.ccount[kv[u]], 1) : -1;
+    for (int u = 0; u < 8; ++u) {
+      const bool want = kv[u] >= 0 && sv[u] >= thr;
+      rk[u] = want ? atomicAdd(&a.ccount[kv[u]], 1) : -1;
+      sg[u] = want && a.seg ? a.seg[kv[u]] : int2{0, 0};
+    }
+    if (a.seg) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (rk[u] >= 0) {
+          if (rk[u] < sg[u].y - sg[u].x)
+            a.ent_n[sg[u].x + rk[u]] = p;
+          else
+            atomicOr(a.seg_miss, 1);
+        }
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       if (j0 + u < cn) {
@@ -282,6 +300,18 @@ __device__ __forceinline__ void keep_pairs(const EArgs& a, int32_t* __restrict__
         }
       }
     }
+  }
+}
+
+// the pair range of component k in ent_n: its segment, or (no segments, or a pair missed its
+// segment) the exclusive scan of the counts
+__device__ __forceinline__ void pair_range(const EArgs& a, int64_t k, int32_t& e0, int32_t& e1) {
+  if (a.seg && *a.seg_miss == 0) {
+    e0 = a.seg[k].x;
+    e1 = e0 + a.ccount[k];
+  } else {
+    e0 = a.coffset[k];
+    e1 = a.coffset[k + 1];
   }
 }
 
@@ -1027,7 +1057,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       const double L2 = mm + log2(ll);
       if (g == 0) a.lse2[p] = L2;
       const float thr = (float)(L2 - (double)a.T2);  // FP32 rounding is monotone (see evict_candidates)
-      keep_pairs(a, ck, cs, S.cn[b], thr, kept);
+      keep_pairs(a, p, ck, cs, S.cn[b], thr, kept);
     }
   }
   count_refined(&a.frame->refined2, kept);
@@ -1402,7 +1432,8 @@ __global__ __launch_bounds__(256) void k_point_lse(const EArgs a) {
       // keep the pairs that can carry mass (FP32 rounding is monotone, see evict_candidates)
       const float thr = (float)(L2 - (double)a.T2);
       for (int g = 0; g < 4; ++g)
-        keep_pairs(a, a.cand_k + (p * 4 + g) * CS, a.cand_s + (p * 4 + g) * CS, a.cand_n[p * 4 + g], thr, kept);
+        keep_pairs(a, (int32_t)p, a.cand_k + (p * 4 + g) * CS, a.cand_s + (p * 4 + g) * CS, a.cand_n[p * 4 + g], thr,
+                   kept);
     }
     if (a.lse_out) a.lse_out[p] = L2 * LN2;
   }
@@ -1643,8 +1674,10 @@ __global__ __launch_bounds__(256) void k_over_stats(const EArgs a) {
 // exclusive scan of the per-component pair counts (off[K] = total) in two coalesced steps: block
 // sums, then the local scans, each block adding the sums of the blocks before it
 constexpr int SCAN_B = 1024;
+// (gate: when set, the scan runs only if gate[0] != 0)
 __global__ __launch_bounds__(256) void k_scan_blocks(const int32_t* __restrict__ cnt, int64_t K,
-                                                     int32_t* __restrict__ bsum) {
+                                                     int32_t* __restrict__ bsum, const int32_t* gate) {
+  if (gate && gate[0] == 0) return;
   __shared__ int32_t red[256];
   const int t = threadIdx.x;
   const int64_t k0 = (int64_t)blockIdx.x * SCAN_B + 4 * t;
@@ -1679,7 +1712,9 @@ __device__ __forceinline__ int32_t block_excl_scan256(int32_t v, int32_t* sh, in
 // each block starts from the sum of the block sums before it (a strided sum and a tree in LDS);
 // the last block also writes the total
 __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ cnt, int64_t K,
-                                                    const int32_t* __restrict__ bsum, int32_t* __restrict__ off) {
+                                                    const int32_t* __restrict__ bsum, int32_t* __restrict__ off,
+                                                    const int32_t* gate) {
+  if (gate && gate[0] == 0) return;
   __shared__ int32_t sh[256];
   const int t = threadIdx.x;
   int32_t pre = 0;
@@ -1709,12 +1744,74 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ 
   if (blockIdx.x == gridDim.x - 1 && t == 255) off[K] = run;
 }
 
+// Segments of the kept pairs for the next culled sweep, from the counts of the last one (read
+// before they are cleared): component k gets 3 c_k + 32 slots (c_k clamped to [0, 2^24]), in
+// component order, the starts clamped to the capacity of ent_n, so that the segments never overlap
+// whatever the counts hold (a pair that finds no room sets the miss flag). Clears the flag. One
+// workgroup, each thread a contiguous range of components.
+constexpr int SEG_T = 1024;
+__device__ __forceinline__ long long seg_slots(int32_t c) { return 3ll * min(max(c, 0), 1 << 24) + 32; }
+
+// (cnt holds Kpad + 1 >= K + 1 entries and seg Kpad, Kpad a multiple of 64, so the 16-byte
+// accesses of a range that starts at a multiple of 4 below K stay inside them)
+__global__ __launch_bounds__(SEG_T) void k_seg_layout(const int32_t* __restrict__ cnt, int64_t K, int64_t cap,
+                                                      int2* __restrict__ seg, int32_t* __restrict__ miss) {
+  __shared__ long long wsum[SEG_T / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t per = ((K + SEG_T - 1) / SEG_T + 3) / 4 * 4;
+  const int64_t k0 = min(K, (int64_t)t * per), k1 = min(K, k0 + per);
+  long long s = 0;
+#pragma unroll 4
+  for (int64_t k = k0; k < k1; k += 4) {
+    const int4 v = *reinterpret_cast<const int4*>(cnt + k);
+    s += seg_slots(v.x) + (k + 1 < k1 ? seg_slots(v.y) : 0) + (k + 2 < k1 ? seg_slots(v.z) : 0) +
+         (k + 3 < k1 ? seg_slots(v.w) : 0);
+  }
+  long long x = s;  // inclusive scan over the workgroup
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  long long off = x - s;
+  for (int q = 0; q < w; ++q) off += wsum[q];
+  // (the entries past K - 1 in the last group are written too and never read)
+#pragma unroll 4
+  for (int64_t k = k0; k < k1; k += 4) {
+    const int4 v = *reinterpret_cast<const int4*>(cnt + k);
+    int32_t o[5];
+    o[0] = (int32_t)min(off, (long long)cap);
+    off += seg_slots(v.x);
+    o[1] = (int32_t)min(off, (long long)cap);
+    off += seg_slots(v.y);
+    o[2] = (int32_t)min(off, (long long)cap);
+    off += seg_slots(v.z);
+    o[3] = (int32_t)min(off, (long long)cap);
+    off += seg_slots(v.w);
+    o[4] = (int32_t)min(off, (long long)cap);
+    int4* s4 = reinterpret_cast<int4*>(seg + k);
+    s4[0] = int4{o[0], o[1], o[1], o[2]};
+    s4[1] = int4{o[2], o[3], o[3], o[4]};
+  }
+  if (t == 0) miss[0] = 0;
+}
+
+hipError_t launch_seg_layout(const DevPtrs& d, hipStream_t s) {
+  const Layout& L = *d.L;
+  const int64_t cap = L.ent_cap < INT32_MAX ? L.ent_cap : INT32_MAX;
+  hipLaunchKernelGGL(k_seg_layout, dim3(1), dim3(SEG_T), 0, s, d.at<int32_t>(L.ccount), d.K, cap,
+                     d.at<int2>(L.segoff), d.at<int32_t>(L.seg_miss));
+  return hipGetLastError();
+}
+
 // exclusive scan of n counts: off[i] = sum_{j < i} cnt[j], off[n] = total; part: ceil(n / SCAN_B) + 1
 hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t* part, hipStream_t s) {
   const int64_t nsb = (n + SCAN_B - 1) / SCAN_B;
   if (nsb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part, off);
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, cnt, n, part, off, (const int32_t*)nullptr);
   return hipGetLastError();
 }
 
@@ -1723,6 +1820,7 @@ hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t
 __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= a.N * 4) return;
+  if (a.seg && *a.seg_miss == 0) return;  // every pair is in its segment already
   const int64_t p = i >> 2;
   const int cnt = a.cand_n[i];
   if (cnt <= 0 || a.cand_n[p * 4] < 0) return;  // (an overflowed point: the rescan's statistics)
@@ -1830,7 +1928,9 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
   __syncthreads();
   if (tid < 64) {
     const int64_t k = (int64_t)blockIdx.x * 64 + tid;
-    if (k < a.K && a.coffset[k + 1] - a.coffset[k] > HEAVY) heavy[atomicAdd(&nheavy, 1)] = (int32_t)k;
+    int32_t e0 = 0, e1 = 0;
+    if (k < a.K) pair_range(a, k, e0, e1);
+    if (e1 - e0 > HEAVY) heavy[atomicAdd(&nheavy, 1)] = (int32_t)k;
   }
   __syncthreads();
   const int nh = nheavy;
@@ -1859,7 +1959,8 @@ __global__ __launch_bounds__(256) void k_comp_stats_heavy(const EArgs a) {
     acc.hi = grp == 0 && l < F ? (long long)a.fx[(k * FP + l) * 2 + 1] : 0ll;
     acc.hd = 0.0;
     const double* row = a.direct + k * a.dts;
-    const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
+    int32_t e0, e1;
+    pair_range(a, k, e0, e1);
     for (int32_t c0 = e0; c0 < e1; c0 += 256) {
       const int m = min(256, e1 - c0);
       bool small = true;
@@ -1924,7 +2025,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   __shared__ f64x2 rows[256 / SG][16];  // each group's component row (direct form, 32 doubles)
   const int grp = threadIdx.x / SG, l = threadIdx.x % SG;
   const int64_t k = (int64_t)blockIdx.x * (256 / SG) + grp;
-  const bool val = k < a.K && a.coffset[k + 1] - a.coffset[k] <= HEAVY;  // uniform over the group
+  int32_t e0 = 0, e1 = 0;
+  if (k < a.K) pair_range(a, k, e0, e1);
+  const bool val = k < a.K && e1 - e0 <= HEAVY;  // uniform over the group
   // the feature this lane sums: r (l = 0), r u_i (l = 1 + i), r u_i u_j (i <= j, row-major)
   int fi = l >= 1 && l <= DT ? l - 1 : -1, fj = -1;
   {
@@ -1957,7 +2060,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double* row = reinterpret_cast<const double*>(rows[grp]);
     double* rec = buf[grp];
-    const int32_t e0 = a.coffset[k], e1 = a.coffset[k + 1];
     for (int32_t c0 = e0; c0 < e1; c0 += SG) {
       const int m = min(SG, e1 - c0);
       bool small = true;
@@ -2246,13 +2348,14 @@ hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) 
   if (N > 0) {
     const dim3 gp((unsigned)((4 * N + 255) / 256));  // k_scatter_pairs: one thread per candidate list
     const int64_t nsb = (a.K + SCAN_B - 1) / SCAN_B;
+    const int32_t* miss = a.seg ? a.seg_miss : nullptr;  // with segments, the scan only after a miss
     switch (D) {
 #define VB_ST(DD)                                                                         \
   case DD:                                                                                \
     hipLaunchKernelGGL(k_over_stats<DD>, dim3(256), dim3(256), 0, s, a);                  \
-    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part); \
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part,   \
-                       a.coffset);                                                                       \
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part, miss); \
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nsb), dim3(256), 0, s, a.ccount, a.K, a.scan_part,         \
+                       a.coffset, miss);                                                                       \
     hipLaunchKernelGGL(k_scatter_pairs, gp, dim3(256), 0, s, a);                          \
     hipLaunchKernelGGL(k_comp_stats<DD>, dim3((unsigned)((a.K + 256 / SG - 1) / (256 / SG))), dim3(256), 0, s, a); \
     hipLaunchKernelGGL(k_comp_stats_heavy<DD>, dim3((unsigned)((a.K + 63) / 64)), dim3(256), 0, s, a); \
@@ -2303,6 +2406,8 @@ EArgs make_eargs(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N,
   a.fx = d.at<unsigned long long>(L.fx);
   a.ccount = d.at<int32_t>(L.ccount);
   a.coffset = d.at<int32_t>(L.coffset);
+  a.seg = c.seg ? d.at<int2>(L.segoff) : nullptr;
+  a.seg_miss = d.at<int32_t>(L.seg_miss);
   a.ent_n = d.at<int32_t>(L.ent_n);
   a.frame = d.frame();
   a.gate = c.gate;

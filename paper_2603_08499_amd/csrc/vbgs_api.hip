@@ -39,6 +39,7 @@ struct vbgs_ctx {
   uint64_t lse_version;
   bool have_stats;
   bool order_reset;  // the sweep's block costs are not measured yet
+  bool seg_used;     // the last E-step wrote its kept pairs into segments (culled path)
   bool pending_clear;  // attached to a state: the workspace's flags and counters are not cleared yet
   // side streams (default priority) of the culled path: the component preparation, which overlaps
   // the point preparation, and the KL terms of the ELBO, which overlap both (not the sweep: their
@@ -290,7 +291,10 @@ Layout make_layout(const vbgs_params& p) {
   L.fx = take(sparse ? (size_t)L.Kpad * FP * 16 : 0);
   L.ccount = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
   L.coffset = take(sparse ? (size_t)(L.Kpad + 1) * 4 : 0);
+  L.segoff = take(sparse ? (size_t)L.Kpad * 8 : 0);
+  L.seg_miss = take(sparse ? 4 : 0);
   L.ent_n = take(sparse ? (size_t)n * 4 * CS * 4 : 0);
+  L.ent_cap = sparse ? n * 4 * CS : 0;
   int64_t npow = 2048, kpow = 2048;
   while (npow < n) npow <<= 1;
   while (kpow < K) kpow <<= 1;
@@ -490,6 +494,7 @@ static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   c->lse_version = ~(uint64_t)0;
   c->have_stats = false;
   c->order_reset = true;
+  c->seg_used = false;
   c->pending_clear = false;
   c->timing = false;
   c->timers_made = false;
@@ -625,6 +630,8 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
   cfg.cull = use_cull(c) ? 1 : 0;
+  cfg.seg = cfg.cull;  // (the layout is made below, on the stream that clears the counts)
+  c->seg_used = cfg.seg != 0;
   cfg.order_reset = c->order_reset ? 1 : 0;
   const bool cull = use_cull(c);
   const hipStream_t s = S(stream);
@@ -632,10 +639,11 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   if (cull) {
     // the frame moments first (the components are centred and Hilbert-coded with them), then three
     // streams: the component sort, then the gather of the rows into its order with the tile
-    // bounds (side); the sweep's cleared counters, the alpha sum, the coefficient rows in
-    // component order, the point features, and the KL terms (ELBO only) (side2); the point sort
-    // and the blocks' dispatch order (the caller's stream, which waits for the gather and the
-    // features before the sweep, and for the KL terms after pass 1)
+    // bounds (side); the kept pairs' segments sized from the last sweep's counts, the sweep's
+    // cleared counters, the alpha sum, the coefficient rows in component order, the point
+    // features, and the KL terms (ELBO only) (side2); the point sort and the blocks' dispatch
+    // order (the caller's stream, which waits for the gather and the features before the sweep,
+    // and for the KL terms after pass 1)
     e = c->side ? hipSuccess : hipErrorInvalidResourceHandle;  // made with the context
     if (e == hipSuccess) {
       Phase ph(c, 0, s);
@@ -644,6 +652,7 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     if (e == hipSuccess) e = hipEventRecord(c->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side2, c->fork, 0);
+    if (e == hipSuccess) e = launch_seg_layout(d, c->side2);
     if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, c->side2, 0);
     if (e == hipSuccess) e = launch_coeffs(d, c->side2, true, true);
     if (e == hipSuccess) e = hipEventRecord(c->rows_done, c->side2);
@@ -702,6 +711,7 @@ static vbgs_status estep_body(vbgs_ctx* c, const float* X, int64_t N, double* ls
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, c->p.exact, c->T2, c->nsplit};
   cfg.cull = use_cull(c) ? 1 : 0;
+  cfg.seg = cfg.cull;  // (as in run_pass1)
   hipError_t e;
   {
     Phase ph(c, 3, S(stream));
@@ -744,7 +754,7 @@ vbgs_status vbgs_estep_stats_scratch(vbgs_ctx* c, const float* X, int64_t N, dou
   // the same launches as vbgs_estep_stats with the scratch as the workspace; the context's own
   // workspace and bookkeeping are left as they were
   void* const ws = c->ws;
-  const bool order_reset = c->order_reset;
+  const bool order_reset = c->order_reset, seg_used = c->seg_used;
   c->ws = c->scratch;
   c->order_reset = true;  // block costs in the scratch may come from another context
   const DevPtrs sd = c->dev();
@@ -752,6 +762,7 @@ vbgs_status vbgs_estep_stats_scratch(vbgs_ctx* c, const float* X, int64_t N, dou
   vbgs_status st = e == hipSuccess ? estep_body(c, X, N, lse_out, stats_out, stream) : hipfail(c, e, "scratch");
   c->ws = ws;
   c->order_reset = order_reset;
+  c->seg_used = seg_used;
   if (st != VBGS_OK) return st;
   return hipfail(c, launch_merge_flags(sd.frame(), c->dev().frame(), S(stream)), "scratch flags");
 }
@@ -879,12 +890,15 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* c, void* stream) {
   return hipfail(c, e, "clear_flags");
 }
 
-vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[10], void* stream) {
+vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[11], void* stream) {
   if (!c || !out) return VBGS_ERR_ARG;
   VBGS_SETTLE(c, stream);
   FrameInfo f;
+  int32_t miss = -1;
   hipError_t e = hipStreamSynchronize(S(stream));
   if (e == hipSuccess) e = hipMemcpy(&f, (char*)c->ws + c->L.frame, sizeof f, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && c->seg_used)
+    e = hipMemcpy(&miss, (char*)c->ws + c->L.seg_miss, sizeof miss, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hipfail(c, e, "counters");
   out[0] = (int64_t)f.refined1;
   out[1] = (int64_t)f.refined2;
@@ -896,6 +910,7 @@ vbgs_status vbgs_counters(vbgs_ctx* c, int64_t out[10], void* stream) {
   out[7] = f.n_over;
   out[8] = f.screen_prec;
   out[9] = (int64_t)llround((double)f.screen_slack * 1000.0);
+  out[10] = miss;
   return VBGS_OK;
 }
 
@@ -1019,6 +1034,7 @@ vbgs_status vbgs_estep_stats_pruned(vbgs_ctx* c, const float* X, int64_t N, cons
     return fail(c, VBGS_ERR_ARG, "bad X / audit arguments");
   if (!isfinite(logmass_bound) || !(frac_bound >= 0.0)) return fail(c, VBGS_ERR_ARG, "bad bounds");
   VBGS_SETTLE(c, stream);
+  c->seg_used = false;
   const hipStream_t s = S(stream);
   const DevPtrs d = c->dev();
   EstepCfg cfg{c->p.score_prec, 1, c->T2, 1};

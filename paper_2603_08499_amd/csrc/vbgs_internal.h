@@ -116,8 +116,9 @@ struct Layout {
   int fp8;
   int f32rows;  // the points' FP32 feature rows are read (FP32, automatic and FP8 screens; plain tiers)
   size_t frame, mom_part, phi32, phih, phil, nphi, lse2, lse_part, direct, c32, ch, cl, nc, kl,
-      spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ent_n, total;
+      spart, stats, cand_k, cand_s, cand_n, over_list, fx, ccount, coffset, ent_n, segoff, seg_miss, total;
   int64_t Kpad, n_lse_part;
+  int64_t ent_cap;  // entries of ent_n
   int nsplit_max;
   // spatial ordering (culled exact sweep)
   size_t pkeys, porder, pcode, ckeys, corder, cinv, ccode, lam, tinfo, rowb, ncg, lhist, scan_part;
@@ -346,6 +347,7 @@ struct EstepCfg {
   int nsplit;    // pass-2 point splits
   const int32_t* gate = nullptr;  // device flag gating the exact dense kernels (proposal fallback)
   int cull = 0;                   // culled sweep over spatially sorted points and components
+  int seg = 0;                    // kept pairs written straight into per-component segments
   int order_reset = 0;            // forget the measured block costs (first sweep of a context)
 };
 
@@ -378,6 +380,9 @@ struct EArgs {
   int32_t* ccount;            // Kpad + 1: kept pairs per component (their ranks: keep_pairs)
   int32_t* coffset;           // Kpad + 1: exclusive scan of ccount
   int32_t* ent_n;             // kept pairs grouped by component: point index
+  const int2* seg;            // or null: per component, its segment [x, y) of ent_n sized from the
+                              // last counts; keep_pairs writes each pair at x + rank when it fits
+  int32_t* seg_miss;          // set when a pair did not fit: the statistics take the scan + transpose
   FrameInfo* frame;
   const int32_t* gate;        // when set, the exact dense kernels run only if gate[0] != 0
   const int32_t* porder;      // culled sweep: sorted position -> point index
@@ -418,6 +423,9 @@ hipError_t launch_fold(const DevPtrs& d, const EstepCfg& c, double* stats_out, h
 hipError_t launch_exact_sweep(const EArgs& a, int prec, int D, int64_t N, hipStream_t s, int cull = 0);
 hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s);
 hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s);
+// the kept pairs' segments (EArgs::seg) for the next culled sweep, from the counts of the last one;
+// before the counts are cleared
+hipError_t launch_seg_layout(const DevPtrs& d, hipStream_t s);
 hipError_t launch_render(const DevPtrs& d, const EstepCfg& c, const float* X, int64_t N, const double* reg, int Dc,
                          float* out, hipStream_t s);
 

@@ -191,12 +191,12 @@ class VBGS:
         self._check(self.lib.vbgs_clear_flags(self.ctx, _stream()))
 
     def counters(self):
-        out = (ctypes.c_int64 * 10)()
+        out = (ctypes.c_int64 * 11)()
         self._check(self.lib.vbgs_counters(self.ctx, out, _stream()))
         names = {v: k for k, v in _lib.PREC.items()}
         return dict(refined_pass1=out[0], refined_pass2=out[1], N=out[2], K=out[3], blocks=out[4],
                     blocks_dense=out[5], blocks_cum=out[6], n_over=out[7], screen=names.get(out[8], out[8]),
-                    screen_bound_bf16x3=out[9] / 1000.0)
+                    screen_bound_bf16x3=out[9] / 1000.0, seg_miss=out[10])
 
     def reassign(self, X, lse, gumbel, n):
         """Move the means of the n least-used components onto n points drawn with probabilities

@@ -397,6 +397,39 @@ def test_cull_matches_unculled(dev, case):
 
 
 @gpu
+def test_pair_segments_hit_and_miss(dev):
+    """The culled path writes kept pairs straight into per-component segments sized from the last
+    culled E-step's counts; a pair that finds no room sends the statistics through the scan and
+    transpose instead. Both give the same bits (fixed-point sums), and agree with the unculled
+    sweep: a small frame, then an 8x larger one (segments too small: miss), then the same again
+    (segments from its own counts: hit)."""
+    X, pr = scenes.random_problem(16000, 300, 6, seed=21)
+    Xd = torch.from_numpy(X).to(dev)
+    m = _model(dev, pr, X.shape[0], "bf16x3", True, cull=1)
+    runs = []
+    for n in (2000, 16000, 16000):
+        print("segments: N =", n, flush=True)
+        lse, st = m.estep_stats(Xd[:n])
+        torch.cuda.synchronize()
+        runs.append((lse.cpu().numpy(), st.cpu().numpy(), m.counters()["seg_miss"]))
+    assert m.sync_status() == 0
+    misses = [r[2] for r in runs]
+    print("  seg_miss per call", misses)
+    assert misses[1] == 1 and misses[2] == 0
+    assert np.array_equal(runs[1][0], runs[2][0]) and np.array_equal(runs[1][1], runs[2][1])
+    u = _model(dev, pr, X.shape[0], "bf16x3", True, cull=0)
+    lse_u, st_u = u.estep_stats(Xd)
+    torch.cuda.synchronize()
+    assert u.counters()["seg_miss"] == -1
+    dl = np.abs(lse_u.cpu().numpy() - runs[2][0]).max()
+    es = _stat_err(st_u.cpu().numpy(), runs[2][1], 6)
+    print("  vs unculled: max|dLSE| %.2e stats relerr %.2e" % (dl, es))
+    assert dl < 1e-9 and es < 1e-9
+    m.close()
+    u.close()
+
+
+@gpu
 def test_auto_screen_choice(dev):
     """VBGS_AUTO keeps the split-BF16 screen where its bound is small (c3 slice) and takes the FP32
     screen where it is not (the 800x800 image, 50000 components in the unit square); both match the
