@@ -1817,25 +1817,28 @@ hipError_t launch_excl_scan(const int32_t* cnt, int64_t n, int32_t* off, int32_t
 
 // one thread per candidate list (point i / 4, list i % 4): each kept pair goes to its component's
 // segment at the rank it drew when it was kept (keep_pairs)
+// (a grid of at most SCATTER_BLOCKS workgroups, each list taken by the thread i = list mod stride:
+// with segments and no miss the launch is a few workgroups that exit at once)
+constexpr int SCATTER_BLOCKS = 2048;
 __global__ __launch_bounds__(256) void k_scatter_pairs(const EArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.N * 4) return;
   if (a.seg && *a.seg_miss == 0) return;  // every pair is in its segment already
-  const int64_t p = i >> 2;
-  const int cnt = a.cand_n[i];
-  if (cnt <= 0 || a.cand_n[p * 4] < 0) return;  // (an overflowed point: the rescan's statistics)
-  const int32_t* ck = a.cand_k + i * CS;
-  const float* cs = a.cand_s + i * CS;
-  for (int j0 = 0; j0 < cnt; j0 += 8) {
-    int32_t k[8], r[8];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.N * 4; i += (int64_t)gridDim.x * 256) {
+    const int64_t p = i >> 2;
+    const int cnt = a.cand_n[i];
+    if (cnt <= 0 || a.cand_n[p * 4] < 0) continue;  // (an overflowed point: the rescan's statistics)
+    const int32_t* ck = a.cand_k + i * CS;
+    const float* cs = a.cand_s + i * CS;
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
+      int32_t k[8], r[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      k[u] = j0 + u < cnt ? ck[j0 + u] : -1;
-      r[u] = j0 + u < cnt ? __float_as_int(cs[j0 + u]) : 0;
+      for (int u = 0; u < 8; ++u) {
+        k[u] = j0 + u < cnt ? ck[j0 + u] : -1;
+        r[u] = j0 + u < cnt ? __float_as_int(cs[j0 + u]) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k[u] >= 0) a.ent_n[a.coffset[k[u]] + r[u]] = (int32_t)p;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k[u] >= 0) a.ent_n[a.coffset[k[u]] + r[u]] = (int32_t)p;
   }
 }
 
@@ -2346,7 +2349,8 @@ hipError_t launch_point_lse(const EArgs& a, int D, int64_t N, hipStream_t s) {
 // statistics of the kept candidates: overflowed points (atomics), transpose, per-component sums
 hipError_t launch_sparse_stats(const EArgs& a, int D, int64_t N, hipStream_t s) {
   if (N > 0) {
-    const dim3 gp((unsigned)((4 * N + 255) / 256));  // k_scatter_pairs: one thread per candidate list
+    const int64_t ng = (4 * N + 255) / 256;
+    const dim3 gp((unsigned)(ng < SCATTER_BLOCKS ? ng : SCATTER_BLOCKS));  // k_scatter_pairs
     const int64_t nsb = (a.K + SCAN_B - 1) / SCAN_B;
     const int32_t* miss = a.seg ? a.seg_miss : nullptr;  // with segments, the scan only after a miss
     switch (D) {

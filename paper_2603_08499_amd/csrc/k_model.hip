@@ -52,43 +52,73 @@ hipError_t launch_init_state(const DevPtrs& d, const double* m0, const Init0& in
 // ---------------------------------------------------------------------------
 // frame moments (deterministic two-level reduction) and features
 // ---------------------------------------------------------------------------
+// sum of v over a wave (xor butterfly: a fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// per j, the sum of v[j] over a workgroup of 256 threads: each wave's, then the four in order;
+// thread t < 2 MAXD returns the sum for j = t
+__device__ __forceinline__ double block_sums(const double (&v)[2 * MAXD], double (*sh)[2 * MAXD]) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int j = 0; j < 2 * MAXD; ++j) {
+    const double u = wave_sum(v[j]);
+    if (lane == 0) sh[w][j] = u;
+  }
+  __syncthreads();
+  return t < 2 * MAXD ? ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t] : 0.0;
+}
+
+// per workgroup of 256 threads, the sums of x and x^2 per coordinate over its range of points
 __global__ __launch_bounds__(256) void k_moments_partial(const float* __restrict__ X, int64_t N, int D,
                                                          double* __restrict__ part) {
-  __shared__ double sh[256][2 * MAXD];
+  __shared__ double sh[4][2 * MAXD];
   const int t = threadIdx.x;
   const int64_t per = (N + MOM_BLOCKS - 1) / MOM_BLOCKS;
   const int64_t a = (int64_t)blockIdx.x * per, b = min(N, a + per);
-  double s1[MAXD], s2[MAXD];
-  for (int i = 0; i < MAXD; ++i) s1[i] = s2[i] = 0.0;
+  double v[2 * MAXD];
+#pragma unroll
+  for (int j = 0; j < 2 * MAXD; ++j) v[j] = 0.0;
   for (int64_t n = a + t; n < b; n += 256)
-    for (int i = 0; i < D; ++i) {
-      const double v = (double)X[n * D + i];
-      if (isfinite(v)) {
-        s1[i] += v;
-        s2[i] += v * v;
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i)
+      if (i < D) {
+        const double x = (double)X[n * D + i];
+        if (isfinite(x)) {
+          v[i] += x;
+          v[MAXD + i] += x * x;
+        }
       }
-    }
-  for (int i = 0; i < MAXD; ++i) {
-    sh[t][i] = s1[i];
-    sh[t][MAXD + i] = s2[i];
-  }
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w)
-      for (int i = 0; i < 2 * MAXD; ++i) sh[t][i] += sh[t + w][i];
-    __syncthreads();
-  }
-  if (t < 2 * MAXD) part[blockIdx.x * 2 * MAXD + t] = sh[0][t];
+  const double r = block_sums(v, sh);
+  if (t < 2 * MAXD) part[blockIdx.x * 2 * MAXD + t] = r;
 }
 
-__global__ void k_moments_final(const double* __restrict__ part, int64_t N, int D, FrameInfo* fr) {
-  const int i = threadIdx.x;
-  if (i >= MAXD) return;
-  double s1 = 0.0, s2 = 0.0;
-  for (int b = 0; b < MOM_BLOCKS; ++b) {
-    s1 += part[b * 2 * MAXD + i];
-    s2 += part[b * 2 * MAXD + MAXD + i];
+__global__ __launch_bounds__(256) void k_moments_final(const double* __restrict__ part, int64_t N, int D,
+                                                       FrameInfo* fr) {
+  __shared__ double sh[4][2 * MAXD];
+  __shared__ double tot[2 * MAXD];
+  const int t = threadIdx.x;
+  double v[2 * MAXD];
+#pragma unroll
+  for (int j = 0; j < 2 * MAXD; ++j) v[j] = 0.0;
+  for (int b = t; b < MOM_BLOCKS; b += 256) {
+    const f64x2* p2 = reinterpret_cast<const f64x2*>(part + b * 2 * MAXD);
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) {
+      const f64x2 q = p2[j];
+      v[2 * j] += q.x;
+      v[2 * j + 1] += q.y;
+    }
   }
+  const double r = block_sums(v, sh);
+  if (t < 2 * MAXD) tot[t] = r;
+  __syncthreads();
+  const int i = t;
+  if (i >= MAXD) return;
+  const double s1 = tot[i], s2 = tot[MAXD + i];
   float mu = 0.0f;
   double sc = 1.0;
   if (i < D && N > 0) {
@@ -254,7 +284,7 @@ hipError_t launch_frame_prep(const DevPtrs& d, const float* X, int64_t N, hipStr
   double* part = d.at<double>(L.mom_part);
   if (part_sel != 1) {
     hipLaunchKernelGGL(k_moments_partial, dim3(MOM_BLOCKS), dim3(256), 0, s, X, N, d.D, part);
-    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(64), 0, s, part, N, d.D, d.frame());
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(256), 0, s, part, N, d.D, d.frame());
   }
   if (part_sel == 0) return hipGetLastError();
   if (N > 0 && d.D <= 6)  // quadratic features fill 1 + D + D(D+1)/2 <= 32 slots only for D <= 6
@@ -582,6 +612,24 @@ hipError_t launch_coeffs(const DevPtrs& d, hipStream_t s, bool alpha, bool stage
   return hipGetLastError();
 }
 
+// the sum of the KL terms over one contiguous range of components per workgroup (ELBO_BLOCKS
+// workgroups of 256 threads, a fixed order)
+constexpr int ELBO_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_kl_part(const double* __restrict__ kl, int64_t K, double* __restrict__ part) {
+  __shared__ double b[256];
+  const int t = threadIdx.x;
+  const int64_t pk = (K + ELBO_BLOCKS - 1) / ELBO_BLOCKS, k0 = blockIdx.x * pk, k1 = min(k0 + pk, K);
+  double u = 0.0;
+  for (int64_t i = k0 + t; i < k1; i += 256) u += kl[i];
+  b[t] = u;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) b[t] += b[t + w];
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x] = b[0];
+}
+
 hipError_t launch_kl(const DevPtrs& d, hipStream_t s) {
   const Layout& L = *d.L;
   const dim3 grid((unsigned)((d.K + 127) / 128)), blk(128);
@@ -596,6 +644,7 @@ hipError_t launch_kl(const DevPtrs& d, hipStream_t s) {
     default:
       return hipErrorInvalidValue;
   }
+  hipLaunchKernelGGL(k_kl_part, dim3(ELBO_BLOCKS), dim3(256), 0, s, d.at<double>(L.kl), d.K, d.at<double>(L.elbo_part));
   return hipGetLastError();
 }
 
@@ -699,43 +748,18 @@ hipError_t launch_update(const DevPtrs& d, int commit, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // ELBO: F = ln2 * sum LSE2 - [lnGamma(sum alpha) - lnGamma(sum alpha_p)] - sum_k kl_k
 // ---------------------------------------------------------------------------
-// Two stages in a fixed order (so the value does not depend on scheduling): ELBO_BLOCKS workgroups
-// each sum one contiguous range of the LSE partials and of the KL terms, then one workgroup sums
-// their partials.
-constexpr int ELBO_BLOCKS = 256;
-
-__global__ __launch_bounds__(256) void k_elbo_part(const double* __restrict__ lse_part, int64_t np,
-                                                   const double* __restrict__ kl, int64_t K,
-                                                   double* __restrict__ part) {
-  __shared__ double a[256], b[256];
-  const int t = threadIdx.x;
-  const int64_t pp = (np + ELBO_BLOCKS - 1) / ELBO_BLOCKS, pk = (K + ELBO_BLOCKS - 1) / ELBO_BLOCKS;
-  const int64_t p0 = blockIdx.x * pp, p1 = min(p0 + pp, np), k0 = blockIdx.x * pk, k1 = min(k0 + pk, K);
-  double s = 0.0, u = 0.0;
-  for (int64_t i = p0 + t; i < p1; i += 256) s += lse_part[i];
-  for (int64_t i = k0 + t; i < k1; i += 256) u += kl[i];
-  a[t] = s;
-  b[t] = u;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      a[t] += a[t + w];
-      b[t] += b[t + w];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    part[blockIdx.x] = a[0];
-    part[ELBO_BLOCKS + blockIdx.x] = b[0];
-  }
-}
-
-__global__ __launch_bounds__(256) void k_elbo(const double* __restrict__ part, const FrameInfo* __restrict__ fr,
+// In a fixed order (so the value does not depend on scheduling): the KL terms are summed in
+// ELBO_BLOCKS contiguous ranges as soon as they are made (k_kl_part, with launch_kl), and one
+// workgroup sums the LSE partials of the first pass and those range sums.
+__global__ __launch_bounds__(256) void k_elbo(const double* __restrict__ lse_part, int64_t np,
+                                              const double* __restrict__ klpart, const FrameInfo* __restrict__ fr,
                                               double* out) {
   __shared__ double a[256], b[256];
   const int t = threadIdx.x;
-  a[t] = part[t];
-  b[t] = part[ELBO_BLOCKS + t];
+  double s = 0.0;
+  for (int64_t i = t; i < np; i += 256) s += lse_part[i];
+  a[t] = s;
+  b[t] = klpart[t];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (t < w) {
@@ -751,10 +775,8 @@ __global__ __launch_bounds__(256) void k_elbo(const double* __restrict__ part, c
 }
 
 hipError_t launch_elbo(const DevPtrs& d, int64_t n_lse_part, double* out, hipStream_t s) {
-  double* part = d.at<double>(d.L->elbo_part);
-  hipLaunchKernelGGL(k_elbo_part, dim3(ELBO_BLOCKS), dim3(256), 0, s, d.at<double>(d.L->lse_part), n_lse_part,
-                     d.at<double>(d.L->kl), d.K, part);
-  hipLaunchKernelGGL(k_elbo, dim3(1), dim3(256), 0, s, part, d.frame(), out);
+  hipLaunchKernelGGL(k_elbo, dim3(1), dim3(256), 0, s, d.at<double>(d.L->lse_part), n_lse_part,
+                     d.at<double>(d.L->elbo_part), d.frame(), out);
   return hipGetLastError();
 }
 

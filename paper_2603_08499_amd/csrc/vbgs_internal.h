@@ -23,7 +23,7 @@ constexpr int CT = 64;        // components per LDS tile (pass 1) and per pass-2
 constexpr int PT = 64;        // points per LDS tile (pass 2)
 constexpr int P1_PB = 4;      // 16-point blocks per wave in pass 1
 constexpr int P1_PTS = 4 * P1_PB * 16;  // points per pass-1 workgroup (4 waves)
-constexpr int MOM_BLOCKS = 256;
+constexpr int MOM_BLOCKS = 1024;
 constexpr int CS = 32;        // candidate slots per (point, lane group) in the exact sweep
 constexpr float DEAD_C0 = -1.0e30f;     // constant slot of padding components
 
