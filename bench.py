@@ -561,7 +561,10 @@ def main():
             "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": avg[dom],
             "blocks_screened_per_launch": blocks, "blocks_dense": cnt_run["blocks_dense"],
             "dense_equivalent_tflops": 2.0 * F * N * K / t_dom / 1e12,
-            "pairs_rescored_pass1": cnt["refined_pass1"], "pairs_rescored_pass2": cnt["refined_pass2"]}
+            "pairs_rescored_pass1": cnt["refined_pass1"], "pairs_rescored_pass2": cnt["refined_pass2"],
+            # 0: the last timed step's kept pairs all fitted the segments sized from the step before
+            # (no scan or transpose); 1: one did not and the statistics took the transpose
+            "pair_segment_miss_last_step": cnt_run["seg_miss"]}
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
