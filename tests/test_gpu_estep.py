@@ -291,6 +291,35 @@ def test_device_flags(dev):
 
 
 @gpu
+def test_dead_component_culled_matches_unculled(dev):
+    """A component whose W^-1 is not positive definite is a dead row (no pairs, zero statistics,
+    the device flag raised); the culled sweep, whose rows are written in component order and
+    gathered into the sorted tables with their bounds, agrees with the unculled one on all the
+    others. K = 70 leaves a padded last tile."""
+    X, pr = scenes.random_problem(3000, 70, 6, seed=33)
+    p = R.NW.from_prior(pr)
+    bad = p.copy()
+    bad.Winv[3] = -np.eye(6)
+    bad.Winv[41] = -np.eye(6)
+    Xg = torch.from_numpy(X).to(dev)
+    out = []
+    for cull in (0, 1):
+        m = _model(dev, pr, X.shape[0], "bf16x3", True, cull=cull)
+        _set(m, "posterior", bad)
+        lse, st = m.estep_stats(Xg)
+        torch.cuda.synchronize()
+        assert m.sync_status() == -4
+        out.append((lse.cpu().numpy(), st.cpu().numpy()))
+        m.close()
+    (l0, s0), (l1, s1) = out
+    assert np.all(s1[[3, 41]] == 0.0) and np.all(s0[[3, 41]] == 0.0)
+    dl = np.abs(l0 - l1).max()
+    es = _stat_err(s0, s1, 6)
+    print("dead components: culled vs unculled max|dLSE| %.2e stats relerr %.2e" % (dl, es))
+    assert dl < 1e-9 and es < 1e-9
+
+
+@gpu
 def test_elbo_state_error_after_update(dev):
     import paper_2603_08499_amd as P
     X, pr = scenes.random_problem(300, 20, 5, seed=10)
