@@ -63,7 +63,7 @@ typedef enum {
   VBGS_ERR_NOT_PD = -4,      /* sticky: some W^{-1} was not positive definite */
   VBGS_ERR_NONFINITE = -5,   /* sticky: non-finite input coordinates */
   VBGS_ERR_STATE = -6,       /* call order: e.g. vbgs_elbo(X=NULL) after an update */
-  VBGS_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+  VBGS_ERR_UNSUPPORTED = -7  /* valid request the library does not implement */
 } vbgs_status;
 
 /* Precision of the score GEMM (the dot product of quadratic point features
