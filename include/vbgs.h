@@ -284,6 +284,11 @@ vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[11], void* stream);
  * summed duration in ms and the number of recorded launches of each phase, and clears them. */
 #define VBGS_NPHASE 10
 vbgs_status vbgs_timing(vbgs_ctx* ctx, int32_t enable);
+/* As vbgs_timing, recording only the phases p whose bit (1 << p) is set in `mask` (0 stops
+ * recording; (1 << VBGS_NPHASE) - 1 is vbgs_timing(ctx, 1)). Each recorded phase adds two events
+ * to its stream per launch, and with them some time: a timed loop can record the one phase it
+ * needs and leave the others to untimed launches. Errors: VBGS_ERR_ARG for bits >= VBGS_NPHASE. */
+vbgs_status vbgs_timing_phases(vbgs_ctx* ctx, uint32_t mask);
 vbgs_status vbgs_timing_read(vbgs_ctx* ctx, double ms[VBGS_NPHASE], int64_t counts[VBGS_NPHASE], void* stream);
 
 /* ---------------------------------------------------------------------------------------

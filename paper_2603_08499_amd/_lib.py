@@ -67,6 +67,7 @@ def load():
         "vbgs_proposal_candidates": (i32, [vp, vp, i64, vp, vp]),
         "vbgs_proposal_train_step": (i32, [vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, vp, vp, vp]),
         "vbgs_timing": (i32, [vp, i32]),
+        "vbgs_timing_phases": (i32, [vp, ctypes.c_uint32]),
         "vbgs_timing_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp]),
         "vbgs_last_error": (ctypes.c_char_p, [vp]),
         "vbgs_destroy": (None, [vp]),

@@ -27,6 +27,7 @@ struct PhaseTimer {
 struct vbgs_ctx {
   vbgs_params p;
   bool timing;
+  uint32_t timing_mask;  // the phases recorded while timing is on
   bool timers_made;
   bool prop_ready;     // the state holds network weights
   bool prop_prepared;  // the workspace holds their MFMA operand copies
@@ -219,7 +220,7 @@ bool aligned(const void* p) { return ((uintptr_t)p % ALIGN) == 0; }
 }  // namespace
 
 Phase::Phase(vbgs_ctx* c_, int ph_, hipStream_t s_) : c(c_), ph(ph_), s(s_), slot(-1) {
-  if (!c->timing) return;
+  if (!c->timing || !((c->timing_mask >> ph) & 1u)) return;
   PhaseTimer& t = c->tm[ph];
   slot = t.head;
   harvest(t, slot);
@@ -497,6 +498,7 @@ static vbgs_ctx* new_ctx(const vbgs_params* p, void* state, void* ws) {
   c->seg_used = false;
   c->pending_clear = false;
   c->timing = false;
+  c->timing_mask = 0;
   c->timers_made = false;
   c->prop_ready = false;
   c->prop_prepared = false;
@@ -1153,6 +1155,12 @@ vbgs_status vbgs_proposal_train_step(vbgs_ctx* c, const float* X, const int32_t*
 
 vbgs_status vbgs_timing(vbgs_ctx* c, int32_t enable) {
   if (!c || (enable != 0 && enable != 1)) return VBGS_ERR_ARG;
+  return vbgs_timing_phases(c, enable ? (1u << VBGS_NPHASE) - 1u : 0u);
+}
+
+vbgs_status vbgs_timing_phases(vbgs_ctx* c, uint32_t mask) {
+  if (!c || (mask >> VBGS_NPHASE) != 0) return VBGS_ERR_ARG;
+  const bool enable = mask != 0;
   if (enable && !c->timers_made) {
     for (int p = 0; p < VBGS_NPHASE; ++p) {
       PhaseTimer& t = c->tm[p];
@@ -1168,7 +1176,8 @@ vbgs_status vbgs_timing(vbgs_ctx* c, int32_t enable) {
     }
     c->timers_made = true;
   }
-  c->timing = enable != 0;
+  c->timing = enable;
+  c->timing_mask = mask;
   return VBGS_OK;
 }
 

@@ -312,8 +312,15 @@ class VBGS:
                                                       _ptr(g), _stream()))
         return loss_out, g
 
-    def timing(self, enable=True):
-        self._check(self.lib.vbgs_timing(self.ctx, 1 if enable else 0))
+    def timing(self, enable=True, phases=None):
+        """Per-phase HIP-event timing on (every phase, or only the named ones, e.g. ["pass1"]) or off."""
+        if phases is None or not enable:
+            self._check(self.lib.vbgs_timing(self.ctx, 1 if enable else 0))
+        else:
+            mask = 0
+            for p in phases:
+                mask |= 1 << _lib.PHASES.index(p)
+            self._check(self.lib.vbgs_timing_phases(self.ctx, mask))
 
     def timing_read(self):
         ms = (ctypes.c_double * _lib.NPHASE)()

@@ -512,3 +512,31 @@ def test_plain_tier_error_white_noise_vs_scene(dev, prec):
     # measured: white noise understates the scene error (about 4x for both tiers), so a tolerance met
     # on white noise does not carry over to scenes; white noise never shows the larger error here
     assert 0.0 < errs["white"] <= errs["scene"]
+
+
+@gpu
+def test_phase_timing_mask(dev):
+    """vbgs_timing records every phase; vbgs_timing_phases only the chosen ones (the rest count 0)."""
+    import paper_2603_08499_amd as P
+    X, pr = scenes.random_problem(3000, 200, 6, seed=5)
+    Xg = torch.from_numpy(X).to(dev)
+    m = _model(dev, pr, X.shape[0], "bf16x3", True, cull=1)
+    m.timing(True)
+    m.estep_stats(Xg)
+    m.update()
+    every = m.timing_read()
+    m.timing(True, phases=["pass1"])
+    m.estep_stats(Xg)
+    m.update()
+    only = m.timing_read()
+    m.timing(False)
+    m.estep_stats(Xg)
+    off = m.timing_read()
+    print("phase counts: all", {k: v[1] for k, v in every.items()}, "pass1 only", {k: v[1] for k, v in only.items()})
+    assert every["pass1"][1] == 1 and every["update"][1] == 1 and every["prep"][1] == 1
+    assert only["pass1"][1] == 1 and only["pass1"][0] > 0.0
+    assert all(v[1] == 0 for k, v in only.items() if k != "pass1")
+    assert all(v[1] == 0 for v in off.values())
+    with pytest.raises(P.VBGSError):
+        m._check(m.lib.vbgs_timing_phases(m.ctx, 1 << 10))
+    m.close()
