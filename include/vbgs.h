@@ -273,12 +273,15 @@ vbgs_status vbgs_clear_flags(vbgs_ctx* ctx, void* stream);
  * not the culled path. */
 vbgs_status vbgs_counters(vbgs_ctx* ctx, int64_t out[11], void* stream);
 
-/* Per-phase timing with HIP events recorded on the stream of each call.
- * Phases: 0 frame moments + features, 1 expectations + coefficient rows (with culling also the
- * spatial sort of the components and the tile bounds), 2 the first pass over all pairs (in
- * exact MFMA mode the screening sweep kernel alone), 3 pass 2 (statistics), 4 fold, 5 update,
- * 6 ELBO reduction, 7 proposal network (forward, logits, top-C, audit), 8 spatial sort of the
- * points and clearing of the transpose counters, 9 exact per-point LSE from the candidates.
+/* Per-phase timing with HIP events recorded on the stream that runs each phase.
+ * Phases: 0 frame moments + features, 1 expectations + coefficient rows, 2 the first pass over
+ * all pairs (in exact MFMA mode the screening sweep kernel alone), 3 pass 2 (statistics), 4 fold,
+ * 5 update, 6 ELBO reduction, 7 proposal network (forward, logits, top-C, audit), 8 clearing of
+ * the transpose counters, 9 exact per-point LSE from the candidates. With culling (exact MFMA
+ * mode): 0 the frame moments only, 1 the spatial sort of the components and the gather of their
+ * rows with the row and tile bounds (on one of the context's streams), 8 the spatial sort of the
+ * points and the sweep's dispatch order; the coefficient rows, the features and the KL terms run
+ * on the context's other stream, untimed.
  * vbgs_timing(ctx, 1) creates the events (host-side objects, no device memory) and records
  * every later phase; 0 stops recording. vbgs_timing_read synchronises `stream`, writes the
  * summed duration in ms and the number of recorded launches of each phase, and clears them. */
