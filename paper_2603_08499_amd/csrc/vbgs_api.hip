@@ -46,7 +46,8 @@ struct vbgs_ctx {
   // the point preparation, and the KL terms of the ELBO, which overlap both (not the sweep: their
   // waves hold most of a SIMD's registers and would keep the sweep's first blocks waiting)
   hipStream_t side = nullptr, side2 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, kl_done = nullptr, rows_done = nullptr, feat_done = nullptr;
+  hipEvent_t begin = nullptr, fork = nullptr, join = nullptr, kl_done = nullptr, rows_done = nullptr,
+             feat_done = nullptr;
   int nsplit;
   float T2;
   void* scratch = nullptr;  // device address of this device's static scratch (vbgs_estep_stats_scratch)
@@ -429,7 +430,9 @@ static hipError_t make_side(vbgs_ctx* c) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->kl_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->rows_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->feat_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->begin, hipEventDisableTiming);
   if (e != hipSuccess) {
+    if (c->begin) hipEventDestroy(c->begin);
     if (c->feat_done) hipEventDestroy(c->feat_done);
     if (c->rows_done) hipEventDestroy(c->rows_done);
     if (c->kl_done) hipEventDestroy(c->kl_done);
@@ -438,7 +441,7 @@ static hipError_t make_side(vbgs_ctx* c) {
     if (c->side2) hipStreamDestroy(c->side2);
     if (c->side) hipStreamDestroy(c->side);
     c->side = c->side2 = nullptr;
-    c->fork = c->join = c->kl_done = c->rows_done = c->feat_done = nullptr;
+    c->begin = c->fork = c->join = c->kl_done = c->rows_done = c->feat_done = nullptr;
   }
   return e;
 }
@@ -647,6 +650,11 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     // order (the caller's stream, which waits for the gather and the features before the sweep,
     // and for the KL terms after pass 1)
     e = c->side ? hipSuccess : hipErrorInvalidResourceHandle;  // made with the context
+    // (the segments and the cleared counters need nothing of this frame: beside the moments)
+    if (e == hipSuccess) e = hipEventRecord(c->begin, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side2, c->begin, 0);
+    if (e == hipSuccess) e = launch_seg_layout(d, c->side2);
+    if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, c->side2, 0);
     if (e == hipSuccess) {
       Phase ph(c, 0, s);
       e = launch_frame_prep(d, X, N, s, 0);
@@ -654,8 +662,6 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
     if (e == hipSuccess) e = hipEventRecord(c->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->fork, 0);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side2, c->fork, 0);
-    if (e == hipSuccess) e = launch_seg_layout(d, c->side2);
-    if (e == hipSuccess) e = launch_pass1(d, cfg, X, N, lse_out, c->side2, 0);
     if (e == hipSuccess) e = launch_coeffs(d, c->side2, true, true);
     if (e == hipSuccess) e = hipEventRecord(c->rows_done, c->side2);
     if (e == hipSuccess) e = launch_frame_prep(d, X, N, c->side2, 1);
@@ -1209,6 +1215,7 @@ void vbgs_destroy(vbgs_ctx* c) {
     hipEventDestroy(c->fork);
     hipEventDestroy(c->join);
     hipEventDestroy(c->kl_done);
+    hipEventDestroy(c->begin);
     hipEventDestroy(c->rows_done);
     hipEventDestroy(c->feat_done);
     hipStreamDestroy(c->side2);
