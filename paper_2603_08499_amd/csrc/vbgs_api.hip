@@ -642,13 +642,13 @@ static vbgs_status run_pass1(vbgs_ctx* c, const float* X, int64_t N, double* lse
   const hipStream_t s = S(stream);
   hipError_t e;
   if (cull) {
-    // the frame moments first (the components are centred and Hilbert-coded with them), then three
-    // streams: the component sort, then the gather of the rows into its order with the tile
-    // bounds (side); the kept pairs' segments sized from the last sweep's counts, the sweep's
-    // cleared counters, the alpha sum, the coefficient rows in component order, the point
-    // features, and the KL terms (ELBO only) (side2); the point sort and the blocks' dispatch
-    // order (the caller's stream, which waits for the gather and the features before the sweep,
-    // and for the KL terms after pass 1)
+    // the frame moments first (the components are centred and Hilbert-coded with them; beside them
+    // on side2, the kept pairs' segments sized from the last sweep's counts and the sweep's
+    // cleared counters), then three streams: the component sort, then the gather of the rows into
+    // its order with the tile bounds (side); the alpha sum, the coefficient rows in component
+    // order, the point features, and the KL terms (ELBO only) (side2); the point sort and the
+    // blocks' dispatch order (the caller's stream, which waits for the gather and the features
+    // before the sweep, and for the KL terms after pass 1)
     e = c->side ? hipSuccess : hipErrorInvalidResourceHandle;  // made with the context
     // (the segments and the cleared counters need nothing of this frame: beside the moments)
     if (e == hipSuccess) e = hipEventRecord(c->begin, s);
